@@ -1,0 +1,138 @@
+"""Pins for the oracle's gradient term, integrators and energy.
+
+* eq 10 (section 4.1): the relaxed 1-D 180-degree wall of the 2-4 model with
+  the paper's parameters converges to the tanh profile at second order in h.
+* the sixth-order BaTiO3 wall (closed form derived from the first integral
+  G P'^2/2 = f(P) - f(Ps)) converges the same way.
+* an exact discrete eigenmode of the linear problem decays by exactly the
+  Euler / Heun amplification factor (pins the Laplacian with periodic and
+  open boundaries, and both integrators).
+* Euler is first order, Heun second order in dtau on the nonlinear problem.
+"""
+import copy
+import json
+import os
+
+import numpy as np
+import pytest
+
+import tdgl_inputs as I
+from oracle import tdgl_oracle as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _chain_cfg(material, gradient, scales, nx, h, T):
+    return dict(n=(nx, 1, 1), d=(h, 1e-9, 1e-9), periodic=(0, 0, 0), mimg=0,
+                materials=[material], layers=[0], gradient=gradient, scales=scales,
+                T=T, eext=(0, 0, 0), terms=O.LANDAU | O.GRAD)
+
+
+def _relax_wall(cfg, start, tau, dtau):
+    """Relax a 1-D chain from start(x) (x in metres, wall centred between
+    the two middle cells, so symmetry pins its position)."""
+    prob = O.Problem(cfg)
+    nx = cfg["n"][0]
+    x = (np.arange(nx) + 0.5 - nx / 2) * prob.h[0] * prob.l0
+    P = np.zeros((3, 1, 1, nx))
+    P[2, 0, 0] = start(x)
+    for _ in range(int(round(tau / dtau))):
+        P = O.step_heun(P, prob, dtau)
+    return x, P[2, 0, 0]
+
+
+def test_tanh_wall_eq10_second_order():
+    g = json.load(open(os.path.join(GOLD, "wall_180_params.json")))
+    a1, a11, G = g["alpha1"], g["alpha11"], g["G44"] + g["G44p"]
+    mat = dict(I.BATIO3)
+    mat.update(a1_form=0, a1_slope=1.0, a1_T0=-a1, a11_slope=0.0, a11_offset=a11,
+               a12=0.0, a111_slope=0.0, a111_offset=0.0, a112=0.0, a123=0.0)
+    grad = dict(G11=0.0, G12=0.0, G44=g["G44"], G44p=g["G44p"])
+    scales = dict(P0=1.0, alpha_ref=abs(a1), G110=G, eps_b=1.0)
+    xi = np.sqrt(G / abs(a1))
+    Ps = np.sqrt(abs(a1) / (2 * a11))
+    errs = []
+    for k in (4, 8, 16):
+        h = xi / k
+        exact_fn = lambda x: Ps * np.tanh(x / xi)
+        x, Pz = _relax_wall(_chain_cfg(mat, grad, scales, 20 * k, h, 0.0), exact_fn,
+                            tau=10.0, dtau=0.25 / k**2)
+        exact = exact_fn(x)
+        errs.append(np.abs(Pz - exact).max() / Ps)
+    assert errs[-1] < 2e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def test_sixth_order_bto_wall_second_order():
+    T = 300.0
+    a1 = 3.34e5 * (T - 381.0)
+    a11 = 4.69e6 * (T - 393.0) - 2.02e8
+    a111 = -5.52e7 * (T - 393.0) + 2.76e9
+    G = 5.1e-10
+    Ps = np.sqrt((-a11 + np.sqrt(a11 * a11 - 3 * a1 * a111)) / (3 * a111))
+    c = a11 / a111 + 2 * Ps**2
+    xi6 = np.sqrt(G / (2 * a111)) / (Ps * np.sqrt(Ps**2 + c))
+    scales = dict(P0=1.0, alpha_ref=abs(a1), G110=G, eps_b=45.0)
+    l0 = np.sqrt(G / abs(a1))
+    errs = []
+    for hs in (0.2, 0.1, 0.05):
+        nx = int(round(12 * xi6 / (hs * l0) / 2)) * 2
+        def exact_fn(x):
+            u = x / xi6
+            return Ps * np.sqrt(c) * np.tanh(u) / np.sqrt(c + Ps**2 / np.cosh(u)**2)
+        x, Pz = _relax_wall(_chain_cfg(copy.deepcopy(I.BATIO3), I.isotropic_gradient(G),
+                                       scales, nx, hs * l0, T), exact_fn,
+                            tau=10.0, dtau=0.2 * hs**2)
+        exact = exact_fn(x)
+        errs.append(np.abs(Pz - exact).max() / Ps)
+    assert errs[-1] < 1e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def _linear_cfg(n, periodic):
+    mat = dict(I.BATIO3)
+    mat.update(a1_form=0, a1_slope=2.7054e7, a1_T0=0.0, a11_slope=0.0, a11_offset=0.0,
+               a12=0.0, a111_slope=0.0, a111_offset=0.0, a112=0.0, a123=0.0)
+    return dict(n=n, d=(1.0e-9, 1.3e-9, 0.8e-9), periodic=periodic, mimg=0,
+                materials=[mat], layers=[0] * n[2], gradient=I.isotropic_gradient(5.1e-10),
+                scales=dict(P0=1.0, alpha_ref=2.7054e7, G110=5.1e-10, eps_b=45.0),
+                T=1.0, eext=(0, 0, 0), terms=O.LANDAU | O.GRAD)
+
+
+@pytest.mark.parametrize("scheme", ["euler", "heun"])
+def test_exact_discrete_mode(scheme):
+    n = (8, 6, 5)
+    prob = O.Problem(_linear_cfg(n, (1, 0, 0)))
+    kx, ky, kz = 3, 2, 1
+    nx, ny, nz = n
+    xi = np.arange(nx)
+    yj = np.arange(ny)
+    zk = np.arange(nz)
+    mode = (np.cos(np.pi * kz * (zk + 0.5) / nz)[:, None, None]
+            * np.cos(np.pi * ky * (yj + 0.5) / ny)[None, :, None]
+            * np.cos(2 * np.pi * kx * xi / nx)[None, None, :])
+    A = np.array([0.3, -0.2, 0.1])
+    P0 = A[:, None, None, None] * mode[None]
+    lam = 2 * prob.coef[0, 0] + sum(
+        4 * np.sin(th / 2) ** 2 / prob.h[d] ** 2
+        for d, th in ((0, 2 * np.pi * kx / nx), (1, np.pi * ky / ny), (2, np.pi * kz / nz)))
+    dtau, steps = 2e-3, 50
+    z = -dtau * lam
+    amp = (1 + z) if scheme == "euler" else (1 + z + z * z / 2)
+    P = O.run(P0, prob, scheme, dtau, steps)
+    assert np.allclose(P, P0 * amp**steps, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme,order", [("euler", 1), ("heun", 2)])
+def test_integrator_order(scheme, order):
+    cfg = I.config("c1")
+    cfg.update(n=(4, 4, 2), layers=[0, 0])
+    prob = O.Problem(cfg)
+    P0 = I.initial_P(cfg, 5)
+    tau = 0.2
+    ref = O.run(P0, prob, "heun", tau / 1600, 1600)
+    errs = []
+    for m in (50, 100):
+        errs.append(np.abs(O.run(P0, prob, scheme, tau / m, m) - ref).max())
+    rate = np.log2(errs[0] / errs[1])
+    assert abs(rate - order) < 0.15, (errs, rate)
