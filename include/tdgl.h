@@ -1,0 +1,220 @@
+/*
+ * tdgl.h — C ABI of libtdgl: one time-dependent Ginzburg-Landau (TDGL) time
+ * step of the full three-component polarisation P on a 3-D finite-difference
+ * grid, on an AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper section 2): dP/dt = -L dF/dP (eq 1) with
+ * F = F_Land + F_Grad + F_Elec + F_Ext (eq 2): sixth-order Landau energy
+ * (eq 3), gradient energy (eq 4), electrostatic energy of the bound charges
+ * (eqs 5-6, finite sample in vacuum, P = 0 outside), applied-field energy
+ * (eq 7).  Section 3: P uniform in each cell, per-cell materials, time-
+ * dependent excitation, several explicit integrators, per-term on/off flags,
+ * Table 2 normalisation.  The electrostatic field is a zero-padded FFT
+ * convolution with the cell-averaged dipolar tensor.
+ *
+ * Conventions shared by all entry points
+ *  - Units at the boundary are SI: P in C/m^2, fields in V/m, T in K,
+ *    lengths in m, energies in J.  Internally the library works in the
+ *    reduced units of Table 2 with a fixed reference stiffness alpha_ref
+ *    (tdgl_set_scales); the time step dtau is given in reduced time
+ *    tau = alpha_ref * L * t with L = 1.
+ *  - Arrays of P and of fields are structure-of-arrays [3][nz][ny][nx]
+ *    (component slowest, x fastest), row-major, densely packed.
+ *  - Every call returns a tdgl_status; nothing is thrown across the ABI.
+ *    On an argument error the context is left unchanged.  The message of
+ *    the last failure is available from tdgl_last_error.
+ *  - Device work is enqueued on the HIP stream given to tdgl_create, in
+ *    call order.  Calls documented as "synchronising" wait for that stream.
+ *  - A context is not thread-safe.  Separate contexts are independent.
+ *  - Pointers passed in are borrowed for the duration of the call only,
+ *    except a workspace bound with tdgl_bind_workspace.
+ */
+#ifndef TDGL_H
+#define TDGL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDGL_ABI_VERSION 1
+
+typedef struct tdgl_ctx tdgl_ctx;
+
+typedef enum {
+    TDGL_OK = 0,
+    TDGL_E_ARG = -1,          /* invalid argument; context unchanged          */
+    TDGL_E_NOMEM = -2,        /* device allocation failed                     */
+    TDGL_E_HIP = -3,          /* HIP runtime error (no device, launch failure)*/
+    TDGL_E_NONFINITE = -4,    /* a non-finite P appeared during tdgl_step     */
+    TDGL_E_STATE = -5,        /* call out of order (e.g. step before set_P)   */
+    TDGL_E_UNSUPPORTED = -6   /* valid input this build does not handle       */
+} tdgl_status;
+
+enum { TDGL_FP32 = 0, TDGL_FP64 = 1 };            /* arithmetic of the step     */
+enum { TDGL_EULER = 0, TDGL_HEUN = 1 };           /* integrators                */
+/* energy terms (section 3: each contribution can be switched on or off) */
+enum { TDGL_LANDAU = 1, TDGL_GRAD = 2, TDGL_ELEC = 4, TDGL_EXT = 8, TDGL_ALL = 15 };
+
+/* Grid (section 3, finite differences with P uniform per cell).
+ * periodic_mask: bit0 x, bit1 y, bit2 z.  Supported: 0 (open box in vacuum,
+ * the paper's setting), 3 (film periodic in x and y, open in z) and 7
+ * (fully periodic).  Open dimensions are zero-padded to the smallest power
+ * of two >= max(8, 2n-1); a periodic dimension needs n a power of two in
+ * [8, 1024].  Padded lengths must not exceed 1024. */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;            /* cell edge lengths, m                      */
+    unsigned periodic_mask;
+} tdgl_grid;
+
+/* Landau coefficients of one material (eq 3), forms of Table 1:
+ *   a1_form 0: alpha1(T) = a1_slope * (T - a1_T0)
+ *   a1_form 1: alpha1(T) = a1_A * (coth(a1_Ts/T) - coth(a1_Ts/a1_T0))
+ *   alpha11(T)  = a11_slope  * (T - a11_Tref)  + a11_offset
+ *   alpha111(T) = a111_slope * (T - a111_Tref) + a111_offset
+ *   alpha12, alpha112, alpha123 constant.
+ * rs scales the z part of the quadratic term (strain parameter of the
+ * skyrmion study, section 4.4): alpha1 (Px^2 + Py^2) + rs alpha1 Pz^2.
+ * SI units as in Table 1. */
+typedef struct {
+    int a1_form;
+    double a1_slope, a1_T0, a1_A, a1_Ts;
+    double a11_slope, a11_Tref, a11_offset;
+    double a12;
+    double a111_slope, a111_Tref, a111_offset;
+    double a112, a123;
+    double rs;
+} tdgl_material;
+
+#define TDGL_MAX_MATERIALS 16
+
+/* ABI version of the loaded library (TDGL_ABI_VERSION at build time). */
+int tdgl_abi_version(void);
+
+/* Create a context for one simulation.  precision: TDGL_FP32 or TDGL_FP64
+ * (arithmetic of the step; tensor construction and energy sums are always
+ * FP64).  hip_stream: a hipStream_t (NULL = default stream).  No device
+ * memory is touched until the first call that needs it.
+ * Errors: TDGL_E_ARG (bad sizes or mask), TDGL_E_UNSUPPORTED (FFT length). */
+tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream,
+                        tdgl_ctx **out);
+
+/* Release the context and all device memory it allocated.  NULL is a no-op. */
+void tdgl_destroy(tdgl_ctx *ctx);
+
+/* Message of the last failed call on ctx (empty if none).  Owned by ctx. */
+const char *tdgl_last_error(const tdgl_ctx *ctx);
+
+/* dims out[7]: nx, ny, nz, padded mx, my, mz, hx = mx/2+1. */
+tdgl_status tdgl_get_dims(const tdgl_ctx *ctx, int out[7]);
+
+/* Bytes of device workspace the context needs for its state, spectra and
+ * tensor (tensor construction temporaries excluded). */
+tdgl_status tdgl_workspace_size(const tdgl_ctx *ctx, size_t *bytes);
+
+/* Hand the context caller-owned device memory (e.g. a torch tensor) of at
+ * least tdgl_workspace_size bytes, 256-byte aligned, instead of letting it
+ * allocate.  Must precede every call that touches the device; the memory
+ * must outlive the context.  Errors: TDGL_E_ARG (size, alignment),
+ * TDGL_E_STATE (device memory already allocated). */
+tdgl_status tdgl_bind_workspace(tdgl_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Normalisation of Table 2: P0 (C/m^2), alpha_ref (N m^2 C^-2, > 0, used in
+ * place of |alpha1(T)| so reduced time is the same at every temperature),
+ * G110 (N m^4 C^-2), eps_b (background permittivity, section 2). */
+tdgl_status tdgl_set_scales(tdgl_ctx *ctx, double P0, double alpha_ref, double G110,
+                            double eps_b);
+
+/* Define material id (0 <= id < TDGL_MAX_MATERIALS). */
+tdgl_status tdgl_set_material(tdgl_ctx *ctx, int id, const tdgl_material *mat);
+
+/* Material of every z layer (section 3: spatially varying parameters),
+ * ids[nz]; -1 marks a vacuum layer, where P is held at zero. */
+tdgl_status tdgl_set_layer_materials(tdgl_ctx *ctx, const signed char *ids);
+
+/* Gradient coefficients of eq 4 (N m^4 C^-2).  This build handles the
+ * diagonal part exactly: d/dP_i gives G11 d_ii P_i + (G44 + G44') d_jj P_i;
+ * a non-zero mixed coefficient G12 + G44 - G44' returns TDGL_E_UNSUPPORTED. */
+tdgl_status tdgl_set_gradient(tdgl_ctx *ctx, double G11, double G12, double G44,
+                              double G44p);
+
+/* Build the electrostatic interaction tensor on the device in FP64 (eq 6 for
+ * cell-wise uniform P: cell-averaged dipolar tensor, closed form for touching
+ * cells and Gauss-Legendre quadrature elsewhere; periodic dimensions sum
+ * lattice images |offset| <= (mimg + 1/2) * n and fix the in-plane k = 0
+ * mode to its infinite-lattice value), transform it and keep one octant of
+ * the real spectrum with -kappa/(mx my mz) folded in.  Needs set_scales.
+ * Synchronising.  Temporaries of about 24 * mx*my*mz bytes are allocated for
+ * the duration of the call.  mimg in [0, 64]. */
+tdgl_status tdgl_build_tensor(tdgl_ctx *ctx, int mimg);
+
+/* Copy the tensor octant spectrum ([6][mz/2+1][my/2+1][hx], component order
+ * xx yy zz xy xz yz, converted to double) to host memory dst of count
+ * doubles.  Synchronising.  For tests and inspection. */
+tdgl_status tdgl_get_tensor_spectrum(tdgl_ctx *ctx, double *dst, size_t count);
+
+/* Temperature (K) for the Table 1 coefficient forms. */
+tdgl_status tdgl_set_temperature(tdgl_ctx *ctx, double T_kelvin);
+
+/* Uniform applied field E_ext (V/m), eq 7.  May change between tdgl_step
+ * calls (time-dependent excitation, section 3). */
+tdgl_status tdgl_set_eext(tdgl_ctx *ctx, double ex, double ey, double ez);
+
+/* Energy terms in the effective field (TDGL_* bits). */
+tdgl_status tdgl_set_terms(tdgl_ctx *ctx, unsigned mask);
+
+/* Integrator (TDGL_EULER or TDGL_HEUN) and reduced time step dtau > 0. */
+tdgl_status tdgl_set_integrator(tdgl_ctx *ctx, int scheme, double dtau);
+
+/* Number of steps captured per HIP graph by tdgl_step (default 64; 0 runs
+ * plain stream launches). */
+tdgl_status tdgl_set_graph_chunk(tdgl_ctx *ctx, int steps);
+
+/* Load P (C/m^2, [3][nz][ny][nx]) from src: host memory if src_on_device is
+ * 0, device memory otherwise; src_precision TDGL_FP32 or TDGL_FP64 (converted
+ * to the context precision).  Vacuum layers are set to zero and the
+ * non-finite flag is cleared.  Needs the model to be complete (scales,
+ * every material named by the layer map, gradient coefficients when the
+ * gradient term is on).  Host sources are copied before return. */
+tdgl_status tdgl_set_P(tdgl_ctx *ctx, const void *src, int src_on_device, int src_precision);
+
+/* Store the current P to dst (host or device, FP32 or FP64).  Host
+ * destinations are synchronising and report TDGL_E_NONFINITE like
+ * tdgl_sync (the data is copied either way). */
+tdgl_status tdgl_get_P(tdgl_ctx *ctx, void *dst, int dst_on_device, int dst_precision);
+
+/* Advance nsteps time steps (one Euler step = 1 field evaluation, one Heun
+ * step = 2).  Asynchronous: a non-finite P produced by a step is recorded on
+ * the device and reported as TDGL_E_NONFINITE by the next tdgl_sync,
+ * tdgl_energies or host tdgl_get_P; P then holds the bad state (restore a
+ * copy taken with tdgl_get_P and retry with a smaller dtau).  Needs set_P,
+ * and build_tensor when the electrostatic term is on. */
+tdgl_status tdgl_step(tdgl_ctx *ctx, long long nsteps);
+
+/* Effective field E_eff (V/m) of the current P with the terms in mask (a
+ * subset of TDGL_ALL), written to device memory dst_dev ([3][nz][ny][nx],
+ * context precision).  Vacuum cells get 0. */
+tdgl_status tdgl_eval_field(tdgl_ctx *ctx, unsigned mask, void *dst_dev);
+
+/* Energies of the current P with the context's term mask, in J:
+ * F[0] Landau, F[1] gradient, F[2] electrostatic, F[3] external, F[4] total;
+ * meanP[3]: mean P over material cells (C/m^2).  FP64 accumulation.
+ * Synchronising. */
+tdgl_status tdgl_energies(tdgl_ctx *ctx, double F[5], double meanP[3]);
+
+/* Reduced per-layer Landau coefficients ([nz][8]: a1x a1y a1z a11 a12 a111
+ * a112 a123, zero for vacuum) and scalars out[8]: kappa, hx*, hy*, hz*,
+ * dV*, energy scale (J), field scale (V/m), l0 (m).  Host-side; for tests. */
+tdgl_status tdgl_get_reduced(const tdgl_ctx *ctx, double *coef, double scal[8]);
+
+/* Wait for all work of the context; returns TDGL_E_NONFINITE if a step
+ * produced a non-finite P. */
+tdgl_status tdgl_sync(tdgl_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDGL_H */

@@ -1,0 +1,198 @@
+// Radix-8/4/2 Stockham FFT of one line per group of threads, for gfx950.
+//
+// A line of length M (power of two, 8..1024) is owned by M/8 threads.  Thread
+// t of the line holds the eight elements x[t + q*M/8], q = 0..7, in registers
+// on entry and the eight outputs X[t + q*M/8] (natural order) on exit.  Only
+// the exchanges between radix stages go through LDS, so a pass kernel can
+// load its inputs from and store its outputs to global memory directly, with
+// consecutive threads touching consecutive addresses.
+//
+// Stage with radix R after stages of total length P (Stockham autosort):
+// butterfly i in [0, M/R), k = i mod P, inputs x[i + r M/R] twiddled by
+// W_{PR}^{rk}, R-point DFT, outputs to y[(i-k) R + k + r P].  The first stage
+// (P = 1) needs no twiddles and reads the registers; the last stage
+// (P R = M) writes y[i + r M/R], which is again the register layout.
+//
+// Forward transforms use W = exp(-2 pi i/M); inverse transforms the
+// conjugate, unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tdgl {
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b)
+{
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> rot90(cpx<T> a)
+{
+    return INV ? cpx<T>{-a.y, a.x} : cpx<T>{a.y, -a.x};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cpx<T> *v)
+{
+    cpx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cpx<T> *v)
+{
+    cpx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    cpx<T> t2 = cadd(v[1], v[3]), t3 = rot90<T, INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+// 8-point DFT as radix-2 (n, n+4) pairs, W_8^n twiddles, two 4-point DFTs.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cpx<T> *v)
+{
+    const T s = T(0.70710678118654752440084436210485);
+    cpx<T> a[4], b[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        a[n] = cadd(v[n], v[n + 4]);
+        b[n] = csub(v[n], v[n + 4]);
+    }
+    {
+        cpx<T> u = b[1];
+        b[1] = INV ? cpx<T>{s * (u.x - u.y), s * (u.x + u.y)}
+                   : cpx<T>{s * (u.x + u.y), s * (u.y - u.x)};
+        b[2] = rot90<T, INV>(b[2]);
+        u = b[3];
+        b[3] = INV ? cpx<T>{-s * (u.x + u.y), s * (u.x - u.y)}
+                   : cpx<T>{s * (u.y - u.x), -s * (u.x + u.y)};
+    }
+    dft4<T, INV>(a);
+    dft4<T, INV>(b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = a[k];
+        v[2 * k + 1] = b[k];
+    }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cpx<T> *v)
+{
+    if constexpr (R == 8) dft8<T, INV>(v);
+    else if constexpr (R == 4) dft4<T, INV>(v);
+    else dft2<T, INV>(v);
+}
+
+// LDS index policies for one line's scratch.
+struct IdxStride {      // element e of the line at e * s (lines interleaved)
+    int s;
+    __device__ __forceinline__ int operator()(int e) const { return e * s; }
+};
+struct IdxPad {         // contiguous line, one pad slot after every 8 elements
+    __device__ __forceinline__ int operator()(int e) const { return e + (e >> 3); }
+};
+
+template <int M>
+struct LinePad {
+    static constexpr int len = M + M / 8;   // LDS elements per line with IdxPad
+};
+
+// Remaining stages after the first.  Every thread of the work-group must
+// reach these barriers; threads with act == false only skip memory traffic.
+template <typename T, int M, int P, bool INV, class Idx>
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
+                                           const cpx<T> *__restrict__ tw, bool act)
+{
+    constexpr int R = (M / P >= 8) ? 8 : (M / P);
+    constexpr int NB = 8 / R;          // butterflies per thread
+    constexpr int TPL = M / 8;         // threads per line
+    constexpr int MR = M / R;
+    constexpr bool LAST = (P * R == M);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = t + b * TPL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b * R + r] = lds[idx(i + r * MR)];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = t + b * TPL;
+            const int k = i & (P - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cpx<T> w = tw[r * k * (M / (P * R))];
+                v[b * R + r] = INV ? cmulc(v[b * R + r], w) : cmul(v[b * R + r], w);
+            }
+            dftR<T, R, INV>(v + b * R);
+        }
+    }
+    if constexpr (LAST) {
+        if constexpr (NB > 1) {
+            cpx<T> tmp[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) tmp[q] = v[q];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b + r * NB] = tmp[b * R + r];
+        }
+    } else {
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = t + b * TPL;
+                const int k = i & (P - 1);
+                const int j = (i - k) * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[idx(j + r * P)] = v[b * R + r];
+            }
+        }
+        fft_stages<T, M, P * R, INV, Idx>(v, lds, idx, t, tw, act);
+    }
+}
+
+// Full line transform.  The caller must make sure no thread still reads the
+// line's LDS region from an earlier use (barrier) before calling, and must
+// barrier again before reusing it afterwards.
+template <typename T, int M, bool INV, class Idx>
+__device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
+                                         const cpx<T> *__restrict__ tw, bool act)
+{
+    static_assert(M >= 8 && M <= 1024 && (M & (M - 1)) == 0, "length");
+    if (act) dft8<T, INV>(v);
+    if constexpr (M > 8) {
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) lds[idx(8 * t + r)] = v[r];
+        }
+        fft_stages<T, M, 8, INV, Idx>(v, lds, idx, t, tw, act);
+    }
+}
+
+}  // namespace tdgl

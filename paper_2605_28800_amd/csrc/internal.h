@@ -1,0 +1,80 @@
+// Declarations shared by the host API (tdgl_api.cpp) and the HIP kernel
+// translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace tdgl {
+
+constexpr int NCOEF = 12;      // per z layer: a1x a1y a1z a11 a12 a111 a112 a123, material, pad
+constexpr int MAXLEN = 1024;   // largest FFT length
+constexpr int GL_MAXN = 24;    // Gauss-Legendre table rows/columns
+
+enum { PREC_F32 = 0, PREC_F64 = 1 };
+enum { T_LANDAU = 1, T_GRAD = 2, T_ELEC = 4, T_EXT = 8 };
+
+// Device-resident scalars read by the update kernel (can change between
+// graph launches without re-capturing).
+template <typename T>
+struct KParams {
+    T dtau;          // reduced time step
+    T eext[3];       // reduced applied field
+    T gh2[3][3];     // g[i][d] / h_d^2: gradient coefficient of component i along d
+    T out_scale;     // V/m per reduced field unit (field output)
+    T pad[2];
+};
+
+struct Geom {
+    int nx, ny, nz;      // physical cells
+    int mx, my, mz;      // padded FFT lengths
+    int hx;              // mx/2 + 1
+    int px, py, pz;      // periodic flags
+};
+
+// Update kernel modes.
+enum { UPD_STEP = 0, UPD_FIELD = 1, UPD_ENERGY = 2 };
+
+struct UpdArgs {
+    const void *P_in;      // state the field is evaluated at
+    const void *P_old;     // Heun corrector: state at the start of the step
+    void *P_out;           // new state (STEP) or field (FIELD)
+    void *S1;              // x-spectra rows [3][nz][ny][hx]: field in, new P spectrum out
+    const void *coef;      // [nz][NCOEF]
+    const void *kp;        // KParams<T>
+    double *partials;      // ENERGY: [grid][8]
+    int *flag;             // non-finite flag
+    int stage;             // STEP: 0 = P_in + dtau E, 1 = (P_old + P_in)/2 + dtau/2 E
+    unsigned terms;        // term mask for this evaluation
+    int elec_in;           // read the electrostatic field rows from S1
+    int fx_out;            // write the x-spectrum of P_out to S1
+    int yt;                // rows per work-group (even)
+};
+
+hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
+                     long long in_stride, void *out, long long out_stride,
+                     const void *tw, hipStream_t s);
+hipError_t launch_col(int prec, int M, bool inv, const void *in, void *out, long long C,
+                      long long nbatch, long long in_bstride, long long out_bstride,
+                      long long lstride, int n_in, int n_out, const void *tw, hipStream_t s);
+hipError_t launch_zmul(int prec, const Geom &g, void *S, const void *Nt, const void *tw,
+                       hipStream_t s);
+hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a,
+                         const void *tw, hipStream_t s, int *nblocks_out);
+int update_rows_per_block(int prec, const Geom &g);
+hipError_t launch_reduce_partials(const double *partials, int n, double *out, hipStream_t s);
+hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst, size_t n,
+                          double scale, hipStream_t s);
+hipError_t launch_zero_layers(int prec, void *P, const void *coef, const Geom &g, hipStream_t s);
+
+// tensor construction (FP64)
+hipError_t launch_tensor_real(const Geom &g, unsigned pmask, int mimg, double dx, double dy,
+                              double dz, const double *gl_t, const double *gl_w, double *R,
+                              hipStream_t s);
+hipError_t launch_tensor_k0(const Geom &g, unsigned pmask, double *R, double *sums,
+                            hipStream_t s);
+hipError_t launch_tensor_octant(int prec, const Geom &g, const void *C, double scale, void *Nt,
+                                hipStream_t s);
+
+}  // namespace tdgl

@@ -1,0 +1,876 @@
+// Host side of the libtdgl C ABI (include/tdgl.h).
+//
+// Holds the context (grid, FFT plan, materials, scales, state buffers),
+// turns the SI inputs of the paper's Tables 1-2 into the reduced
+// coefficients the kernels use, and enqueues one TDGL step as
+//     Fy -> Fz*N*Iz -> Iy -> (Ix + local terms + update + Fx)
+// per field evaluation (one for Euler, two for Heun), captured into HIP
+// graphs of several steps.
+#include "../../include/tdgl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace tdgl;
+
+namespace {
+
+constexpr double EPS0 = 8.8541878128e-12;   // F/m (CODATA 2018)
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int cur = 0, scheme = 0, chunk = 0;
+    unsigned elec = 0;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct tdgl_ctx {
+    Geom g{};
+    double d[3]{};
+    unsigned pmask = 0;
+    int prec = 0;
+    size_t esz = 4;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    // host-side model state
+    bool scales_set = false;
+    double P0 = 1.0, alpha_ref = 0.0, G110 = 0.0, eps_b = 1.0;
+    tdgl_material mats[TDGL_MAX_MATERIALS]{};
+    bool mat_set[TDGL_MAX_MATERIALS]{};
+    std::vector<signed char> layer;
+    bool grad_set = false;
+    double G11 = 0, G12 = 0, G44 = 0, G44p = 0;
+    double T = 300.0;
+    double eext[3] = {0, 0, 0};
+    unsigned terms = TDGL_ALL;
+    int scheme = TDGL_HEUN;
+    double dtau = 1e-3;
+    int graph_chunk = 64;
+    // device
+    bool dev_init = false;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    void *P[2]{};
+    void *S1 = nullptr, *S2 = nullptr, *Nt = nullptr, *coef = nullptr, *kp = nullptr;
+    void *twf = nullptr, *twd = nullptr;
+    double *gl = nullptr, *partials = nullptr, *res = nullptr;
+    int *flag = nullptr;
+    int cur = 0;
+    int yt = 2;
+    int nblocks = 1;
+    bool P_set = false, tensor_built = false, spec_valid = false, params_dirty = true;
+    int mimg = -1;
+    std::vector<GraphEntry> graphs;
+    std::string err;
+};
+
+namespace {
+
+tdgl_status fail(tdgl_ctx *c, tdgl_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIP_TRY(c, expr)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((c), TDGL_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+// ---- layout of the device workspace
+struct Layout {
+    size_t P, S1, S2, Nt, coef, kp, twf, twd, gl, partials, flag, res, total;
+};
+
+Layout layout_of(const tdgl_ctx *c)
+{
+    const Geom &g = c->g;
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.P = take(2 * 3 * N * c->esz);
+    L.S1 = take((size_t)3 * g.nz * g.ny * g.hx * 2 * c->esz);
+    L.S2 = take((size_t)3 * g.nz * g.my * g.hx * 2 * c->esz);
+    L.Nt = take((size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * g.hx * c->esz);
+    L.coef = take((size_t)g.nz * NCOEF * c->esz);
+    L.kp = take(sizeof(KParams<double>));
+    L.twf = take((size_t)2 * MAXLEN * 2 * sizeof(float));
+    L.twd = take((size_t)2 * MAXLEN * 2 * sizeof(double));
+    L.gl = take((size_t)2 * GL_MAXN * GL_MAXN * sizeof(double));
+    L.partials = take((size_t)c->nblocks * 8 * sizeof(double));
+    L.flag = take(sizeof(int));
+    L.res = take(8 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+// Gauss-Legendre nodes and weights on [0,1] (Newton on the Legendre
+// recurrence in long double); row n of the tables holds n nodes.
+void gauss_legendre_tables(double *t, double *w)
+{
+    for (int i = 0; i < GL_MAXN * GL_MAXN; ++i) t[i] = w[i] = 0.0;
+    for (int n = 1; n < GL_MAXN; ++n) {
+        for (int i = 0; i < n; ++i) {
+            long double x = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+            long double dp = 1.0L;
+            for (int it = 0; it < 100; ++it) {
+                long double p0 = 1.0L, p1 = x;
+                for (int k = 2; k <= n; ++k) {
+                    long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                if (n == 1) { p0 = 1.0L; p1 = x; }
+                dp = n * (x * p1 - p0) / (x * x - 1.0L);
+                long double dx = p1 / dp;
+                x -= dx;
+                if (fabsl(dx) < 1e-19L) break;
+            }
+            {   // final derivative at the converged root
+                long double p0 = 1.0L, p1 = x;
+                for (int k = 2; k <= n; ++k) {
+                    long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = n * (x * p1 - p0) / (x * x - 1.0L);
+            }
+            const long double wt = 2.0L / ((1.0L - x * x) * dp * dp);
+            t[n * GL_MAXN + i] = (double)(0.5L * (x + 1.0L));
+            w[n * GL_MAXN + i] = (double)(0.5L * wt);
+        }
+    }
+}
+
+// twiddles W_M^k = exp(-2 pi i k / M) for every power-of-two M, table of M at offset M
+template <typename T>
+std::vector<T> twiddle_table()
+{
+    std::vector<T> tw(2 * 2 * MAXLEN, T(0));
+    for (int M = 1; M <= MAXLEN; M <<= 1)
+        for (int k = 0; k < M; ++k) {
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / M;
+            tw[2 * (M + k)] = (T)cosl(a);
+            tw[2 * (M + k) + 1] = (T)sinl(a);
+        }
+    return tw;
+}
+
+tdgl_status ensure_device(tdgl_ctx *c)
+{
+    if (c->dev_init) return TDGL_OK;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(c, TDGL_E_HIP, "no HIP device available");
+    HIP_TRY(c, hipStreamCreate(&c->cap));
+    Layout L = layout_of(c);
+    if (!c->ws) {
+        void *p = nullptr;
+        if (hipMalloc(&p, L.total) != hipSuccess)
+            return fail(c, TDGL_E_NOMEM, "hipMalloc(%zu) failed", L.total);
+        c->ws = p;
+        c->ws_bytes = L.total;
+        c->ws_owned = true;
+    }
+    char *b = static_cast<char *>(c->ws);
+    const size_t N = (size_t)c->g.nx * c->g.ny * c->g.nz;
+    c->P[0] = b + L.P;
+    c->P[1] = b + L.P + 3 * N * c->esz;
+    c->S1 = b + L.S1;
+    c->S2 = b + L.S2;
+    c->Nt = b + L.Nt;
+    c->coef = b + L.coef;
+    c->kp = b + L.kp;
+    c->twf = b + L.twf;
+    c->twd = b + L.twd;
+    c->gl = reinterpret_cast<double *>(b + L.gl);
+    c->partials = reinterpret_cast<double *>(b + L.partials);
+    c->flag = reinterpret_cast<int *>(b + L.flag);
+    c->res = reinterpret_cast<double *>(b + L.res);
+    auto twf = twiddle_table<float>();
+    auto twd = twiddle_table<double>();
+    std::vector<double> gl(2 * GL_MAXN * GL_MAXN);
+    gauss_legendre_tables(gl.data(), gl.data() + GL_MAXN * GL_MAXN);
+    HIP_TRY(c, hipMemcpy(c->twf, twf.data(), twf.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->twd, twd.data(), twd.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->gl, gl.data(), gl.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemset(c->flag, 0, sizeof(int)));
+    c->dev_init = true;
+    return TDGL_OK;
+}
+
+const void *tw(const tdgl_ctx *c) { return c->prec == PREC_F32 ? c->twf : c->twd; }
+
+// ---- reduced parameters (Table 2 with alpha_ref in place of |alpha1|)
+void landau_si(const tdgl_material &m, double T, double out[8])
+{
+    double a1;
+    if (m.a1_form == 0) a1 = m.a1_slope * (T - m.a1_T0);
+    else a1 = m.a1_A * (1.0 / std::tanh(m.a1_Ts / T) - 1.0 / std::tanh(m.a1_Ts / m.a1_T0));
+    out[0] = a1;
+    out[1] = a1;
+    out[2] = m.rs * a1;
+    out[3] = m.a11_slope * (T - m.a11_Tref) + m.a11_offset;
+    out[4] = m.a12;
+    out[5] = m.a111_slope * (T - m.a111_Tref) + m.a111_offset;
+    out[6] = m.a112;
+    out[7] = m.a123;
+}
+
+tdgl_status check_model(tdgl_ctx *c)
+{
+    if (!c->scales_set) return fail(c, TDGL_E_STATE, "tdgl_set_scales has not been called");
+    for (int z = 0; z < c->g.nz; ++z) {
+        const int id = c->layer[z];
+        if (id >= 0 && !c->mat_set[id])
+            return fail(c, TDGL_E_STATE, "layer %d uses material %d, which is not set", z, id);
+    }
+    if ((c->terms & TDGL_GRAD) && !c->grad_set)
+        return fail(c, TDGL_E_STATE, "gradient term on but tdgl_set_gradient not called");
+    return TDGL_OK;
+}
+
+void reduced(const tdgl_ctx *c, std::vector<double> &coef, double scal[8], double gh2[3][3])
+{
+    const double l0 = std::sqrt(c->G110 / c->alpha_ref);
+    const double h[3] = {c->d[0] / l0, c->d[1] / l0, c->d[2] / l0};
+    coef.assign((size_t)c->g.nz * NCOEF, 0.0);
+    for (int z = 0; z < c->g.nz; ++z) {
+        const int id = c->layer[z];
+        if (id < 0 || !c->mat_set[id]) continue;
+        double si[8];
+        landau_si(c->mats[id], c->T, si);
+        const double a = c->alpha_ref, p2 = c->P0 * c->P0, p4 = p2 * p2;
+        double *o = &coef[(size_t)z * NCOEF];
+        o[0] = si[0] / a;
+        o[1] = si[1] / a;
+        o[2] = si[2] / a;
+        o[3] = si[3] * p2 / a;
+        o[4] = si[4] * p2 / a;
+        o[5] = si[5] * p4 / a;
+        o[6] = si[6] * p4 / a;
+        o[7] = si[7] * p4 / a;
+        o[8] = 1.0;
+    }
+    scal[0] = 1.0 / (EPS0 * c->eps_b * c->alpha_ref);
+    scal[1] = h[0];
+    scal[2] = h[1];
+    scal[3] = h[2];
+    scal[4] = h[0] * h[1] * h[2];
+    scal[5] = c->alpha_ref * c->P0 * c->P0 * l0 * l0 * l0;
+    scal[6] = c->alpha_ref * c->P0;
+    scal[7] = l0;
+    for (int i = 0; i < 3; ++i)
+        for (int dd = 0; dd < 3; ++dd) {
+            const double gcoef = c->grad_set ? ((i == dd ? c->G11 : c->G44 + c->G44p) / c->G110) : 0.0;
+            gh2[i][dd] = gcoef / (h[dd] * h[dd]);
+        }
+}
+
+template <typename T>
+tdgl_status upload_params_t(tdgl_ctx *c)
+{
+    std::vector<double> coef;
+    double scal[8], gh2[3][3];
+    reduced(c, coef, scal, gh2);
+    std::vector<T> cf(coef.size());
+    for (size_t i = 0; i < coef.size(); ++i) cf[i] = (T)coef[i];
+    KParams<T> kp{};
+    kp.dtau = (T)c->dtau;
+    for (int k = 0; k < 3; ++k) kp.eext[k] = (T)(c->eext[k] / scal[6]);
+    for (int i = 0; i < 3; ++i)
+        for (int dd = 0; dd < 3; ++dd) kp.gh2[i][dd] = (T)gh2[i][dd];
+    kp.out_scale = (T)scal[6];
+    HIP_TRY(c, hipMemcpyAsync(c->coef, cf.data(), cf.size() * sizeof(T), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->kp, &kp, sizeof kp, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->params_dirty = false;
+    return TDGL_OK;
+}
+
+tdgl_status upload_params(tdgl_ctx *c)
+{
+    if (!c->params_dirty) return TDGL_OK;
+    tdgl_status st = check_model(c);
+    if (st != TDGL_OK) return st;
+    st = ensure_device(c);
+    if (st != TDGL_OK) return st;
+    return c->prec == PREC_F32 ? upload_params_t<float>(c) : upload_params_t<double>(c);
+}
+
+void drop_graphs(tdgl_ctx *c)
+{
+    for (auto &e : c->graphs)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    c->graphs.clear();
+}
+
+bool elec_on(const tdgl_ctx *c) { return (c->terms & TDGL_ELEC) != 0; }
+
+// ---- enqueue helpers
+hipError_t enq_fx(tdgl_ctx *c, const void *P, hipStream_t s)
+{
+    const Geom &g = c->g;
+    return launch_fx(c->prec, g.mx, P, 3LL * g.nz * g.ny, g.nx, g.nx, c->S1, g.hx, tw(c), s);
+}
+
+// y pass, z pass with the tensor, inverse y pass: S1 (x spectra) -> S1 (field rows)
+hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
+{
+    const Geom &g = c->g;
+    hipError_t e = launch_col(c->prec, g.my, false, c->S1, c->S2, g.hx, 3LL * g.nz,
+                              (long long)g.ny * g.hx, (long long)g.my * g.hx, g.hx, g.ny, g.my,
+                              tw(c), s);
+    if (e != hipSuccess) return e;
+    e = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), s);
+    if (e != hipSuccess) return e;
+    return launch_col(c->prec, g.my, true, c->S2, c->S1, g.hx, 3LL * g.nz,
+                      (long long)g.my * g.hx, (long long)g.ny * g.hx, g.hx, g.my, g.ny, tw(c), s);
+}
+
+hipError_t enq_eval(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
+                    int stage, unsigned terms, bool elec, bool fx_out, hipStream_t s)
+{
+    if (elec) {
+        hipError_t e = enq_yz(c, s);
+        if (e != hipSuccess) return e;
+    }
+    UpdArgs a{};
+    a.P_in = Pin;
+    a.P_old = Pold;
+    a.P_out = Pout;
+    a.S1 = c->S1;
+    a.coef = c->coef;
+    a.kp = c->kp;
+    a.partials = c->partials;
+    a.flag = c->flag;
+    a.stage = stage;
+    a.terms = terms;
+    a.elec_in = elec ? 1 : 0;
+    a.fx_out = fx_out ? 1 : 0;
+    a.yt = c->yt;
+    return launch_update(c->prec, mode, c->g, a, tw(c), s, nullptr);
+}
+
+// one time step starting from buffer *cur (updated for Euler)
+hipError_t enq_step(tdgl_ctx *c, int *cur, hipStream_t s)
+{
+    const bool el = elec_on(c);
+    const unsigned t = c->terms;
+    void *A = c->P[*cur], *B = c->P[1 - *cur];
+    if (c->scheme == TDGL_EULER) {
+        hipError_t e = enq_eval(c, UPD_STEP, A, nullptr, B, 0, t, el, el, s);
+        *cur = 1 - *cur;
+        return e;
+    }
+    hipError_t e = enq_eval(c, UPD_STEP, A, nullptr, B, 0, t, el, el, s);
+    if (e != hipSuccess) return e;
+    return enq_eval(c, UPD_STEP, B, A, A, 1, t, el, el, s);
+}
+
+tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
+{
+    const unsigned el = elec_on(c) ? 1u : 0u;
+    for (auto &e : c->graphs)
+        if (e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk && e.elec == el) {
+            *out = e.exec;
+            return TDGL_OK;
+        }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    int cur = c->cur;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < chunk && le == hipSuccess; ++i) le = enq_step(c, &cur, c->cap);
+    hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, TDGL_E_HIP, "graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess)
+        return fail(c, TDGL_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    GraphEntry ge;
+    ge.exec = exec;
+    ge.cur = c->cur;
+    ge.scheme = c->scheme;
+    ge.chunk = chunk;
+    ge.elec = el;
+    c->graphs.push_back(ge);
+    *out = exec;
+    return TDGL_OK;
+}
+
+tdgl_status read_flag(tdgl_ctx *c)
+{
+    int f = 0;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (f) return fail(c, TDGL_E_NONFINITE, "a time step produced a non-finite polarisation");
+    return TDGL_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+int tdgl_abi_version(void) { return TDGL_ABI_VERSION; }
+
+tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream, tdgl_ctx **out)
+{
+    if (!out) return TDGL_E_ARG;
+    *out = nullptr;
+    if (!grid) return TDGL_E_ARG;
+    if (precision != TDGL_FP32 && precision != TDGL_FP64) return TDGL_E_ARG;
+    const int n[3] = {grid->nx, grid->ny, grid->nz};
+    const double d[3] = {grid->dx, grid->dy, grid->dz};
+    for (int k = 0; k < 3; ++k) {
+        if (n[k] < 1 || n[k] > 4096) return TDGL_E_ARG;
+        if (!(d[k] > 0.0) || !std::isfinite(d[k])) return TDGL_E_ARG;
+    }
+    const unsigned pm = grid->periodic_mask;
+    if (pm != 0u && pm != 3u && pm != 7u) return TDGL_E_UNSUPPORTED;
+    int m[3];
+    for (int k = 0; k < 3; ++k) {
+        if (pm >> k & 1u) {
+            if (n[k] < 8 || (n[k] & (n[k] - 1)) != 0) return TDGL_E_UNSUPPORTED;
+            m[k] = n[k];
+        } else {
+            m[k] = next_pow2(2 * n[k] - 1);
+            if (m[k] < 8) m[k] = 8;
+        }
+        if (m[k] > MAXLEN) return TDGL_E_UNSUPPORTED;
+    }
+    tdgl_ctx *c = new (std::nothrow) tdgl_ctx();
+    if (!c) return TDGL_E_NOMEM;
+    c->g = Geom{n[0], n[1], n[2], m[0], m[1], m[2], m[0] / 2 + 1,
+                (int)(pm & 1u), (int)(pm >> 1 & 1u), (int)(pm >> 2 & 1u)};
+    for (int k = 0; k < 3; ++k) c->d[k] = d[k];
+    c->pmask = pm;
+    c->prec = precision;
+    c->esz = precision == TDGL_FP32 ? 4 : 8;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->layer.assign(n[2], 0);
+    c->yt = update_rows_per_block(c->prec, c->g);
+    c->nblocks = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
+    *out = c;
+    return TDGL_OK;
+}
+
+void tdgl_destroy(tdgl_ctx *c)
+{
+    if (!c) return;
+    if (c->dev_init) {
+        (void)hipStreamSynchronize(c->stream);
+        drop_graphs(c);
+        if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+        if (c->cap) (void)hipStreamDestroy(c->cap);
+    }
+    delete c;
+}
+
+const char *tdgl_last_error(const tdgl_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+tdgl_status tdgl_get_dims(const tdgl_ctx *c, int out[7])
+{
+    if (!c || !out) return TDGL_E_ARG;
+    const Geom &g = c->g;
+    const int v[7] = {g.nx, g.ny, g.nz, g.mx, g.my, g.mz, g.hx};
+    for (int k = 0; k < 7; ++k) out[k] = v[k];
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_workspace_size(const tdgl_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return TDGL_E_ARG;
+    *bytes = layout_of(c).total;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_bind_workspace(tdgl_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c) return TDGL_E_ARG;
+    if (c->dev_init) return fail(c, TDGL_E_STATE, "device memory already in use");
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) != 0)
+        return fail(c, TDGL_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < layout_of(c).total)
+        return fail(c, TDGL_E_ARG, "workspace too small: %zu < %zu", bytes, layout_of(c).total);
+    c->ws = dev_ptr;
+    c->ws_bytes = bytes;
+    c->ws_owned = false;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_scales(tdgl_ctx *c, double P0, double alpha_ref, double G110, double eps_b)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!(P0 > 0) || !(alpha_ref > 0) || !(G110 > 0) || !(eps_b > 0) || !std::isfinite(P0) ||
+        !std::isfinite(alpha_ref) || !std::isfinite(G110) || !std::isfinite(eps_b))
+        return fail(c, TDGL_E_ARG, "scales must be positive and finite");
+    const bool geom_change = !c->scales_set || alpha_ref != c->alpha_ref || G110 != c->G110 ||
+                             eps_b != c->eps_b;
+    c->P0 = P0;
+    c->alpha_ref = alpha_ref;
+    c->G110 = G110;
+    c->eps_b = eps_b;
+    c->scales_set = true;
+    if (geom_change) c->tensor_built = false;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_material(tdgl_ctx *c, int id, const tdgl_material *m)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!m || id < 0 || id >= TDGL_MAX_MATERIALS) return fail(c, TDGL_E_ARG, "bad material id");
+    if (m->a1_form != 0 && m->a1_form != 1) return fail(c, TDGL_E_ARG, "a1_form must be 0 or 1");
+    if (m->a1_form == 1 && (!(m->a1_Ts > 0) || !(m->a1_T0 > 0)))
+        return fail(c, TDGL_E_ARG, "Barrett form needs a1_Ts > 0 and a1_T0 > 0");
+    c->mats[id] = *m;
+    c->mat_set[id] = true;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_layer_materials(tdgl_ctx *c, const signed char *ids)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!ids) return fail(c, TDGL_E_ARG, "null layer map");
+    for (int z = 0; z < c->g.nz; ++z)
+        if (ids[z] < -1 || ids[z] >= TDGL_MAX_MATERIALS)
+            return fail(c, TDGL_E_ARG, "layer %d: material id %d out of range", z, (int)ids[z]);
+    c->layer.assign(ids, ids + c->g.nz);
+    c->params_dirty = true;
+    c->spec_valid = false;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_gradient(tdgl_ctx *c, double G11, double G12, double G44, double G44p)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!std::isfinite(G11) || !std::isfinite(G12) || !std::isfinite(G44) || !std::isfinite(G44p))
+        return fail(c, TDGL_E_ARG, "gradient coefficients must be finite");
+    const double mixed = G12 + G44 - G44p;
+    const double scale = std::fabs(G11) + std::fabs(G44) + std::fabs(G44p);
+    if (std::fabs(mixed) > 1e-12 * scale)
+        return fail(c, TDGL_E_UNSUPPORTED, "mixed-derivative gradient term G12+G44-G44' != 0");
+    c->G11 = G11;
+    c->G12 = G12;
+    c->G44 = G44;
+    c->G44p = G44p;
+    c->grad_set = true;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_build_tensor(tdgl_ctx *c, int mimg)
+{
+    if (!c) return TDGL_E_ARG;
+    if (mimg < 0 || mimg > 64) return fail(c, TDGL_E_ARG, "mimg must be in [0, 64]");
+    if (!c->scales_set) return fail(c, TDGL_E_STATE, "tdgl_set_scales has not been called");
+    tdgl_status st = ensure_device(c);
+    if (st != TDGL_OK) return st;
+    const Geom &g = c->g;
+    const size_t nreal = (size_t)g.mx * g.my * g.mz;
+    const size_t ncplx = (size_t)g.mz * g.my * g.hx;
+    double *R = nullptr;
+    void *C = nullptr;
+    if (hipMalloc(&R, 6 * nreal * sizeof(double)) != hipSuccess)
+        return fail(c, TDGL_E_NOMEM, "tensor build: hipMalloc failed");
+    if (hipMalloc(&C, 6 * ncplx * 2 * sizeof(double)) != hipSuccess) {
+        (void)hipFree(R);
+        return fail(c, TDGL_E_NOMEM, "tensor build: hipMalloc failed");
+    }
+    const double l0 = std::sqrt(c->G110 / c->alpha_ref);
+    const double kappa = 1.0 / (EPS0 * c->eps_b * c->alpha_ref);
+    hipError_t e = launch_tensor_real(g, c->pmask, mimg, c->d[0] / l0, c->d[1] / l0,
+                                      c->d[2] / l0, c->gl, c->gl + GL_MAXN * GL_MAXN, R,
+                                      c->stream);
+    if (e == hipSuccess) e = launch_tensor_k0(g, c->pmask, R, nullptr, c->stream);
+    if (e == hipSuccess)
+        e = launch_fx(PREC_F64, g.mx, R, 6LL * g.mz * g.my, g.mx, g.mx, C, g.hx, c->twd,
+                      c->stream);
+    if (e == hipSuccess)
+        e = launch_col(PREC_F64, g.my, false, C, C, g.hx, 6LL * g.mz, (long long)g.my * g.hx,
+                       (long long)g.my * g.hx, g.hx, g.my, g.my, c->twd, c->stream);
+    if (e == hipSuccess)
+        e = launch_col(PREC_F64, g.mz, false, C, C, (long long)g.my * g.hx, 6,
+                       (long long)g.mz * g.my * g.hx, (long long)g.mz * g.my * g.hx,
+                       (long long)g.my * g.hx, g.mz, g.mz, c->twd, c->stream);
+    if (e == hipSuccess)
+        e = launch_tensor_octant(c->prec, g, C, -kappa / (double)nreal, c->Nt, c->stream);
+    hipError_t se = hipStreamSynchronize(c->stream);
+    (void)hipFree(R);
+    (void)hipFree(C);
+    if (e != hipSuccess || se != hipSuccess)
+        return fail(c, TDGL_E_HIP, "tensor build failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : se));
+    c->tensor_built = true;
+    c->mimg = mimg;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_tensor_spectrum(tdgl_ctx *c, double *dst, size_t count)
+{
+    if (!c || !dst) return TDGL_E_ARG;
+    if (!c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
+    const Geom &g = c->g;
+    const size_t n = (size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * g.hx;
+    if (count < n) return fail(c, TDGL_E_ARG, "need %zu doubles", n);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->prec == PREC_F64) {
+        HIP_TRY(c, hipMemcpy(dst, c->Nt, n * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(n);
+        HIP_TRY(c, hipMemcpy(tmp.data(), c->Nt, n * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) dst[i] = tmp[i];
+    }
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_temperature(tdgl_ctx *c, double T)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!(T > 0) || !std::isfinite(T)) return fail(c, TDGL_E_ARG, "temperature must be > 0");
+    c->T = T;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_eext(tdgl_ctx *c, double ex, double ey, double ez)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!std::isfinite(ex) || !std::isfinite(ey) || !std::isfinite(ez))
+        return fail(c, TDGL_E_ARG, "E_ext must be finite");
+    c->eext[0] = ex;
+    c->eext[1] = ey;
+    c->eext[2] = ez;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_terms(tdgl_ctx *c, unsigned mask)
+{
+    if (!c) return TDGL_E_ARG;
+    if (mask & ~(unsigned)TDGL_ALL) return fail(c, TDGL_E_ARG, "unknown term bits");
+    if ((mask & TDGL_ELEC) != (c->terms & TDGL_ELEC)) c->spec_valid = false;
+    c->terms = mask;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_integrator(tdgl_ctx *c, int scheme, double dtau)
+{
+    if (!c) return TDGL_E_ARG;
+    if (scheme != TDGL_EULER && scheme != TDGL_HEUN) return fail(c, TDGL_E_ARG, "unknown scheme");
+    if (!(dtau > 0) || !std::isfinite(dtau)) return fail(c, TDGL_E_ARG, "dtau must be > 0");
+    c->scheme = scheme;
+    c->dtau = dtau;
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_graph_chunk(tdgl_ctx *c, int steps)
+{
+    if (!c) return TDGL_E_ARG;
+    if (steps < 0 || steps > 100000) return fail(c, TDGL_E_ARG, "graph chunk out of range");
+    c->graph_chunk = steps;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_P(tdgl_ctx *c, const void *src, int on_dev, int src_prec)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!src) return fail(c, TDGL_E_ARG, "null source");
+    if (src_prec != TDGL_FP32 && src_prec != TDGL_FP64) return fail(c, TDGL_E_ARG, "bad precision");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    const Geom &g = c->g;
+    const size_t n = (size_t)3 * g.nx * g.ny * g.nz;
+    void *dst = c->P[c->cur];
+    // stored in units of P0 (Table 2)
+    const double inv = 1.0 / c->P0;
+    if (on_dev) {
+        HIP_TRY(c, launch_convert(src_prec, src, c->prec, dst, n, inv, c->stream));
+    } else {
+        std::vector<unsigned char> tmp(n * c->esz);
+        for (size_t i = 0; i < n; ++i) {
+            const double v = (src_prec == TDGL_FP32 ? (double)static_cast<const float *>(src)[i]
+                                                    : static_cast<const double *>(src)[i]) * inv;
+            if (c->prec == PREC_F32) reinterpret_cast<float *>(tmp.data())[i] = (float)v;
+            else reinterpret_cast<double *>(tmp.data())[i] = v;
+        }
+        HIP_TRY(c, hipMemcpyAsync(dst, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    HIP_TRY(c, launch_zero_layers(c->prec, dst, c->coef, g, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    c->P_set = true;
+    c->spec_valid = false;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_P(tdgl_ctx *c, void *dst, int on_dev, int dst_prec)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!dst) return fail(c, TDGL_E_ARG, "null destination");
+    if (dst_prec != TDGL_FP32 && dst_prec != TDGL_FP64) return fail(c, TDGL_E_ARG, "bad precision");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    const Geom &g = c->g;
+    const size_t n = (size_t)3 * g.nx * g.ny * g.nz;
+    const void *src = c->P[c->cur];
+    if (on_dev) {
+        HIP_TRY(c, launch_convert(c->prec, src, dst_prec, dst, n, c->P0, c->stream));
+        return TDGL_OK;
+    }
+    std::vector<unsigned char> tmp(n * c->esz);
+    HIP_TRY(c, hipMemcpyAsync(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < n; ++i) {
+        const double v = (c->prec == PREC_F32 ? (double)reinterpret_cast<const float *>(tmp.data())[i]
+                                              : reinterpret_cast<const double *>(tmp.data())[i]) * c->P0;
+        if (dst_prec == TDGL_FP32) static_cast<float *>(dst)[i] = (float)v;
+        else static_cast<double *>(dst)[i] = v;
+    }
+    return read_flag(c);
+}
+
+tdgl_status tdgl_step(tdgl_ctx *c, long long nsteps)
+{
+    if (!c) return TDGL_E_ARG;
+    if (nsteps < 0) return fail(c, TDGL_E_ARG, "nsteps < 0");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    if (elec_on(c) && !c->tensor_built)
+        return fail(c, TDGL_E_STATE, "electrostatic term on but tensor not built");
+    if (nsteps == 0) return TDGL_OK;
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    const bool el = elec_on(c);
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    int chunk = c->graph_chunk;
+    if (c->scheme == TDGL_EULER && (chunk & 1)) chunk -= 1;
+    long long left = nsteps;
+    if (chunk > 0) {
+        while (left >= chunk) {
+            hipGraphExec_t exec = nullptr;
+            st = get_graph(c, chunk, &exec);
+            if (st != TDGL_OK) return st;
+            HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+            left -= chunk;
+        }
+    }
+    for (; left > 0; --left) {
+        int cur = c->cur;
+        HIP_TRY(c, enq_step(c, &cur, c->stream));
+        c->cur = cur;
+    }
+    c->spec_valid = el;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_eval_field(tdgl_ctx *c, unsigned mask, void *dst)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!dst) return fail(c, TDGL_E_ARG, "null destination");
+    if (mask & ~(unsigned)TDGL_ALL) return fail(c, TDGL_E_ARG, "unknown term bits");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    const bool el = (mask & TDGL_ELEC) != 0;
+    if (el && !c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
+    if ((mask & TDGL_GRAD) && !c->grad_set)
+        return fail(c, TDGL_E_STATE, "gradient coefficients not set");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    HIP_TRY(c, enq_eval(c, UPD_FIELD, c->P[c->cur], nullptr, dst, 0, mask, el, false, c->stream));
+    if (el) c->spec_valid = false;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_energies(tdgl_ctx *c, double F[5], double meanP[3])
+{
+    if (!c) return TDGL_E_ARG;
+    if (!F || !meanP) return fail(c, TDGL_E_ARG, "null output");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    const bool el = elec_on(c);
+    if (el && !c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    HIP_TRY(c, enq_eval(c, UPD_ENERGY, c->P[c->cur], nullptr, nullptr, 0, c->terms, el, false,
+                        c->stream));
+    if (el) c->spec_valid = false;
+    HIP_TRY(c, launch_reduce_partials(c->partials, c->nblocks, c->res, c->stream));
+    double r[8];
+    HIP_TRY(c, hipMemcpyAsync(r, c->res, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    st = read_flag(c);
+    std::vector<double> coef;
+    double scal[8], gh2[3][3];
+    reduced(c, coef, scal, gh2);
+    const double f = scal[4] * scal[5];
+    F[0] = r[0] * f;
+    F[1] = r[1] * f;
+    F[2] = r[2] * f;
+    F[3] = r[3] * f;
+    F[4] = F[0] + F[1] + F[2] + F[3];
+    long long nmat = 0;
+    for (int z = 0; z < c->g.nz; ++z)
+        if (c->layer[z] >= 0) nmat += (long long)c->g.nx * c->g.ny;
+    for (int k = 0; k < 3; ++k) meanP[k] = nmat ? r[4 + k] / (double)nmat * c->P0 : 0.0;
+    return st;
+}
+
+tdgl_status tdgl_get_reduced(const tdgl_ctx *c, double *coef, double scal[8])
+{
+    if (!c || !coef || !scal) return TDGL_E_ARG;
+    if (!c->scales_set) return TDGL_E_STATE;
+    std::vector<double> cf;
+    double gh2[3][3];
+    reduced(c, cf, scal, gh2);
+    for (int z = 0; z < c->g.nz; ++z)
+        for (int k = 0; k < 8; ++k) coef[z * 8 + k] = cf[(size_t)z * NCOEF + k];
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_sync(tdgl_ctx *c)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!c->dev_init) return TDGL_OK;
+    return read_flag(c);
+}
+
+}  // extern "C"

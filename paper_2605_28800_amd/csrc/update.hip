@@ -1,0 +1,419 @@
+// Fused local-field and time-integration kernel.
+//
+// One work-group owns yt consecutive rows (all x) of one z layer, for all
+// three components.  In order:
+//   1. inverse x transform of the electrostatic field rows (two rows of one
+//      component per complex line, Hermitian extension on the fly);
+//   2. per cell: Landau field (minus the P-derivative of eq 3), gradient
+//      field (eq 4, diagonal part, 7-point stencil; neighbours across an open
+//      surface or in vacuum are dropped, periodic dimensions wrap), applied
+//      field (eq 7) and the electrostatic field (eqs 5-6), then
+//        STEP  : an explicit stage of eq 1 (L = 1, reduced time):
+//                stage 0  P_out = P_in + dtau E          (Euler / Heun predictor)
+//                stage 1  P_out = (P_old + P_in)/2 + dtau/2 E   (Heun corrector)
+//        FIELD : E written out in V/m
+//        ENERGY: FP64 partial sums of the energy terms and of P;
+//   3. STEP with fx_out: forward x transform of the new rows, written over
+//      the spectra rows read in step 1, so the next field evaluation starts
+//      at the y pass.
+#include "fft_core.h"
+#include "internal.h"
+
+namespace tdgl {
+
+template <typename T>
+__device__ __forceinline__ T landau_dfdp(const T p[3], const T sq[3], const T *cf, int i)
+{
+    const int j = i == 0 ? 1 : 0;
+    const int k = i == 2 ? 1 : 2;
+    const T sj = sq[j] + sq[k];
+    const T s4 = sq[j] * sq[j] + sq[k] * sq[k];
+    // d/dP_i of eq 3 (cf: a1x a1y a1z a11 a12 a111 a112 a123)
+    return p[i] * (T(2) * cf[i] + T(4) * cf[3] * sq[i] + T(2) * cf[4] * sj +
+                   T(6) * cf[5] * sq[i] * sq[i] + cf[6] * (T(4) * sq[i] * sj + T(2) * s4) +
+                   T(2) * cf[7] * sq[j] * sq[k]);
+}
+
+template <typename T>
+__device__ __forceinline__ T landau_f(const T sq[3], const T *cf)
+{
+    const T x = sq[0], y = sq[1], z = sq[2];
+    return cf[0] * x + cf[1] * y + cf[2] * z + cf[3] * (x * x + y * y + z * z) +
+           cf[4] * (x * y + y * z + z * x) + cf[5] * (x * x * x + y * y * y + z * z * z) +
+           cf[6] * (x * x * (y + z) + y * y * (x + z) + z * z * (x + y)) + cf[7] * x * y * z;
+}
+
+template <typename T, int M, int MODE>
+__global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
+{
+    constexpr int TPL = M / 8;
+    constexpr int LEN = LinePad<M>::len;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
+    T *hs = reinterpret_cast<T *>(smem_raw);   // [3][yt][nx], aliases the FFT scratch
+    const int yt = a.yt, half = yt / 2, nlines = 3 * half;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int z = blockIdx.y, y0 = blockIdx.x * yt;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const long long plane = (long long)ny * nx;
+    const long long comp = (long long)nz * plane;
+    const T *Pin = reinterpret_cast<const T *>(a.P_in);
+    const T *coefz = reinterpret_cast<const T *>(a.coef) + (long long)z * NCOEF;
+    const KParams<T> *kp = reinterpret_cast<const KParams<T> *>(a.kp);
+    const bool material = coefz[8] != T(0);
+    const unsigned terms = a.terms;
+
+    // line mapping of the x transforms
+    const int l = tid / TPL, t = tid - l * TPL;
+    const bool lact = l < nlines;
+    const int lc = lact ? l / half : 0, lp = lact ? l - lc * half : 0;
+    const int ya = y0 + 2 * lp, yb = ya + 1;
+    const bool has_a = lact && ya < ny, has_b = lact && yb < ny;
+    cpx<T> *L = lds + (lact ? l : 0) * LEN;
+    cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
+    const IdxPad pad{};
+
+    // ---- 1. electrostatic field rows
+    if (a.elec_in) {
+        cpx<T> v[8];
+        const cpx<T> *ra = S1 + (((long long)lc * nz + z) * ny + ya) * g.hx;
+        const cpx<T> *rb = ra + g.hx;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = t + q * TPL;
+            const int kk = k <= M / 2 ? k : M - k;
+            cpx<T> A = has_a ? ra[kk] : cpx<T>{T(0), T(0)};
+            cpx<T> B = has_b ? rb[kk] : cpx<T>{T(0), T(0)};
+            if (kk == 0 || kk == M / 2) {
+                A.y = T(0);
+                B.y = T(0);
+            }
+            v[q] = k <= M / 2 ? cpx<T>{A.x - B.y, A.y + B.x} : cpx<T>{A.x + B.y, B.x - A.y};
+        }
+        fft_line<T, M, true>(v, L, pad, t, tw, lact);
+        __syncthreads();
+        if (lact) {
+            T *ha = hs + ((long long)lc * yt + 2 * lp) * nx;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int x = t + q * TPL;
+                if (x < nx) {
+                    ha[x] = v[q].x;
+                    ha[nx + x] = v[q].y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- 2. local terms and the update
+    const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const T dtau = kp->dtau;
+    const T *Pold = reinterpret_cast<const T *>(a.P_old);
+    T *Pout = reinterpret_cast<T *>(a.P_out);
+    const T *coefzm = z > 0 ? coefz - NCOEF : (g.pz ? coefz + (long long)(nz - 1) * NCOEF : nullptr);
+    const T *coefzp = z < nz - 1 ? coefz + NCOEF : (g.pz ? coefz - (long long)(nz - 1) * NCOEF : nullptr);
+    const bool hzm = coefzm && coefzm[8] != T(0);
+    const bool hzp = coefzp && coefzp[8] != T(0);
+    const long long dzm = z > 0 ? -plane : (long long)(nz - 1) * plane;
+    const long long dzp = z < nz - 1 ? plane : -(long long)(nz - 1) * plane;
+
+    for (int e = tid; e < yt * nx; e += nthr) {
+        const int yy = e / nx, x = e - yy * nx, y = y0 + yy;
+        if (y >= ny) continue;
+        const long long cell = (long long)z * plane + (long long)y * nx + x;
+        T p[3] = {Pin[cell], Pin[comp + cell], Pin[2 * comp + cell]};
+        T E[3] = {T(0), T(0), T(0)};
+        // neighbours
+        int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+        bool hxm = true, hxp = true, hym = true, hyp = true;
+        if (xm < 0) { if (g.px) xm += nx; else hxm = false; }
+        if (xp >= nx) { if (g.px) xp -= nx; else hxp = false; }
+        if (ym < 0) { if (g.py) ym += ny; else hym = false; }
+        if (yp >= ny) { if (g.py) yp -= ny; else hyp = false; }
+        const long long rowc = (long long)z * plane + (long long)y * nx;
+        const long long cxm = rowc + xm, cxp = rowc + xp;
+        const long long cym = (long long)z * plane + (long long)ym * nx + x;
+        const long long cyp = (long long)z * plane + (long long)yp * nx + x;
+        const long long czm = cell + dzm, czp = cell + dzp;
+        T sq[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sq[c] = p[c] * p[c];
+        T hel[3] = {T(0), T(0), T(0)};
+        if (a.elec_in) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hel[c] = hs[((long long)c * yt + yy) * nx + x];
+        }
+        T fg = T(0);
+        if (material) {
+            if (terms & T_LANDAU) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) E[c] -= landau_dfdp(p, sq, coefz, c);
+            }
+            if (terms & T_GRAD) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T *Pc = Pin + c * comp;
+                    const T pc = p[c];
+                    T lx = T(0), ly = T(0), lz = T(0);
+                    if (hxm) lx += Pc[cxm] - pc;
+                    if (hxp) lx += Pc[cxp] - pc;
+                    if (hym) ly += Pc[cym] - pc;
+                    if (hyp) ly += Pc[cyp] - pc;
+                    if (hzm) lz += Pc[czm] - pc;
+                    if (hzp) lz += Pc[czp] - pc;
+                    E[c] += kp->gh2[c][0] * lx + kp->gh2[c][1] * ly + kp->gh2[c][2] * lz;
+                    if (MODE == UPD_ENERGY) {
+                        // edges towards +x, +y, +z, each counted once
+                        if (hxp) { const T d = Pc[cxp] - pc; fg += T(0.5) * kp->gh2[c][0] * d * d; }
+                        if (hyp) { const T d = Pc[cyp] - pc; fg += T(0.5) * kp->gh2[c][1] * d * d; }
+                        if (hzp) { const T d = Pc[czp] - pc; fg += T(0.5) * kp->gh2[c][2] * d * d; }
+                    }
+                }
+            }
+            if (a.elec_in) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) E[c] += hel[c];
+            }
+            if (terms & T_EXT) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) E[c] += kp->eext[c];
+            }
+        }
+        if constexpr (MODE == UPD_STEP) {
+            T o[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!material) o[c] = T(0);
+                else if (a.stage == 0) o[c] = p[c] + dtau * E[c];
+                else o[c] = T(0.5) * (Pold[c * comp + cell] + p[c]) + T(0.5) * dtau * E[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Pout[c * comp + cell] = o[c];
+                if (!isfinite(o[c])) atomicOr(a.flag, 1);
+                if (do_fx) hs[((long long)c * yt + yy) * nx + x] = o[c];
+            }
+        } else if constexpr (MODE == UPD_FIELD) {
+            const T sc = kp->out_scale;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Pout[c * comp + cell] = material ? sc * E[c] : T(0);
+        } else {
+            if (material) {
+                if (terms & T_LANDAU) acc[0] += (double)landau_f(sq, coefz);
+                acc[1] += (double)fg;
+                if (a.elec_in)
+                    acc[2] += -0.5 * ((double)p[0] * hel[0] + (double)p[1] * hel[1] +
+                                      (double)p[2] * hel[2]);
+                if (terms & T_EXT)
+                    acc[3] += -((double)p[0] * kp->eext[0] + (double)p[1] * kp->eext[1] +
+                                (double)p[2] * kp->eext[2]);
+                acc[4] += (double)p[0];
+                acc[5] += (double)p[1];
+                acc[6] += (double)p[2];
+            }
+        }
+    }
+
+    // ---- 3. x spectrum of the new rows
+    if (do_fx) {
+        __syncthreads();
+        cpx<T> v[8];
+        const T *ha = hs + ((long long)lc * yt + 2 * lp) * nx;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int x = t + q * TPL;
+            const T av = (has_a && x < nx) ? ha[x] : T(0);
+            const T bv = (has_b && x < nx) ? ha[nx + x] : T(0);
+            v[q] = {av, bv};
+        }
+        __syncthreads();
+        fft_line<T, M, false>(v, L, pad, t, tw, lact);
+        __syncthreads();
+        if (lact) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) L[pad(t + q * TPL)] = v[q];
+        }
+        __syncthreads();
+        if (lact) {
+            cpx<T> *ra = S1 + (((long long)lc * nz + z) * ny + ya) * g.hx;
+            cpx<T> *rb = ra + g.hx;
+            for (int k = t; k <= M / 2; k += TPL) {
+                const cpx<T> zk = L[pad(k)], zm = L[pad((M - k) & (M - 1))];
+                if (has_a) ra[k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+                if (has_b) rb[k] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+            }
+        }
+    }
+
+    if constexpr (MODE == UPD_ENERGY) {
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(smem_raw);
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            double s = acc[k];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            acc[k] = s;
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) red[wave * 8 + k] = acc[k];
+        }
+        __syncthreads();
+        if (tid < 7) {
+            double s = 0.0;
+            const int nw = (nthr + 63) / 64;
+            for (int w = 0; w < nw; ++w) s += red[w * 8 + tid];
+            a.partials[((long long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = s;
+        }
+    }
+}
+
+// rows per work-group: even, about 256 threads per group for the x transforms
+int update_rows_per_block(int prec, const Geom &g)
+{
+    (void)prec;
+    const int tpl = g.mx / 8;
+    int lines = 256 / tpl;
+    if (lines < 3) lines = 3;
+    int yt = 2 * (lines / 3);
+    if (yt < 2) yt = 2;
+    const int ny_even = g.ny + (g.ny & 1);
+    if (yt > ny_even) yt = ny_even;
+    return yt;
+}
+
+template <typename T, int M, int MODE>
+static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, hipStream_t s,
+                              int *nblocks_out)
+{
+    constexpr int TPL = M / 8;
+    const int nlines = 3 * (a.yt / 2);
+    int nthr = nlines * TPL;
+    if (nthr < 64) nthr = 64;
+    nthr = (nthr + 63) / 64 * 64;
+    size_t shm = (size_t)nlines * LinePad<M>::len * sizeof(cpx<T>);
+    const size_t hs_bytes = (size_t)3 * a.yt * g.nx * sizeof(T);
+    if (shm < hs_bytes) shm = hs_bytes;
+    if (shm < 16 * 8 * sizeof(double)) shm = 16 * 8 * sizeof(double);
+    if (shm > 65536 || nthr > 1024) return hipErrorInvalidConfiguration;
+    dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz);
+    if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
+    hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, a, g,
+                       (const cpx<T> *)tw + M);
+    return hipGetLastError();
+}
+
+#define TDGL_MODE_SWITCH(T, LEN)                                                          \
+    switch (mode) {                                                                       \
+    case UPD_STEP: return update_impl<T, LEN, UPD_STEP>(g, a, tw, s, nblocks_out);        \
+    case UPD_FIELD: return update_impl<T, LEN, UPD_FIELD>(g, a, tw, s, nblocks_out);      \
+    default: return update_impl<T, LEN, UPD_ENERGY>(g, a, tw, s, nblocks_out);            \
+    }
+
+#define TDGL_UPD_LEN(T)                                        \
+    switch (g.mx) {                                            \
+    case 8: TDGL_MODE_SWITCH(T, 8)                             \
+    case 16: TDGL_MODE_SWITCH(T, 16)                           \
+    case 32: TDGL_MODE_SWITCH(T, 32)                           \
+    case 64: TDGL_MODE_SWITCH(T, 64)                           \
+    case 128: TDGL_MODE_SWITCH(T, 128)                         \
+    case 256: TDGL_MODE_SWITCH(T, 256)                         \
+    case 512: TDGL_MODE_SWITCH(T, 512)                         \
+    case 1024: TDGL_MODE_SWITCH(T, 1024)                       \
+    default: return hipErrorInvalidValue;                      \
+    }
+
+hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a, const void *tw,
+                         hipStream_t s, int *nblocks_out)
+{
+    if (prec == PREC_F32) {
+        TDGL_UPD_LEN(float)
+    } else {
+        TDGL_UPD_LEN(double)
+    }
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void k_reduce_partials(const double *__restrict__ part, int n, double *out)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    for (int k = 0; k < 8; ++k) {
+        double s = 0.0;
+        for (int i = tid; i < n; i += 256) s += part[(long long)i * 8 + k];
+        red[tid] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_reduce_partials(const double *partials, int n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+// dst = scale * src, with a precision change if asked (multiply in double)
+template <typename S, typename D>
+__global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t n, double scale)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = scale == 1.0 ? (D)src[i] : (D)(scale * (double)src[i]);
+}
+
+hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst, size_t n,
+                          double scale, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (n == 0) return hipSuccess;
+    if (src_prec == PREC_F32 && dst_prec == PREC_F64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks), dim3(256), 0, s,
+                           (const float *)src, (double *)dst, n, scale);
+    else if (src_prec == PREC_F64 && dst_prec == PREC_F32)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks), dim3(256), 0, s,
+                           (const double *)src, (float *)dst, n, scale);
+    else if (src_prec == PREC_F32)
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(blocks), dim3(256), 0, s,
+                           (const float *)src, (float *)dst, n, scale);
+    else
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(blocks), dim3(256), 0, s,
+                           (const double *)src, (double *)dst, n, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_zero_layers(T *P, const T *__restrict__ coef, int nz, long long plane)
+{
+    const int z = blockIdx.y;
+    const int c = blockIdx.z;
+    if (coef[(long long)z * NCOEF + 8] != T(0)) return;
+    T *row = P + ((long long)c * nz + z) * plane;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < plane;
+         i += (long long)gridDim.x * blockDim.x)
+        row[i] = T(0);
+}
+
+hipError_t launch_zero_layers(int prec, void *P, const void *coef, const Geom &g, hipStream_t s)
+{
+    const long long plane = (long long)g.nx * g.ny;
+    const unsigned bx = (unsigned)((plane + 255) / 256 < 1024 ? (plane + 255) / 256 : 1024);
+    dim3 grid(bx, g.nz, 3);
+    if (prec == PREC_F32)
+        hipLaunchKernelGGL((k_zero_layers<float>), grid, dim3(256), 0, s, (float *)P,
+                           (const float *)coef, g.nz, plane);
+    else
+        hipLaunchKernelGGL((k_zero_layers<double>), grid, dim3(256), 0, s, (double *)P,
+                           (const double *)coef, g.nz, plane);
+    return hipGetLastError();
+}
+
+}  // namespace tdgl

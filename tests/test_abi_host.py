@@ -1,0 +1,148 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/tdgl.h declares, validates arguments before touching the
+device, and computes the same reduced coefficients as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2605_28800_amd as T
+import tdgl_inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    if not os.path.exists(T.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    T.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tdgl.h")).read()
+    return sorted(set(re.findall(r"\b(tdgl_[A-Za-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(T.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(T.EXPORTED)
+
+
+def test_abi_version():
+    assert T.tdgl_abi_version() == 1
+
+
+def _grid(n=(16, 16, 8), d=(1e-9, 1e-9, 1e-9), pm=0):
+    return T.tdgl_grid(n[0], n[1], n[2], d[0], d[1], d[2], pm)
+
+
+@pytest.mark.parametrize("n,d,pm,status", [
+    ((0, 4, 4), (1e-9,) * 3, 0, T.TDGL_E_ARG),
+    ((4, 4, 4), (0.0, 1e-9, 1e-9), 0, T.TDGL_E_ARG),
+    ((4, 4, 4), (1e-9,) * 3, 1, T.TDGL_E_UNSUPPORTED),
+    ((12, 16, 4), (1e-9,) * 3, 3, T.TDGL_E_UNSUPPORTED),     # periodic x not a power of two
+    ((4, 4, 4), (1e-9,) * 3, 3, T.TDGL_E_UNSUPPORTED),       # periodic below 8
+    ((600, 4, 4), (1e-9,) * 3, 0, T.TDGL_E_UNSUPPORTED),     # padded length 2048
+])
+def test_create_rejects(n, d, pm, status):
+    with pytest.raises(T.TdglError) as e:
+        T.tdgl_create(_grid(n, d, pm), T.TDGL_FP32)
+    assert e.value.status == status
+
+
+@pytest.mark.parametrize("n,pm,dims", [
+    ((16, 16, 8), 0, (32, 32, 16)),
+    ((12, 10, 5), 0, (32, 32, 16)),
+    ((1, 1, 1), 0, (8, 8, 8)),
+    ((128, 128, 32), 3, (128, 128, 64)),
+    ((256, 256, 64), 0, (512, 512, 128)),
+    ((16, 8, 32), 7, (16, 8, 32)),
+])
+def test_padded_dims(n, pm, dims):
+    ctx = T.tdgl_create(_grid(n, pm=pm), T.TDGL_FP64)
+    try:
+        d = T.tdgl_get_dims(ctx)
+        assert d[:3] == n and d[3:6] == dims and d[6] == dims[0] // 2 + 1
+        assert T.tdgl_workspace_size(ctx) > 0
+    finally:
+        T.tdgl_destroy(ctx)
+
+
+def test_setter_validation_leaves_context_usable():
+    ctx = T.tdgl_create(_grid(), T.TDGL_FP32)
+    try:
+        for call in (lambda: T.tdgl_set_scales(ctx, 1.0, -1.0, 5e-10, 45.0),
+                     lambda: T.tdgl_set_integrator(ctx, 7, 1e-3),
+                     lambda: T.tdgl_set_integrator(ctx, T.TDGL_EULER, 0.0),
+                     lambda: T.tdgl_set_terms(ctx, 16),
+                     lambda: T.tdgl_set_temperature(ctx, -3.0),
+                     lambda: T.tdgl_set_layer_materials(ctx, [0] * 7 + [20]),
+                     lambda: T.tdgl_build_tensor(ctx, 65)):
+            with pytest.raises(T.TdglError) as e:
+                call()
+            assert e.value.status == T.TDGL_E_ARG
+        with pytest.raises(T.TdglError) as e:
+            T.tdgl_set_gradient(ctx, 5.1e-10, -2e-11, 2e-11, 2e-11)   # BaTiO3 mixed term
+        assert e.value.status == T.TDGL_E_UNSUPPORTED
+        with pytest.raises(T.TdglError) as e:
+            T.tdgl_step(ctx, 1)                                        # no P yet
+        assert e.value.status == T.TDGL_E_STATE
+        with pytest.raises(T.TdglError) as e:
+            T.tdgl_build_tensor(ctx, 4)                                # no scales yet
+        assert e.value.status == T.TDGL_E_STATE
+        assert b"scales" in T.lib().tdgl_last_error(ctx)
+    finally:
+        T.tdgl_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["c1", "c4_small"])
+def test_reduced_coefficients_match_oracle(name):
+    from oracle import tdgl_oracle as O
+    cfg = I.config(name)
+    cfg["T"] = 287.0
+    cfg["layers"] = list(cfg["layers"])
+    cfg["layers"][-1] = -1
+    ctx = T.tdgl_create(_grid(cfg["n"], cfg["d"], 0), T.TDGL_FP64)
+    try:
+        s = cfg["scales"]
+        T.tdgl_set_scales(ctx, s["P0"], s["alpha_ref"], s["G110"], s["eps_b"])
+        for i, m in enumerate(cfg["materials"]):
+            T.tdgl_set_material(ctx, i, m)
+        T.tdgl_set_layer_materials(ctx, cfg["layers"])
+        G = cfg["gradient"]
+        T.tdgl_set_gradient(ctx, G["G11"], G["G12"], G["G44"], G["G44p"])
+        T.tdgl_set_temperature(ctx, cfg["T"])
+        coef, scal = T.tdgl_get_reduced(ctx, cfg["n"][2])
+    finally:
+        T.tdgl_destroy(ctx)
+    prob = O.Problem(cfg, tensor=False)
+    assert np.allclose(coef, prob.coef, rtol=1e-14, atol=0)
+    assert scal[0] == pytest.approx(prob.kappa, rel=1e-14)
+    assert np.allclose(scal[1:4], prob.h, rtol=1e-14)
+    assert scal[4] == pytest.approx(prob.dV, rel=1e-14)
+    assert scal[5] == pytest.approx(prob.energy_scale, rel=1e-14)
+    assert scal[6] == pytest.approx(prob.field_scale, rel=1e-14)
+
+
+def test_device_calls_fail_cleanly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    cfg = I.config("c1")
+    ctx = T.tdgl_create(_grid(), T.TDGL_FP64)
+    try:
+        s = cfg["scales"]
+        T.tdgl_set_scales(ctx, s["P0"], s["alpha_ref"], s["G110"], s["eps_b"])
+        with pytest.raises(T.TdglError) as e:
+            T.tdgl_build_tensor(ctx, 0)
+        assert e.value.status == T.TDGL_E_HIP
+    finally:
+        T.tdgl_destroy(ctx)

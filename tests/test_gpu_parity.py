@@ -1,0 +1,158 @@
+"""GPU parity: HIP path through the C ABI vs the FP64 oracle, element by
+element, on seeded inputs.
+
+Tolerances: FP64 fields 1e-13 of the field's max norm (FFT round-off at
+these lengths is ~1e-15); FP32 fields 2e-6 (the convolution sums ~log2(M)
+FP32 round-offs of the field's magnitude); trajectories |dP|/Ps <= 1e-12
+(FP64) and <= 1e-5 (FP32) over horizons where the flow is contractive.
+"""
+import numpy as np
+import pytest
+
+import paper_2605_28800_amd as T
+import tdgl_inputs as I
+from oracle import tdgl_oracle as O
+from tests.gpu_helpers import announce, gpu_context, oracle_field, ps_of, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+MASKS = [T.TDGL_LANDAU, T.TDGL_GRAD, T.TDGL_ELEC, T.TDGL_EXT, T.TDGL_ALL]
+
+
+def _cfg(n, periodic, mimg=2, layers=None, two_materials=False, eext=(2e6, -1e6, 3e6)):
+    cfg = I.config("c1")
+    cfg.update(n=n, periodic=periodic, mimg=mimg, eext=eext)
+    cfg["layers"] = list(layers) if layers is not None else [0] * n[2]
+    if two_materials:
+        cfg["materials"] = [I.BATIO3, dict(I.BATIO3, a1_T0=420.0, a12=1.0e8, rs=1.3)]
+    return cfg
+
+
+CASES = {
+    "open_16x16x8": dict(n=(16, 16, 8), periodic=(0, 0, 0)),
+    "open_ragged_12x10x5": dict(n=(12, 10, 5), periodic=(0, 0, 0)),
+    "open_odd_7x9x3": dict(n=(7, 9, 3), periodic=(0, 0, 0)),
+    "film_16x16x4": dict(n=(16, 16, 4), periodic=(1, 1, 0)),
+    "bulk_8x16x8": dict(n=(8, 16, 8), periodic=(1, 1, 1)),
+    "bilayer_vacuum_10x12x6": dict(n=(10, 12, 6), periodic=(0, 0, 0),
+                                   layers=[0, 0, 0, 1, 1, -1], two_materials=True),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_field_parity(case, prec):
+    cfg = _cfg(**CASES[case])
+    announce("field parity %s %s" % (case, prec))
+    P = I.initial_P(cfg, 3, np.float32 if prec == "f32" else np.float64)
+    P64 = P.astype(np.float64)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, prec)
+    try:
+        ctx.set_P(P)
+        tol = 1e-13 if prec == "f64" else 2e-6
+        for mask in MASKS:
+            got = ctx.eval_field(mask).cpu().numpy()
+            ref = oracle_field(P64, prob, mask)
+            err = rel_inf(got, ref)
+            assert err <= tol, (case, prec, mask, err)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("case", ["open_16x16x8", "open_ragged_12x10x5", "film_16x16x4",
+                                  "bulk_8x16x8"])
+def test_tensor_spectrum_parity(case):
+    """The device-built FP64 tensor spectrum equals the oracle's table,
+    transformed with numpy, on the stored octant."""
+    cfg = _cfg(**CASES[case])
+    announce("tensor spectrum %s" % case)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64")
+    try:
+        got = T.tdgl_get_tensor_spectrum(ctx.ctx)
+        nx, ny, nz, mx, my, mz, hx = ctx.dims
+    finally:
+        ctx.close()
+    kern = np.zeros((6, mz, my, mx))
+
+    def positions(dim, size, M):
+        if cfg["periodic"][dim]:
+            return np.arange(size), np.arange(size)
+        idx = np.arange(2 * size - 1)
+        return idx, (idx - (size - 1)) % M
+    iz, pz = positions(2, nz, mz)
+    iy, py = positions(1, ny, my)
+    ix, px = positions(0, nx, mx)
+    kern[:, pz[:, None, None], py[None, :, None], px[None, None, :]] = \
+        prob.tab[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]]
+    spec = np.fft.rfftn(kern, axes=(1, 2, 3))
+    assert np.abs(spec.imag).max() < 1e-12 * np.abs(spec.real).max()
+    ref = -prob.kappa / (mx * my * mz) * spec.real[:, :mz // 2 + 1, :my // 2 + 1, :]
+    assert rel_inf(got, ref) <= 1e-13
+
+
+def test_c1_trajectory_fp64():
+    """The FP64 parity configuration in full: 16x16x8 open box, BaTiO3 at
+    300 K, all terms, Euler, 1000 steps of dtau = 1e-3."""
+    cfg = I.config("c1")
+    announce("C1 trajectory fp64 1000 Euler steps")
+    P0 = I.initial_P(cfg, 0)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64")
+    try:
+        ctx.set_P(P0)
+        Ps = ps_of(cfg)
+        P = P0
+        done = 0
+        for chk in (1, 10, 100, 1000):
+            ctx.step(chk - done)
+            P = O.run(P, prob, "euler", cfg["dtau"], chk - done)
+            done = chk
+            err = np.abs(ctx.get_P() - P).max() / Ps
+            assert err <= 1e-12, (chk, err)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_film_heun_trajectory(prec, tol):
+    cfg = I.config("c2_small")
+    announce("c2_small heun trajectory %s" % prec)
+    P0 = I.initial_P(cfg, 0, np.float32 if prec == "f32" else np.float64)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, prec)
+    try:
+        ctx.set_P(P0)
+        Ps = ps_of(cfg)
+        P = P0.astype(np.float64)
+        done = 0
+        for chk in (1, 50, 200):
+            ctx.step(chk - done)
+            P = O.run(P, prob, "heun", cfg["dtau"], chk - done)
+            done = chk
+            err = np.abs(ctx.get_P() - P).max() / Ps
+            assert err <= tol, (chk, err)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("case", ["open_16x16x8", "film_16x16x4", "bilayer_vacuum_10x12x6"])
+def test_energies_parity(case):
+    cfg = _cfg(**CASES[case])
+    announce("energies %s" % case)
+    P = I.initial_P(cfg, 5) * 3
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64")
+    try:
+        ctx.set_P(P)
+        F, meanP = ctx.energies()
+    finally:
+        ctx.close()
+    E = O.energies(P, prob)
+    ref = [E["F_land"], E["F_grad"], E["F_elec"], E["F_ext"], E["F_total"]]
+    ref = [v * prob.energy_scale for v in ref]
+    scale = max(abs(v) for v in ref)
+    for k in range(5):
+        assert abs(F[k] - ref[k]) <= 1e-12 * scale, (k, F[k], ref[k])
+    assert np.allclose(meanP, E["meanP"] * prob.P0, rtol=0, atol=1e-15)
