@@ -209,6 +209,14 @@ tdgl_status tdgl_energies(tdgl_ctx *ctx, double F[5], double meanP[3]);
  * dV*, energy scale (J), field scale (V/m), l0 (m).  Host-side; for tests. */
 tdgl_status tdgl_get_reduced(const tdgl_ctx *ctx, double *coef, double scal[8]);
 
+/* Advance nsteps time steps with plain stream launches and time every kernel
+ * with HIP events recorded on the context's stream around it.  ms_out[5]
+ * receives the mean duration (ms) per launch of: y forward pass, z pass
+ * with tensor multiply, y inverse pass, update (predictor / Euler stage),
+ * update (Heun corrector); 0 for kernels that did not run.  Synchronising.
+ * For benchmarks and profiling; the state advances like tdgl_step. */
+tdgl_status tdgl_profile_step(tdgl_ctx *ctx, int nsteps, double ms_out[5]);
+
 /* Wait for all work of the context; returns TDGL_E_NONFINITE if a step
  * produced a non-finite P. */
 tdgl_status tdgl_sync(tdgl_ctx *ctx);

@@ -77,6 +77,7 @@ _SIGS = {
     "tdgl_eval_field": ([_ctx_p, c_uint, c_void_p], c_int),
     "tdgl_energies": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_get_reduced": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
+    "tdgl_profile_step": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_sync": ([_ctx_p], c_int),
 }
 EXPORTED = tuple(_SIGS)
@@ -221,6 +222,12 @@ def tdgl_get_reduced(ctx, nz: int):
     _check(ctx, lib().tdgl_get_reduced(ctx, coef.ctypes.data_as(ctypes.POINTER(c_double)),
                                        scal.ctypes.data_as(ctypes.POINTER(c_double))))
     return coef, scal
+
+
+def tdgl_profile_step(ctx, nsteps: int):
+    ms = (c_double * 5)()
+    _check(ctx, lib().tdgl_profile_step(ctx, nsteps, ms))
+    return tuple(ms)
 
 
 def tdgl_sync(ctx):

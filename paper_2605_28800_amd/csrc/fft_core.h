@@ -120,17 +120,69 @@ struct LinePad {
     static constexpr int len = M + M / 8;   // LDS elements per line with IdxPad
 };
 
-// Remaining stages after the first.  Every thread of the work-group must
-// reach these barriers; threads with act == false only skip memory traffic.
-template <typename T, int M, int P, bool INV, class Idx>
-__device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
-                                           const cpx<T> *__restrict__ tw, bool act)
+// Radix schedule: stage 0 has P = 1, R = 8; stage s has P = 8^s and
+// R = min(8, M/P).  Each thread needs NB*(R-1) twiddles per stage s >= 1;
+// they depend only on the thread's position, so a kernel loads them into
+// registers at its start (TwReg), overlapping their latency with the data
+// loads, and the stages read them from registers.
+template <int M, int S>
+struct Stage {
+    static constexpr int P = S == 0 ? 1 : 8 * Stage<M, (S > 0 ? S - 1 : 0)>::P;
+    static constexpr int R = (M / P >= 8) ? 8 : (M / P);
+    static constexpr int NB = 8 / R;
+    static constexpr int NTW = S == 0 ? 0 : NB * (R - 1);
+    static constexpr int OFF = S == 0 ? 0 : Stage<M, (S > 0 ? S - 1 : 0)>::OFF +
+                                               Stage<M, (S > 0 ? S - 1 : 0)>::NTW;
+    static constexpr bool LAST = P * R == M;
+};
+template <int M>
+struct Stage<M, 0> {
+    static constexpr int P = 1, R = 8, NB = 1, NTW = 0, OFF = 0;
+    static constexpr bool LAST = (M == 8);
+};
+
+template <int M, int S = 0>
+constexpr int twiddle_count()
 {
-    constexpr int R = (M / P >= 8) ? 8 : (M / P);
-    constexpr int NB = 8 / R;          // butterflies per thread
-    constexpr int TPL = M / 8;         // threads per line
+    if constexpr (Stage<M, S>::LAST) return Stage<M, S>::OFF + Stage<M, S>::NTW;
+    else return twiddle_count<M, S + 1>();
+}
+
+template <typename T, int M>
+struct TwReg {
+    static constexpr int N = twiddle_count<M>();
+    cpx<T> w[N > 0 ? N : 1];
+};
+
+template <typename T, int M, int S = 1>
+__device__ __forceinline__ void twiddle_load(TwReg<T, M> &tr, const cpx<T> *__restrict__ tab,
+                                             int t)
+{
+    if constexpr (M > 8) {
+        using St = Stage<M, S>;
+        constexpr int TPL = M / 8;
+#pragma unroll
+        for (int b = 0; b < St::NB; ++b) {
+            const int i = t + b * TPL;
+            const int k = i & (St::P - 1);
+#pragma unroll
+            for (int r = 1; r < St::R; ++r)
+                tr.w[St::OFF + b * (St::R - 1) + r - 1] = tab[r * k * (M / (St::P * St::R))];
+        }
+        if constexpr (!St::LAST) twiddle_load<T, M, S + 1>(tr, tab, t);
+    }
+}
+
+// Stages s >= 1.  Every thread of the work-group must reach these barriers;
+// threads with act == false only skip memory traffic.
+template <typename T, int M, int S, bool INV, class Idx>
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
+                                           const TwReg<T, M> &tr, bool act)
+{
+    using St = Stage<M, S>;
+    constexpr int R = St::R, NB = St::NB, P = St::P;
+    constexpr int TPL = M / 8;
     constexpr int MR = M / R;
-    constexpr bool LAST = (P * R == M);
     __syncthreads();
     if (act) {
 #pragma unroll
@@ -141,17 +193,15 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx,
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int i = t + b * TPL;
-            const int k = i & (P - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const cpx<T> w = tw[r * k * (M / (P * R))];
+                const cpx<T> w = tr.w[St::OFF + b * (R - 1) + r - 1];
                 v[b * R + r] = INV ? cmulc(v[b * R + r], w) : cmul(v[b * R + r], w);
             }
             dftR<T, R, INV>(v + b * R);
         }
     }
-    if constexpr (LAST) {
+    if constexpr (St::LAST) {
         if constexpr (NB > 1) {
             cpx<T> tmp[8];
 #pragma unroll
@@ -173,16 +223,17 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx,
                 for (int r = 0; r < R; ++r) lds[idx(j + r * P)] = v[b * R + r];
             }
         }
-        fft_stages<T, M, P * R, INV, Idx>(v, lds, idx, t, tw, act);
+        fft_stages<T, M, S + 1, INV, Idx>(v, lds, idx, t, tr, act);
     }
 }
 
 // Full line transform.  The caller must make sure no thread still reads the
 // line's LDS region from an earlier use (barrier) before calling, and must
-// barrier again before reusing it afterwards.
+// barrier again before reusing it afterwards.  tr: this thread's twiddles
+// (twiddle_load with the forward table; the inverse conjugates them).
 template <typename T, int M, bool INV, class Idx>
 __device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
-                                         const cpx<T> *__restrict__ tw, bool act)
+                                         const TwReg<T, M> &tr, bool act)
 {
     static_assert(M >= 8 && M <= 1024 && (M & (M - 1)) == 0, "length");
     if (act) dft8<T, INV>(v);
@@ -191,7 +242,7 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, i
 #pragma unroll
             for (int r = 0; r < 8; ++r) lds[idx(8 * t + r)] = v[r];
         }
-        fft_stages<T, M, 8, INV, Idx>(v, lds, idx, t, tw, act);
+        fft_stages<T, M, 1, INV, Idx>(v, lds, idx, t, tr, act);
     }
 }
 

@@ -31,6 +31,8 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     const long long rb = ra + 1;
     const bool act = (l < lpw) && (ra < nrows);
     const bool hasb = act && (rb < nrows);
+    TwReg<T, M> tr;
+    twiddle_load(tr, tw, t);
     cpx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -42,7 +44,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     }
     cpx<T> *L = lds + l * LEN;
     const IdxPad pad{};
-    fft_line<T, M, false>(v, L, pad, t, tw, act);
+    fft_line<T, M, false>(v, L, pad, t, tr, act);
     __syncthreads();
     if (act) {
 #pragma unroll
@@ -60,30 +62,35 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
 }
 
 // ------------------------------------------------------------ column pass
-// Element e of column col in batch b sits at  base + b*bstride + e*lstride + col.
+// Element e of column col in batch b sits at  b*bstride + e*lstride + col.
+// Columns of all batches are numbered j = b*C + col and tiled CT at a time,
+// so no tile is left partly empty when C is not a multiple of CT.
 // In-place use (in == out) is safe: every thread stores exactly the
 // positions it loaded.
 template <typename T, int M, bool INV>
-__global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, int CT, long long in_bstride,
-                      long long out_bstride, long long lstride, int n_in, int n_out,
-                      const cpx<T> *__restrict__ tw)
+__global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, long long ncols, int CT,
+                      long long in_bstride, long long out_bstride, long long lstride, int n_in,
+                      int n_out, const cpx<T> *__restrict__ tw)
 {
     constexpr int TPL = M / 8;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     const int tid = threadIdx.x;
     const int cc = tid % CT, t = tid / CT;
-    const long long col = (long long)blockIdx.x * CT + cc;
-    const long long b = blockIdx.y;
-    const bool act = col < C;
+    const long long j = (long long)blockIdx.x * CT + cc;
+    const bool act = j < ncols;
+    const long long b = act ? j / C : 0;
+    const long long col = act ? j - b * C : 0;
     const cpx<T> *src = in + b * in_bstride + col;
+    TwReg<T, M> tr;
+    twiddle_load(tr, tw, t);
     cpx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int e = t + q * TPL;
         v[q] = (act && e < n_in) ? src[(long long)e * lstride] : cpx<T>{T(0), T(0)};
     }
-    fft_line<T, M, INV>(v, lds + cc, IdxStride{CT}, t, tw, act);
+    fft_line<T, M, INV>(v, lds + cc, IdxStride{CT}, t, tr, act);
     cpx<T> *dst = out + b * out_bstride + col;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -97,8 +104,14 @@ __global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, int CT, long l
 // components xx yy zz xy xz yz; xy is odd in ky, xz odd in kz, yz odd in
 // both, so entries outside the stored octant take the mirrored value with
 // the corresponding sign.
+// FP64 blocks stay at <= 512 threads so each wave may hold up to 256 VGPRs
+template <typename T>
+struct ZmulMaxThreads {
+    static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
+};
+
 template <typename T, int MZ>
-__global__ void k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int hx, int CT,
+__global__ void __launch_bounds__(ZmulMaxThreads<T>::v) k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int hx, int CT,
                        const cpx<T> *__restrict__ tw)
 {
     constexpr int TPL = MZ / 8;
@@ -108,11 +121,37 @@ __global__ void k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int 
     const int cc = tid % CT;
     const int t = (tid / CT) % TPL;
     const int c = tid / (CT * TPL);
-    const int ky = blockIdx.y;
-    const int kx = blockIdx.x * CT + cc;
-    const bool act = kx < hx;
     const long long plane = (long long)my * hx;
-    cpx<T> *col = S + (long long)c * nz * plane + (long long)ky * hx + kx;
+    // (ky, kx) columns are contiguous within a (component, z) plane
+    const long long j = (long long)blockIdx.x * CT + cc;
+    const bool act = j < plane;
+    const int ky = act ? (int)(j / hx) : 0;
+    const int kx = act ? (int)(j - (long long)ky * hx) : 0;
+    cpx<T> *col = S + (long long)c * nz * plane + (act ? j : 0);
+    TwReg<T, MZ> tr;
+    twiddle_load(tr, tw, t);
+    // tensor row c at this thread's (kx, ky, kz) points, fetched up front
+    const int hy = my / 2;
+    const int kyo = ky <= hy ? ky : my - ky;
+    const T sy = ky > hy ? T(-1) : T(1);
+    const long long s6 = (long long)(MZ / 2 + 1) * (hy + 1) * hx;
+    const int i0 = c == 0 ? 0 : (c == 1 ? 3 : 4);   // (c,x) (c,y) (c,z)
+    const int i1 = c == 0 ? 3 : (c == 1 ? 1 : 5);
+    const int i2 = c == 0 ? 4 : (c == 1 ? 5 : 2);
+    auto sgn = [&](int comp, T sz) -> T {
+        return comp == 3 ? sy : (comp == 4 ? sz : (comp == 5 ? sy * sz : T(1)));
+    };
+    T nrow[8][3];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int kz = t + q * TPL;
+        const int kzo = kz <= MZ / 2 ? kz : MZ - kz;
+        const T sz = kz > MZ / 2 ? T(-1) : T(1);
+        const T *nb = Nt + ((long long)kzo * (hy + 1) + kyo) * hx + kx;
+        nrow[q][0] = act ? nb[i0 * s6] * sgn(i0, sz) : T(0);
+        nrow[q][1] = act ? nb[i1 * s6] * sgn(i1, sz) : T(0);
+        nrow[q][2] = act ? nb[i2 * s6] * sgn(i2, sz) : T(0);
+    }
     cpx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -120,42 +159,26 @@ __global__ void k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int 
         v[q] = (act && z < nz) ? col[(long long)z * plane] : cpx<T>{T(0), T(0)};
     }
     cpx<T> *L = lds + c * MZ * CT + cc;
-    fft_line<T, MZ, false>(v, L, IdxStride{CT}, t, tw, act);
+    fft_line<T, MZ, false>(v, L, IdxStride{CT}, t, tr, act);
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) L[(t + q * TPL) * CT] = v[q];
     }
     __syncthreads();
-    const int hy = my / 2;
-    const int kyo = ky <= hy ? ky : my - ky;
-    const T sy = ky > hy ? T(-1) : T(1);
-    const long long s6 = (long long)(MZ / 2 + 1) * (hy + 1) * hx;
-    // tensor components of row c: (c,x) (c,y) (c,z)
-    const int i0 = c == 0 ? 0 : (c == 1 ? 3 : 4);
-    const int i1 = c == 0 ? 3 : (c == 1 ? 1 : 5);
-    const int i2 = c == 0 ? 4 : (c == 1 ? 5 : 2);
     if (act) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int kz = t + q * TPL;
-            const int kzo = kz <= MZ / 2 ? kz : MZ - kz;
-            const T sz = kz > MZ / 2 ? T(-1) : T(1);
-            const T *nb = Nt + ((long long)kzo * (hy + 1) + kyo) * hx + kx;
-            auto sgn = [&](int comp) -> T {
-                return comp == 3 ? sy : (comp == 4 ? sz : (comp == 5 ? sy * sz : T(1)));
-            };
-            const T n0 = nb[i0 * s6] * sgn(i0);
-            const T n1 = nb[i1 * s6] * sgn(i1);
-            const T n2 = nb[i2 * s6] * sgn(i2);
             const cpx<T> p0 = lds[(0 * MZ + kz) * CT + cc];
             const cpx<T> p1 = lds[(1 * MZ + kz) * CT + cc];
             const cpx<T> p2 = lds[(2 * MZ + kz) * CT + cc];
+            const T n0 = nrow[q][0], n1 = nrow[q][1], n2 = nrow[q][2];
             v[q] = {n0 * p0.x + n1 * p1.x + n2 * p2.x, n0 * p0.y + n1 * p1.y + n2 * p2.y};
         }
     }
     __syncthreads();
-    fft_line<T, MZ, true>(v, L, IdxStride{CT}, t, tw, act);
+    fft_line<T, MZ, true>(v, L, IdxStride{CT}, t, tr, act);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
@@ -224,19 +247,20 @@ static hipError_t col_impl(bool inv, const void *in, void *out, long long C, lon
 {
     constexpr int TPL = M / 8;
     const int ct = col_tile<T, M>();
-    const long long gx = (C + ct - 1) / ct;
-    if (gx <= 0 || nbatch <= 0) return hipSuccess;
-    if (nbatch > 65535 || gx > 0x7fffffffLL) return hipErrorInvalidValue;
+    const long long ncols = C * nbatch;
+    const long long gx = (ncols + ct - 1) / ct;
+    if (gx <= 0) return hipSuccess;
+    if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
     const size_t shm = (size_t)ct * M * sizeof(cpx<T>);
-    dim3 grid((unsigned)gx, (unsigned)nbatch);
+    dim3 grid((unsigned)gx);
     if (inv)
         hipLaunchKernelGGL((k_col<T, M, true>), grid, dim3(ct * TPL), shm, s,
-                           (const cpx<T> *)in, (cpx<T> *)out, C, ct, in_bstride, out_bstride,
-                           lstride, n_in, n_out, (const cpx<T> *)tw + M);
+                           (const cpx<T> *)in, (cpx<T> *)out, C, ncols, ct, in_bstride,
+                           out_bstride, lstride, n_in, n_out, (const cpx<T> *)tw + M);
     else
         hipLaunchKernelGGL((k_col<T, M, false>), grid, dim3(ct * TPL), shm, s,
-                           (const cpx<T> *)in, (cpx<T> *)out, C, ct, in_bstride, out_bstride,
-                           lstride, n_in, n_out, (const cpx<T> *)tw + M);
+                           (const cpx<T> *)in, (cpx<T> *)out, C, ncols, ct, in_bstride,
+                           out_bstride, lstride, n_in, n_out, (const cpx<T> *)tw + M);
     return hipGetLastError();
 }
 
@@ -261,12 +285,13 @@ static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *
 {
     constexpr int TPL = MZ / 8;
     int ct = 128 / (int)sizeof(cpx<T>);
-    while (ct > 1 && (3 * ct * TPL > 1024 || (size_t)3 * ct * MZ * sizeof(cpx<T>) > 65536))
+    while (ct > 1 && (3 * ct * TPL > ZmulMaxThreads<T>::v ||
+                      (size_t)3 * ct * MZ * sizeof(cpx<T>) > 65536))
         ct /= 2;
-    const int gx = (g.hx + ct - 1) / ct;
-    if (g.my > 65535) return hipErrorInvalidValue;
+    const long long ncols = (long long)g.my * g.hx;
+    const long long gx = (ncols + ct - 1) / ct;
     const size_t shm = (size_t)3 * ct * MZ * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.my), dim3(3 * ct * TPL), shm, s,
+    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3((unsigned)gx), dim3(3 * ct * TPL), shm, s,
                        (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.hx, ct,
                        (const cpx<T> *)tw + MZ);
     return hipGetLastError();

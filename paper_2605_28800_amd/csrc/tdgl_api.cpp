@@ -360,13 +360,9 @@ hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
                       (long long)g.my * g.hx, (long long)g.ny * g.hx, g.hx, g.my, g.ny, tw(c), s);
 }
 
-hipError_t enq_eval(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
-                    int stage, unsigned terms, bool elec, bool fx_out, hipStream_t s)
+hipError_t enq_upd(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
+                   int stage, unsigned terms, bool elec_in, bool fx_out, hipStream_t s)
 {
-    if (elec) {
-        hipError_t e = enq_yz(c, s);
-        if (e != hipSuccess) return e;
-    }
     UpdArgs a{};
     a.P_in = Pin;
     a.P_old = Pold;
@@ -378,10 +374,20 @@ hipError_t enq_eval(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, vo
     a.flag = c->flag;
     a.stage = stage;
     a.terms = terms;
-    a.elec_in = elec ? 1 : 0;
+    a.elec_in = elec_in ? 1 : 0;
     a.fx_out = fx_out ? 1 : 0;
     a.yt = c->yt;
     return launch_update(c->prec, mode, c->g, a, tw(c), s, nullptr);
+}
+
+hipError_t enq_eval(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
+                    int stage, unsigned terms, bool elec, bool fx_out, hipStream_t s)
+{
+    if (elec) {
+        hipError_t e = enq_yz(c, s);
+        if (e != hipSuccess) return e;
+    }
+    return enq_upd(c, mode, Pin, Pold, Pout, stage, terms, elec, fx_out, s);
 }
 
 // one time step starting from buffer *cur (updated for Euler)
@@ -863,6 +869,84 @@ tdgl_status tdgl_get_reduced(const tdgl_ctx *c, double *coef, double scal[8])
     reduced(c, cf, scal, gh2);
     for (int z = 0; z < c->g.nz; ++z)
         for (int k = 0; k < 8; ++k) coef[z * 8 + k] = cf[(size_t)z * NCOEF + k];
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
+{
+    if (!c) return TDGL_E_ARG;
+    if (!ms_out || nsteps < 1) return fail(c, TDGL_E_ARG, "need nsteps >= 1 and ms_out");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    const bool el = elec_on(c);
+    if (el && !c->tensor_built)
+        return fail(c, TDGL_E_STATE, "electrostatic term on but tensor not built");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    const int nev = c->scheme == TDGL_HEUN ? 2 : 1;
+    // events: per evaluation y_fwd, z, y_inv, update -> 5 markers
+    std::vector<hipEvent_t> ev((size_t)nsteps * nev * 5);
+    for (auto &e : ev) HIP_TRY(c, hipEventCreate(&e));
+    double sum[5] = {0, 0, 0, 0, 0};
+    int cnt[5] = {0, 0, 0, 0, 0};
+    hipError_t le = hipSuccess;
+    size_t k = 0;
+    const Geom &g = c->g;
+    for (int sidx = 0; sidx < nsteps && le == hipSuccess; ++sidx) {
+        for (int e = 0; e < nev && le == hipSuccess; ++e) {
+            void *A = c->P[c->cur], *B = c->P[1 - c->cur];
+            const void *Pin = e == 0 ? A : B;
+            const void *Pold = e == 0 ? nullptr : A;
+            void *Pout = e == 0 ? B : A;
+            hipEvent_t *E = &ev[k];
+            k += 5;
+            (void)hipEventRecord(E[0], c->stream);
+            if (el) {
+                le = launch_col(c->prec, g.my, false, c->S1, c->S2, g.hx, 3LL * g.nz,
+                                (long long)g.ny * g.hx, (long long)g.my * g.hx, g.hx, g.ny, g.my,
+                                tw(c), c->stream);
+                (void)hipEventRecord(E[1], c->stream);
+                if (le == hipSuccess) le = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), c->stream);
+                (void)hipEventRecord(E[2], c->stream);
+                if (le == hipSuccess)
+                    le = launch_col(c->prec, g.my, true, c->S2, c->S1, g.hx, 3LL * g.nz,
+                                    (long long)g.my * g.hx, (long long)g.ny * g.hx, g.hx, g.my,
+                                    g.ny, tw(c), c->stream);
+                (void)hipEventRecord(E[3], c->stream);
+            } else {
+                (void)hipEventRecord(E[1], c->stream);
+                (void)hipEventRecord(E[2], c->stream);
+                (void)hipEventRecord(E[3], c->stream);
+            }
+            if (le == hipSuccess)
+                le = enq_upd(c, UPD_STEP, Pin, Pold, Pout, e, c->terms, el, el, c->stream);
+            (void)hipEventRecord(E[4], c->stream);
+        }
+        if (c->scheme == TDGL_EULER) c->cur = 1 - c->cur;
+    }
+    (void)le;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    k = 0;
+    for (int sidx = 0; sidx < nsteps; ++sidx)
+        for (int e = 0; e < nev; ++e) {
+            hipEvent_t *E = &ev[k];
+            k += 5;
+            float ms;
+            if (el) {
+                for (int q = 0; q < 3; ++q) {
+                    (void)hipEventElapsedTime(&ms, E[q], E[q + 1]);
+                    sum[q] += ms;
+                    cnt[q]++;
+                }
+            }
+            (void)hipEventElapsedTime(&ms, E[3], E[4]);
+            sum[3 + e] += ms;
+            cnt[3 + e]++;
+        }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (le != hipSuccess) return fail(c, TDGL_E_HIP, "profile launch: %s", hipGetErrorString(le));
+    for (int q = 0; q < 5; ++q) ms_out[q] = cnt[q] ? sum[q] / cnt[q] : 0.0;
+    c->spec_valid = el;
     return TDGL_OK;
 }
 

@@ -44,10 +44,11 @@ __device__ __forceinline__ T landau_f(const T sq[3], const T *cf)
 }
 
 template <typename T, int M, int MODE>
-__global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
+__global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
 {
     constexpr int TPL = M / 8;
     constexpr int LEN = LinePad<M>::len;
+    constexpr int CPT = 2;                     // cells per thread, at most
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     T *hs = reinterpret_cast<T *>(smem_raw);   // [3][yt][nx], aliases the FFT scratch
@@ -62,6 +63,7 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
     const KParams<T> *kp = reinterpret_cast<const KParams<T> *>(a.kp);
     const bool material = coefz[8] != T(0);
     const unsigned terms = a.terms;
+    const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
 
     // line mapping of the x transforms
     const int l = tid / TPL, t = tid - l * TPL;
@@ -73,9 +75,11 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
     cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
     const IdxPad pad{};
 
-    // ---- 1. electrostatic field rows
+    // ---- prologue: issue every global load of the kernel up front
+    TwReg<T, M> tr;
+    if (a.elec_in || do_fx) twiddle_load(tr, tw, t);
+    cpx<T> v[8];
     if (a.elec_in) {
-        cpx<T> v[8];
         const cpx<T> *ra = S1 + (((long long)lc * nz + z) * ny + ya) * g.hx;
         const cpx<T> *rb = ra + g.hx;
 #pragma unroll
@@ -88,9 +92,64 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
                 A.y = T(0);
                 B.y = T(0);
             }
+            // Hermitian extension of two real rows packed as A + iB
             v[q] = k <= M / 2 ? cpx<T>{A.x - B.y, A.y + B.x} : cpx<T>{A.x + B.y, B.x - A.y};
         }
-        fft_line<T, M, true>(v, L, pad, t, tw, lact);
+    }
+    // z neighbours exist if in range (or periodic) and not vacuum
+    const T *coefzm = z > 0 ? coefz - NCOEF : (g.pz ? coefz + (long long)(nz - 1) * NCOEF : nullptr);
+    const T *coefzp = z < nz - 1 ? coefz + NCOEF : (g.pz ? coefz - (long long)(nz - 1) * NCOEF : nullptr);
+    const bool hzm = coefzm && coefzm[8] != T(0);
+    const bool hzp = coefzp && coefzp[8] != T(0);
+    const long long dzm = z > 0 ? -plane : (long long)(nz - 1) * plane;
+    const long long dzp = z < nz - 1 ? plane : -(long long)(nz - 1) * plane;
+    const T *Pold = reinterpret_cast<const T *>(a.P_old);
+    const bool need_nb = material && (terms & T_GRAD);
+    // per cell: centre, neighbours (-x +x -y +y -z +z; a missing neighbour
+    // holds the centre value, so its difference vanishes), old state
+    T cp[CPT][3], cn[CPT][6][3], co[CPT][3];
+    bool cok[CPT];
+    long long ccell[CPT];
+    int cyy[CPT], cx[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const int e = tid + i * nthr;
+        const int yy = e / nx, x = e - yy * nx, y = y0 + yy;
+        cok[i] = e < yt * nx && y < ny;
+        cyy[i] = yy;
+        cx[i] = x;
+        const long long cell = (long long)z * plane + (long long)y * nx + x;
+        ccell[i] = cell;
+        if (!cok[i]) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cp[i][c] = Pin[c * comp + cell];
+        if (need_nb) {
+            int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+            bool hxm = true, hxp = true, hym = true, hyp = true;
+            if (xm < 0) { if (g.px) xm += nx; else hxm = false; }
+            if (xp >= nx) { if (g.px) xp -= nx; else hxp = false; }
+            if (ym < 0) { if (g.py) ym += ny; else hym = false; }
+            if (yp >= ny) { if (g.py) yp -= ny; else hyp = false; }
+            const long long rowz = (long long)z * plane;
+            const long long nbc[6] = {rowz + (long long)y * nx + xm, rowz + (long long)y * nx + xp,
+                                      rowz + (long long)ym * nx + x, rowz + (long long)yp * nx + x,
+                                      cell + dzm, cell + dzp};
+            const bool nbh[6] = {hxm, hxp, hym, hyp, hzm, hzp};
+#pragma unroll
+            for (int d = 0; d < 6; ++d)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    cn[i][d][c] = nbh[d] ? Pin[c * comp + nbc[d]] : cp[i][c];
+        }
+        if (MODE == UPD_STEP && a.stage == 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) co[i][c] = Pold[c * comp + cell];
+        }
+    }
+
+    // ---- 1. electrostatic field rows (inverse x transform)
+    if (a.elec_in) {
+        fft_line<T, M, true>(v, L, pad, t, tr, lact);
         __syncthreads();
         if (lact) {
             T *ha = hs + ((long long)lc * yt + 2 * lp) * nx;
@@ -107,36 +166,16 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
     }
 
     // ---- 2. local terms and the update
-    const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const T dtau = kp->dtau;
-    const T *Pold = reinterpret_cast<const T *>(a.P_old);
     T *Pout = reinterpret_cast<T *>(a.P_out);
-    const T *coefzm = z > 0 ? coefz - NCOEF : (g.pz ? coefz + (long long)(nz - 1) * NCOEF : nullptr);
-    const T *coefzp = z < nz - 1 ? coefz + NCOEF : (g.pz ? coefz - (long long)(nz - 1) * NCOEF : nullptr);
-    const bool hzm = coefzm && coefzm[8] != T(0);
-    const bool hzp = coefzp && coefzp[8] != T(0);
-    const long long dzm = z > 0 ? -plane : (long long)(nz - 1) * plane;
-    const long long dzp = z < nz - 1 ? plane : -(long long)(nz - 1) * plane;
-
-    for (int e = tid; e < yt * nx; e += nthr) {
-        const int yy = e / nx, x = e - yy * nx, y = y0 + yy;
-        if (y >= ny) continue;
-        const long long cell = (long long)z * plane + (long long)y * nx + x;
-        T p[3] = {Pin[cell], Pin[comp + cell], Pin[2 * comp + cell]};
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        if (!cok[i]) continue;
+        const int yy = cyy[i], x = cx[i];
+        const long long cell = ccell[i];
+        const T *p = cp[i];
         T E[3] = {T(0), T(0), T(0)};
-        // neighbours
-        int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-        bool hxm = true, hxp = true, hym = true, hyp = true;
-        if (xm < 0) { if (g.px) xm += nx; else hxm = false; }
-        if (xp >= nx) { if (g.px) xp -= nx; else hxp = false; }
-        if (ym < 0) { if (g.py) ym += ny; else hym = false; }
-        if (yp >= ny) { if (g.py) yp -= ny; else hyp = false; }
-        const long long rowc = (long long)z * plane + (long long)y * nx;
-        const long long cxm = rowc + xm, cxp = rowc + xp;
-        const long long cym = (long long)z * plane + (long long)ym * nx + x;
-        const long long cyp = (long long)z * plane + (long long)yp * nx + x;
-        const long long czm = cell + dzm, czp = cell + dzp;
         T sq[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) sq[c] = p[c] * p[c];
@@ -154,21 +193,16 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
             if (terms & T_GRAD) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const T *Pc = Pin + c * comp;
                     const T pc = p[c];
-                    T lx = T(0), ly = T(0), lz = T(0);
-                    if (hxm) lx += Pc[cxm] - pc;
-                    if (hxp) lx += Pc[cxp] - pc;
-                    if (hym) ly += Pc[cym] - pc;
-                    if (hyp) ly += Pc[cyp] - pc;
-                    if (hzm) lz += Pc[czm] - pc;
-                    if (hzp) lz += Pc[czp] - pc;
+                    const T lx = (cn[i][0][c] - pc) + (cn[i][1][c] - pc);
+                    const T ly = (cn[i][2][c] - pc) + (cn[i][3][c] - pc);
+                    const T lz = (cn[i][4][c] - pc) + (cn[i][5][c] - pc);
                     E[c] += kp->gh2[c][0] * lx + kp->gh2[c][1] * ly + kp->gh2[c][2] * lz;
                     if (MODE == UPD_ENERGY) {
                         // edges towards +x, +y, +z, each counted once
-                        if (hxp) { const T d = Pc[cxp] - pc; fg += T(0.5) * kp->gh2[c][0] * d * d; }
-                        if (hyp) { const T d = Pc[cyp] - pc; fg += T(0.5) * kp->gh2[c][1] * d * d; }
-                        if (hzp) { const T d = Pc[czp] - pc; fg += T(0.5) * kp->gh2[c][2] * d * d; }
+                        const T dx_ = cn[i][1][c] - pc, dy_ = cn[i][3][c] - pc, dz_ = cn[i][5][c] - pc;
+                        fg += T(0.5) * (kp->gh2[c][0] * dx_ * dx_ + kp->gh2[c][1] * dy_ * dy_ +
+                                        kp->gh2[c][2] * dz_ * dz_);
                     }
                 }
             }
@@ -187,7 +221,7 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
             for (int c = 0; c < 3; ++c) {
                 if (!material) o[c] = T(0);
                 else if (a.stage == 0) o[c] = p[c] + dtau * E[c];
-                else o[c] = T(0.5) * (Pold[c * comp + cell] + p[c]) + T(0.5) * dtau * E[c];
+                else o[c] = T(0.5) * (co[i][c] + p[c]) + T(0.5) * dtau * E[c];
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -219,7 +253,6 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
     // ---- 3. x spectrum of the new rows
     if (do_fx) {
         __syncthreads();
-        cpx<T> v[8];
         const T *ha = hs + ((long long)lc * yt + 2 * lp) * nx;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -229,7 +262,7 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
             v[q] = {av, bv};
         }
         __syncthreads();
-        fft_line<T, M, false>(v, L, pad, t, tw, lact);
+        fft_line<T, M, false>(v, L, pad, t, tr, lact);
         __syncthreads();
         if (lact) {
 #pragma unroll
@@ -253,9 +286,9 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
         const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            double s = acc[k];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-            acc[k] = s;
+            double sacc = acc[k];
+            for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
+            acc[k] = sacc;
         }
         if (lane == 0) {
 #pragma unroll
@@ -263,25 +296,24 @@ __global__ void k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
         }
         __syncthreads();
         if (tid < 7) {
-            double s = 0.0;
+            double sacc = 0.0;
             const int nw = (nthr + 63) / 64;
-            for (int w = 0; w < nw; ++w) s += red[w * 8 + tid];
-            a.partials[((long long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = s;
+            for (int w = 0; w < nw; ++w) sacc += red[w * 8 + tid];
+            a.partials[((long long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = sacc;
         }
     }
 }
 
-// rows per work-group: even, about 256 threads per group for the x transforms
+// rows per work-group: even, about one cell per thread of a 256-thread group
+// (enough groups in flight to hide memory latency on small grids)
 int update_rows_per_block(int prec, const Geom &g)
 {
     (void)prec;
-    const int tpl = g.mx / 8;
-    int lines = 256 / tpl;
-    if (lines < 3) lines = 3;
-    int yt = 2 * (lines / 3);
-    if (yt < 2) yt = 2;
+    int yt = 2;
+    while ((yt + 2) * g.nx <= 256) yt += 2;
     const int ny_even = g.ny + (g.ny & 1);
     if (yt > ny_even) yt = ny_even;
+    if (yt < 2) yt = 2;
     return yt;
 }
 
@@ -292,13 +324,14 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
     constexpr int TPL = M / 8;
     const int nlines = 3 * (a.yt / 2);
     int nthr = nlines * TPL;
-    if (nthr < 64) nthr = 64;
+    if (nthr < 256) nthr = 256;
+    if (nthr < (a.yt * g.nx + 1) / 2) nthr = (a.yt * g.nx + 1) / 2;   // <= 2 cells per thread
     nthr = (nthr + 63) / 64 * 64;
     size_t shm = (size_t)nlines * LinePad<M>::len * sizeof(cpx<T>);
     const size_t hs_bytes = (size_t)3 * a.yt * g.nx * sizeof(T);
     if (shm < hs_bytes) shm = hs_bytes;
     if (shm < 16 * 8 * sizeof(double)) shm = 16 * 8 * sizeof(double);
-    if (shm > 65536 || nthr > 1024) return hipErrorInvalidConfiguration;
+    if (shm > 65536 || nthr > 512) return hipErrorInvalidConfiguration;
     dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
     hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, a, g,
