@@ -69,7 +69,7 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def run_gpu(cfg, precision, steps, warmup, profile_steps):
+def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0):
     import numpy as np
     import torch
 
@@ -78,7 +78,10 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps):
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     t0 = time.time()
-    ctx = T.Context(cfg, precision, stream=stream)
+    ctx = T.Context(cfg, precision, stream=stream, build_tensor=False)
+    T.tdgl_set_fft_path(ctx.ctx, fft_path)
+    T.tdgl_set_update_rows(ctx.ctx, rows)
+    T.tdgl_build_tensor(ctx.ctx, cfg["mimg"])
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     P0 = I.initial_P(cfg, 0, np.float32 if precision == T.TDGL_FP32 else np.float64)
@@ -98,8 +101,10 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps):
     prof = T.tdgl_profile_step(ctx.ctx, profile_steps) if profile_steps else None
     F, meanP = ctx.energies()
     dims = ctx.dims
+    fused = T.tdgl_get_fft_path(ctx.ctx)
     ctx.close()
-    return dict(ms=ms, wall=wall, setup_s=setup_s, prof=prof, dims=dims, F=F, meanP=meanP)
+    return dict(ms=ms, wall=wall, setup_s=setup_s, prof=prof, dims=dims, F=F, meanP=meanP,
+                fused=fused)
 
 
 def cpu_baseline(cfg, nsteps):
@@ -135,6 +140,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fft-path", type=int, default=0, help="0 auto (fused if it fits), 1 three passes")
+    ap.add_argument("--rows", type=int, default=0, help="update-kernel rows per group (0 auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (each simulation fits one "
@@ -152,11 +159,12 @@ def main():
     cfg = I.config("c2")
     ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     log("fp32 run: %d warmup + %d timed Heun steps" % (args.warmup, args.steps))
-    r32 = run_gpu(cfg, T.TDGL_FP32, args.steps, args.warmup, args.profile_steps)
+    r32 = run_gpu(cfg, T.TDGL_FP32, args.steps, args.warmup, args.profile_steps,
+                  args.fft_path, args.rows)
     ms_step = r32["ms"] / args.steps
     value = ncell * args.steps / (r32["ms"] / 1e3)
-    log("fp32: %.4f ms/step, %.3e cell-steps/s (wall %.3f s, setup %.2f s)"
-        % (ms_step, value, r32["wall"], r32["setup_s"]))
+    log("fp32: %.4f ms/step, %.3e cell-steps/s (wall %.3f s, setup %.2f s, fused=%d)"
+        % (ms_step, value, r32["wall"], r32["setup_s"], r32["fused"]))
 
     if r32["prof"] is None:
         print(json.dumps({"metric": "TDGL cell-steps/s", "value": value, "unit": "cell-steps/s",

@@ -150,9 +150,10 @@ tdgl_status tdgl_set_gradient(tdgl_ctx *ctx, double G11, double G12, double G44,
  * the duration of the call.  mimg in [0, 64]. */
 tdgl_status tdgl_build_tensor(tdgl_ctx *ctx, int mimg);
 
-/* Copy the tensor octant spectrum ([6][mz/2+1][my/2+1][hx], component order
- * xx yy zz xy xz yz, converted to double) to host memory dst of count
- * doubles.  Synchronising.  For tests and inspection. */
+/* Copy the tensor octant spectrum ([hx][6][mz/2+1][my/2+1], component order
+ * xx yy zz xy xz yz, -kappa/(mx my mz) folded in, converted to double) to
+ * host memory dst of count doubles.  Synchronising.  For tests and
+ * inspection. */
 tdgl_status tdgl_get_tensor_spectrum(tdgl_ctx *ctx, double *dst, size_t count);
 
 /* Temperature (K) for the Table 1 coefficient forms. */
@@ -171,6 +172,21 @@ tdgl_status tdgl_set_integrator(tdgl_ctx *ctx, int scheme, double dtau);
 /* Number of steps captured per HIP graph by tdgl_step (default 64; 0 runs
  * plain stream launches). */
 tdgl_status tdgl_set_graph_chunk(tdgl_ctx *ctx, int steps);
+
+/* FFT pass layout: path 0 (default) fuses the y pass, the z pass with the
+ * tensor multiply and the inverse y pass into one kernel per kx plane when
+ * that plane fits in one work-group's LDS, and uses three kernels
+ * otherwise; path 1 always uses the three kernels.  Results agree to
+ * rounding.  tdgl_get_fft_path reports whether the fused kernel is in use
+ * (known after the first call that touches the device). */
+tdgl_status tdgl_set_fft_path(tdgl_ctx *ctx, int path);
+tdgl_status tdgl_get_fft_path(const tdgl_ctx *ctx, int *fused);
+
+/* Rows of one z layer handled by one work-group of the update kernel (even,
+ * 2..64; 0 restores the built-in choice).  A tuning knob: results do not
+ * depend on it.  Launches that would exceed the device's work-group limits
+ * fail with TDGL_E_HIP at the next step. */
+tdgl_status tdgl_set_update_rows(tdgl_ctx *ctx, int rows);
 
 /* Load P (C/m^2, [3][nz][ny][nx]) from src: host memory if src_on_device is
  * 0, device memory otherwise; src_precision TDGL_FP32 or TDGL_FP64 (converted
@@ -211,9 +227,10 @@ tdgl_status tdgl_get_reduced(const tdgl_ctx *ctx, double *coef, double scal[8]);
 
 /* Advance nsteps time steps with plain stream launches and time every kernel
  * with HIP events recorded on the context's stream around it.  ms_out[5]
- * receives the mean duration (ms) per launch of: y forward pass, z pass
- * with tensor multiply, y inverse pass, update (predictor / Euler stage),
- * update (Heun corrector); 0 for kernels that did not run.  Synchronising.
+ * receives the mean duration (ms) per launch of: y forward pass (or the
+ * fused y-z-y plane kernel), z pass with tensor multiply, y inverse pass,
+ * update (predictor / Euler stage), update (Heun corrector); 0 for kernels
+ * that did not run.  Synchronising.
  * For benchmarks and profiling; the state advances like tdgl_step. */
 tdgl_status tdgl_profile_step(tdgl_ctx *ctx, int nsteps, double ms_out[5]);
 

@@ -53,7 +53,7 @@ def lib():
         L.orc_offset_table.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_uint,
                                        ctypes.c_int, dp, dp, dp, dp]
         L.orc_offset_entry.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_uint,
-                                       ctypes.c_int, dp, dp, dp, dp,
+                                       ctypes.c_int, dp, dp, dp,
                                        ctypes.POINTER(ctypes.c_int), dp]
         L.orc_newell_f.argtypes = [ctypes.c_double] * 3
         L.orc_newell_f.restype = ctypes.c_double

@@ -78,6 +78,9 @@ _SIGS = {
     "tdgl_energies": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_get_reduced": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_profile_step": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
+    "tdgl_set_fft_path": ([_ctx_p, c_int], c_int),
+    "tdgl_get_fft_path": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
+    "tdgl_set_update_rows": ([_ctx_p, c_int], c_int),
     "tdgl_sync": ([_ctx_p], c_int),
 }
 EXPORTED = tuple(_SIGS)
@@ -166,11 +169,26 @@ def tdgl_build_tensor(ctx, mimg: int):
 
 
 def tdgl_get_tensor_spectrum(ctx):
+    """Octant spectrum as [6][mz/2+1][my/2+1][hx] (the device stores it kx-major)."""
     nx, ny, nz, mx, my, mz, hx = tdgl_get_dims(ctx)
-    out = np.zeros((6, mz // 2 + 1, my // 2 + 1, hx))
+    out = np.zeros((hx, 6, mz // 2 + 1, my // 2 + 1))
     _check(ctx, lib().tdgl_get_tensor_spectrum(
         ctx, out.ctypes.data_as(ctypes.POINTER(c_double)), out.size))
-    return out
+    return np.ascontiguousarray(out.transpose(1, 2, 3, 0))
+
+
+def tdgl_set_fft_path(ctx, path: int):
+    _check(ctx, lib().tdgl_set_fft_path(ctx, path))
+
+
+def tdgl_set_update_rows(ctx, rows: int):
+    _check(ctx, lib().tdgl_set_update_rows(ctx, rows))
+
+
+def tdgl_get_fft_path(ctx):
+    f = c_int()
+    _check(ctx, lib().tdgl_get_fft_path(ctx, ctypes.byref(f)))
+    return f.value
 
 
 def tdgl_set_temperature(ctx, T):

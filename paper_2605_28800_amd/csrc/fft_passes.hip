@@ -3,31 +3,45 @@
 // intermediate operations; eq 6 as a zero-padded convolution with the
 // cell-averaged dipolar tensor).
 //
-//   k_fx   : real rows -> half spectra along x (two rows per complex line).
-//            Zero padding beyond n_in is implicit.
-//   k_col  : complex FFT along a strided axis for a tile of adjacent columns
-//            (y passes, tensor y/z passes).  Reads n_in points, writes n_out.
-//   k_zmul : per (kx, ky) column: forward z FFT of the three components,
-//            E^_i = sum_j N~_ij P^_j with the octant-stored real tensor
-//            spectrum, inverse z FFT, cropped to the physical layers.
+// Spectra are stored kx-major: element (kx, c, z, y) of the x-transformed
+// field at ((kx*3 + c)*nz + z)*L + y with L = ny (physical rows) or my
+// (after the y pass), so one kx plane of all components is contiguous.
+//
+//   k_fx    : real rows -> half spectra along x (two rows per complex line),
+//             zero padding beyond n_in implicit; output written kx-major
+//             through an LDS transpose.
+//   k_row   : complex FFT of contiguous lines (y passes; tensor y pass).
+//   k_col   : complex FFT along a strided axis for tiles of adjacent columns
+//             (tensor z pass).
+//   k_zmul  : per (kx, ky) column: forward z FFT of the three components,
+//             E^_i = sum_j N~_ij P^_j with the octant-stored real tensor
+//             spectrum, inverse z FFT, cropped to the physical layers.
+//   k_plane : the three passes above fused for one kx plane held in LDS.
+#include <type_traits>
+
 #include "fft_core.h"
 #include "internal.h"
 
 namespace tdgl {
 
 // ---------------------------------------------------------------- x pass
+// Rows r of n_in reals (stride in_stride) -> out[k * out_kstride + r],
+// k = 0..M/2.  Each work-group transforms 2*lpw consecutive rows.
 template <typename T, int M>
 __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long long in_stride,
-                     cpx<T> *__restrict__ out, long long out_stride,
+                     cpx<T> *__restrict__ out, long long out_kstride,
                      const cpx<T> *__restrict__ tw, int lpw)
 {
     constexpr int TPL = M / 8;
     constexpr int LEN = LinePad<M>::len;
+    constexpr int H = M / 2 + 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
-    const int tid = threadIdx.x;
+    cpx<T> *stg = lds + lpw * LEN;                  // [H][2*lpw] output staging
+    const int tid = threadIdx.x, nthr = blockDim.x;
     const int l = tid / TPL, t = tid - l * TPL;
-    const long long ra = ((long long)blockIdx.x * lpw + l) * 2;
+    const long long r0 = (long long)blockIdx.x * 2 * lpw;
+    const long long ra = r0 + 2 * l;
     const long long rb = ra + 1;
     const bool act = (l < lpw) && (ra < nrows);
     const bool hasb = act && (rb < nrows);
@@ -42,7 +56,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
         if (hasb && x < n_in) bv = in[rb * in_stride + x];
         v[q] = {av, bv};
     }
-    cpx<T> *L = lds + l * LEN;
+    cpx<T> *L = lds + (l < lpw ? l : 0) * LEN;
     const IdxPad pad{};
     fft_line<T, M, false>(v, L, pad, t, tr, act);
     __syncthreads();
@@ -51,22 +65,60 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
         for (int q = 0; q < 8; ++q) L[pad(t + q * TPL)] = v[q];
     }
     __syncthreads();
-    if (act) {
+    if (l < lpw) {
         for (int k = t; k <= M / 2; k += TPL) {
             const cpx<T> zk = L[pad(k)], zm = L[pad((M - k) & (M - 1))];
             // A = (Z[k] + conj Z[M-k]) / 2,  B = (Z[k] - conj Z[M-k]) / (2i)
-            out[ra * out_stride + k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-            if (hasb) out[rb * out_stride + k] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+            stg[k * 2 * lpw + 2 * l] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+            stg[k * 2 * lpw + 2 * l + 1] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
         }
+    }
+    __syncthreads();
+    const int rows_here = (int)((nrows - r0) < 2 * lpw ? (nrows - r0) : 2 * lpw);
+    for (int e = tid; e < H * 2 * lpw; e += nthr) {
+        const int k = e / (2 * lpw), rl = e - k * 2 * lpw;
+        if (rl < rows_here) out[k * out_kstride + r0 + rl] = stg[e];
+    }
+}
+
+// ---------------------------------------------------------- row pass
+// Line r: n_in points at in + r*in_stride, n_out points to out + r*out_stride.
+// In-place use is safe (each thread stores exactly the positions it loaded).
+template <typename T, int M, bool INV>
+__global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long in_stride,
+                      long long out_stride, int n_in, int n_out, const cpx<T> *__restrict__ tw,
+                      int lpw)
+{
+    constexpr int TPL = M / 8;
+    constexpr int LEN = LinePad<M>::len;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int l = tid / TPL, t = tid - l * TPL;
+    const long long line = (long long)blockIdx.x * lpw + l;
+    const bool act = l < lpw && line < nlines;
+    TwReg<T, M> tr;
+    twiddle_load(tr, tw, t);
+    const cpx<T> *src = in + (act ? line : 0) * in_stride;
+    cpx<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = t + q * TPL;
+        v[q] = (act && e < n_in) ? src[e] : cpx<T>{T(0), T(0)};
+    }
+    fft_line<T, M, INV>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr, act);
+    cpx<T> *dst = out + (act ? line : 0) * out_stride;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = t + q * TPL;
+        if (act && e < n_out) dst[e] = v[q];
     }
 }
 
 // ------------------------------------------------------------ column pass
 // Element e of column col in batch b sits at  b*bstride + e*lstride + col.
-// Columns of all batches are numbered j = b*C + col and tiled CT at a time,
-// so no tile is left partly empty when C is not a multiple of CT.
-// In-place use (in == out) is safe: every thread stores exactly the
-// positions it loaded.
+// Columns of all batches are numbered j = b*C + col and tiled CT at a time.
+// In-place use (in == out) is safe.
 template <typename T, int M, bool INV>
 __global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, long long ncols, int CT,
                       long long in_bstride, long long out_bstride, long long lstride, int n_in,
@@ -99,20 +151,52 @@ __global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, long long ncol
     }
 }
 
-// ------------------------------------------------- z pass with multiply
-// S: [3][nz][my][hx] complex (in place).  Nt: [6][MZ/2+1][my/2+1][hx] real,
-// components xx yy zz xy xz yz; xy is odd in ky, xz odd in kz, yz odd in
-// both, so entries outside the stored octant take the mirrored value with
-// the corresponding sign.
-// FP64 blocks stay at <= 512 threads so each wave may hold up to 256 VGPRs
+// ---------------------------------------------------- tensor row fetch
+// Row c of the interaction tensor at (kx, ky, kz) from the octant store
+// Nt[kx][q][kz'][ky'] (q: xx yy zz xy xz yz; kz' <= mz/2, ky' <= my/2).
+// xy is odd in ky, xz odd in kz, yz odd in both.
+struct TensorRow {
+    int i0, i1, i2;    // components (c,x) (c,y) (c,z) of row c
+    __device__ explicit TensorRow(int c, int)
+        : i0(c == 0 ? 0 : (c == 1 ? 3 : 4)), i1(c == 0 ? 3 : (c == 1 ? 1 : 5)),
+          i2(c == 0 ? 4 : (c == 1 ? 5 : 2)) {}
+};
+
 template <typename T>
-struct ZmulMaxThreads {
+__device__ __forceinline__ T odd_sign(int comp, T sy, T sz)
+{
+    return comp == 3 ? sy : (comp == 4 ? sz : (comp == 5 ? sy * sz : T(1)));
+}
+
+template <typename T>
+__device__ __forceinline__ void tensor_row(const T *__restrict__ Nt, int kx, int ky, int kz,
+                                           int my, int mz, const TensorRow &r, T &n0, T &n1,
+                                           T &n2)
+{
+    const int hy = my / 2 + 1, hz = mz / 2 + 1;
+    const int kyo = ky <= my / 2 ? ky : my - ky;
+    const int kzo = kz <= mz / 2 ? kz : mz - kz;
+    const T sy = ky > my / 2 ? T(-1) : T(1);
+    const T sz = kz > mz / 2 ? T(-1) : T(1);
+    const long long qs = (long long)hz * hy;
+    const T *b = Nt + (long long)kx * 6 * qs + (long long)kzo * hy + kyo;
+    n0 = b[r.i0 * qs] * odd_sign(r.i0, sy, sz);
+    n1 = b[r.i1 * qs] * odd_sign(r.i1, sy, sz);
+    n2 = b[r.i2 * qs] * odd_sign(r.i2, sy, sz);
+}
+
+// ------------------------------------------------- z pass with multiply
+// S: [hx][3][nz][my] complex (in place); work-group = (kx, tile of CT ky
+// columns) x 3 components.
+template <typename T>
+struct ZmulMaxThreads {   // FP64 groups stay small so a wave may hold 256 VGPRs
     static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
 };
 
 template <typename T, int MZ>
-__global__ void __launch_bounds__(ZmulMaxThreads<T>::v) k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int hx, int CT,
-                       const cpx<T> *__restrict__ tw)
+__global__ void __launch_bounds__(ZmulMaxThreads<T>::v)
+    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int CT,
+           const cpx<T> *__restrict__ tw)
 {
     constexpr int TPL = MZ / 8;
     extern __shared__ unsigned char smem_raw[];
@@ -121,42 +205,24 @@ __global__ void __launch_bounds__(ZmulMaxThreads<T>::v) k_zmul(cpx<T> *S, const 
     const int cc = tid % CT;
     const int t = (tid / CT) % TPL;
     const int c = tid / (CT * TPL);
-    const long long plane = (long long)my * hx;
-    // (ky, kx) columns are contiguous within a (component, z) plane
-    const long long j = (long long)blockIdx.x * CT + cc;
-    const bool act = j < plane;
-    const int ky = act ? (int)(j / hx) : 0;
-    const int kx = act ? (int)(j - (long long)ky * hx) : 0;
-    cpx<T> *col = S + (long long)c * nz * plane + (act ? j : 0);
+    const int kx = blockIdx.y;
+    const int ky = blockIdx.x * CT + cc;
+    const bool act = ky < my;
+    const long long zst = my;
+    cpx<T> *col = S + ((long long)kx * 3 + c) * nz * zst + (act ? ky : 0);
     TwReg<T, MZ> tr;
     twiddle_load(tr, tw, t);
-    // tensor row c at this thread's (kx, ky, kz) points, fetched up front
-    const int hy = my / 2;
-    const int kyo = ky <= hy ? ky : my - ky;
-    const T sy = ky > hy ? T(-1) : T(1);
-    const long long s6 = (long long)(MZ / 2 + 1) * (hy + 1) * hx;
-    const int i0 = c == 0 ? 0 : (c == 1 ? 3 : 4);   // (c,x) (c,y) (c,z)
-    const int i1 = c == 0 ? 3 : (c == 1 ? 1 : 5);
-    const int i2 = c == 0 ? 4 : (c == 1 ? 5 : 2);
-    auto sgn = [&](int comp, T sz) -> T {
-        return comp == 3 ? sy : (comp == 4 ? sz : (comp == 5 ? sy * sz : T(1)));
-    };
+    const TensorRow trow(c, 0);
+    const int kyc = act ? ky : 0;
     T nrow[8][3];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int kz = t + q * TPL;
-        const int kzo = kz <= MZ / 2 ? kz : MZ - kz;
-        const T sz = kz > MZ / 2 ? T(-1) : T(1);
-        const T *nb = Nt + ((long long)kzo * (hy + 1) + kyo) * hx + kx;
-        nrow[q][0] = act ? nb[i0 * s6] * sgn(i0, sz) : T(0);
-        nrow[q][1] = act ? nb[i1 * s6] * sgn(i1, sz) : T(0);
-        nrow[q][2] = act ? nb[i2 * s6] * sgn(i2, sz) : T(0);
-    }
+    for (int q = 0; q < 8; ++q)
+        tensor_row(Nt, kx, kyc, t + q * TPL, my, MZ, trow, nrow[q][0], nrow[q][1], nrow[q][2]);
     cpx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
-        v[q] = (act && z < nz) ? col[(long long)z * plane] : cpx<T>{T(0), T(0)};
+        v[q] = (act && z < nz) ? col[(long long)z * zst] : cpx<T>{T(0), T(0)};
     }
     cpx<T> *L = lds + c * MZ * CT + cc;
     fft_line<T, MZ, false>(v, L, IdxStride{CT}, t, tr, act);
@@ -182,7 +248,132 @@ __global__ void __launch_bounds__(ZmulMaxThreads<T>::v) k_zmul(cpx<T> *S, const 
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
-        if (act && z < nz) col[(long long)z * plane] = v[q];
+        if (act && z < nz) col[(long long)z * zst] = v[q];
+    }
+}
+
+// ----------------------------------------------------- fused plane pass
+// One work-group per kx.  The plane [3][nz][MY] (lines padded one slot per 8)
+// sits in LDS: y transforms of all (c, z) lines, then the z pass with the
+// tensor multiply in chunks of CK ky columns (scratch [3][MZ][CK]), then the
+// inverse y transforms.  S1: [hx][3][nz][ny] in/out (in place).
+template <typename T, int MY, int MZ>
+struct PlaneCfg {
+    // FP64 groups use at most 384 threads, leaving 256 VGPRs per wave
+    static constexpr int CAP = sizeof(T) == 8 ? 384 : 768;
+    static constexpr int TPLY = MY / 8, TPLZ = MZ / 8;
+    static constexpr int CK = (3 * MY * TPLZ <= CAP) ? MY : CAP / (3 * TPLZ);
+    static constexpr int NTHR = 3 * CK * TPLZ;                 // threads per group
+    static constexpr int YROUND = NTHR / TPLY;                 // y lines per round
+    static constexpr int LINE = LinePad<MY>::len;
+};
+
+template <typename T, int MY, int MZ>
+size_t plane_lds_bytes(int nz)
+{
+    using C = PlaneCfg<T, MY, MZ>;
+    return (size_t)(3 * nz * C::LINE + 3 * MZ * C::CK) * sizeof(cpx<T>);
+}
+
+template <typename T, int MY, int MZ>
+__global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
+    k_plane(cpx<T> *S1, const T *__restrict__ Nt, int ny, int nz, const cpx<T> *__restrict__ twy,
+            const cpx<T> *__restrict__ twz)
+{
+    using C = PlaneCfg<T, MY, MZ>;
+    constexpr int TPLY = C::TPLY, TPLZ = C::TPLZ, CK = C::CK, LINE = C::LINE;
+    static_assert(C::YROUND >= 1 && C::NTHR <= 1024, "plane configuration");
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *pl = reinterpret_cast<cpx<T> *>(smem_raw);        // [3*nz][LINE]
+    cpx<T> *zs = pl + 3 * nz * LINE;                            // [3][MZ][CK]
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x;
+    const IdxPad pad{};
+    const int nlines = 3 * nz;
+    cpx<T> *gplane = S1 + (long long)kx * nlines * ny;
+
+    // y-pass roles
+    const int ly = tid / TPLY, ty = tid - ly * TPLY;
+    TwReg<T, MY> twy_r;
+    twiddle_load(twy_r, twy, ty);
+    // z-pass roles
+    const int cc = tid % CK, tz = (tid / CK) % TPLZ, cz = tid / (CK * TPLZ);
+    TwReg<T, MZ> twz_r;
+    twiddle_load(twz_r, twz, tz);
+
+    // load the plane (rows y >= ny are zero padding)
+    for (int e = tid; e < nlines * MY; e += C::NTHR) {
+        const int line = e / MY, y = e - line * MY;
+        pl[line * LINE + pad(y)] = y < ny ? gplane[(long long)line * ny + y] : cpx<T>{T(0), T(0)};
+    }
+
+    auto ypass = [&](auto inv_tag) {
+        constexpr bool INV = decltype(inv_tag)::value;
+        for (int r0 = 0; r0 < nlines; r0 += C::YROUND) {
+            const int line = r0 + ly;
+            const bool act = line < nlines;
+            cpx<T> *L = pl + (act ? line : 0) * LINE;
+            __syncthreads();
+            cpx<T> v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = act ? L[pad(ty + q * TPLY)] : cpx<T>{T(0), T(0)};
+            __syncthreads();
+            fft_line<T, MY, INV>(v, L, pad, ty, twy_r, act);
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) L[pad(ty + q * TPLY)] = v[q];
+            }
+        }
+    };
+    ypass(std::false_type{});
+
+    // z pass with the tensor multiply, CK ky columns at a time
+    for (int ky0 = 0; ky0 < MY; ky0 += CK) {
+        const int ky = ky0 + cc;
+        const TensorRow trow(cz, 0);
+        T nrow[8][3];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            tensor_row(Nt, kx, ky, tz + q * TPLZ, MY, MZ, trow, nrow[q][0], nrow[q][1], nrow[q][2]);
+        __syncthreads();
+        cpx<T> v[8];
+        const cpx<T> *colp = pl + (cz * nz) * LINE + pad(ky);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int z = tz + q * TPLZ;
+            v[q] = z < nz ? colp[z * LINE] : cpx<T>{T(0), T(0)};
+        }
+        cpx<T> *L = zs + cz * MZ * CK + cc;
+        fft_line<T, MZ, false>(v, L, IdxStride{CK}, tz, twz_r, true);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) L[(tz + q * TPLZ) * CK] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kz = tz + q * TPLZ;
+            const cpx<T> p0 = zs[(0 * MZ + kz) * CK + cc];
+            const cpx<T> p1 = zs[(1 * MZ + kz) * CK + cc];
+            const cpx<T> p2 = zs[(2 * MZ + kz) * CK + cc];
+            const T n0 = nrow[q][0], n1 = nrow[q][1], n2 = nrow[q][2];
+            v[q] = {n0 * p0.x + n1 * p1.x + n2 * p2.x, n0 * p0.y + n1 * p1.y + n2 * p2.y};
+        }
+        __syncthreads();
+        fft_line<T, MZ, true>(v, L, IdxStride{CK}, tz, twz_r, true);
+        cpx<T> *colw = pl + (cz * nz) * LINE + pad(ky);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int z = tz + q * TPLZ;
+            if (z < nz) colw[z * LINE] = v[q];
+        }
+    }
+
+    ypass(std::true_type{});
+    __syncthreads();
+    for (int e = tid; e < nlines * ny; e += C::NTHR) {
+        const int line = e / ny, y = e - line * ny;
+        gplane[e] = pl[line * LINE + pad(y)];
     }
 }
 
@@ -202,30 +393,65 @@ __global__ void __launch_bounds__(ZmulMaxThreads<T>::v) k_zmul(cpx<T> *S, const 
 
 template <typename T, int M>
 static hipError_t fx_impl(const void *in, long long nrows, int n_in, long long in_stride,
-                          void *out, long long out_stride, const void *tw, hipStream_t s)
+                          void *out, long long out_kstride, const void *tw, hipStream_t s)
 {
     constexpr int TPL = M / 8;
     const int lpw = TPL >= 256 ? 1 : 256 / TPL;
     const long long nlines = (nrows + 1) / 2;
     const long long blocks = (nlines + lpw - 1) / lpw;
     if (blocks <= 0) return hipSuccess;
-    const size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
+    const size_t shm = ((size_t)lpw * LinePad<M>::len + (size_t)(M / 2 + 1) * 2 * lpw) *
+                       sizeof(cpx<T>);
     hipLaunchKernelGGL((k_fx<T, M>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
-                       (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_stride,
+                       (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_kstride,
                        (const cpx<T> *)tw + M, lpw);
     return hipGetLastError();
 }
 
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
-                     long long in_stride, void *out, long long out_stride, const void *tw,
+                     long long in_stride, void *out, long long out_kstride, const void *tw,
                      hipStream_t s)
 {
     if (prec == PREC_F32) {
         TDGL_LEN_SWITCH(M, return (fx_impl<float, LEN_>(in, nrows, n_in, in_stride, out,
-                                                         out_stride, tw, s)))
+                                                         out_kstride, tw, s)))
     } else {
         TDGL_LEN_SWITCH(M, return (fx_impl<double, LEN_>(in, nrows, n_in, in_stride, out,
-                                                          out_stride, tw, s)))
+                                                          out_kstride, tw, s)))
+    }
+}
+
+template <typename T, int M>
+static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines,
+                           long long in_stride, long long out_stride, int n_in, int n_out,
+                           const void *tw, hipStream_t s)
+{
+    constexpr int TPL = M / 8;
+    const int lpw = TPL >= 256 ? 1 : 256 / TPL;
+    const long long blocks = (nlines + lpw - 1) / lpw;
+    if (blocks <= 0) return hipSuccess;
+    const size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
+    if (inv)
+        hipLaunchKernelGGL((k_row<T, M, true>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
+                           (const cpx<T> *)in, (cpx<T> *)out, nlines, in_stride, out_stride,
+                           n_in, n_out, (const cpx<T> *)tw + M, lpw);
+    else
+        hipLaunchKernelGGL((k_row<T, M, false>), dim3((unsigned)blocks), dim3(lpw * TPL), shm,
+                           s, (const cpx<T> *)in, (cpx<T> *)out, nlines, in_stride, out_stride,
+                           n_in, n_out, (const cpx<T> *)tw + M, lpw);
+    return hipGetLastError();
+}
+
+hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long long nlines,
+                      long long in_stride, long long out_stride, int n_in, int n_out,
+                      const void *tw, hipStream_t s)
+{
+    if (prec == PREC_F32) {
+        TDGL_LEN_SWITCH(M, return (row_impl<float, LEN_>(inv, in, out, nlines, in_stride,
+                                                          out_stride, n_in, n_out, tw, s)))
+    } else {
+        TDGL_LEN_SWITCH(M, return (row_impl<double, LEN_>(inv, in, out, nlines, in_stride,
+                                                           out_stride, n_in, n_out, tw, s)))
     }
 }
 
@@ -288,12 +514,11 @@ static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *
     while (ct > 1 && (3 * ct * TPL > ZmulMaxThreads<T>::v ||
                       (size_t)3 * ct * MZ * sizeof(cpx<T>) > 65536))
         ct /= 2;
-    const long long ncols = (long long)g.my * g.hx;
-    const long long gx = (ncols + ct - 1) / ct;
+    const int gx = (g.my + ct - 1) / ct;
+    if (g.hx > 65535) return hipErrorInvalidValue;
     const size_t shm = (size_t)3 * ct * MZ * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3((unsigned)gx), dim3(3 * ct * TPL), shm, s,
-                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.hx, ct,
-                       (const cpx<T> *)tw + MZ);
+    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx), dim3(3 * ct * TPL), shm, s,
+                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, ct, (const cpx<T> *)tw + MZ);
     return hipGetLastError();
 }
 
@@ -304,6 +529,59 @@ hipError_t launch_zmul(int prec, const Geom &g, void *S, const void *Nt, const v
         TDGL_LEN_SWITCH(g.mz, return (zmul_impl<float, LEN_>(g, S, Nt, tw, s)))
     } else {
         TDGL_LEN_SWITCH(g.mz, return (zmul_impl<double, LEN_>(g, S, Nt, tw, s)))
+    }
+}
+
+// ---- plane path: instantiated for my in 8..256 and mz in 8..128
+template <typename T, int MY, int MZ>
+static hipError_t plane_impl(const Geom &g, void *S1, const void *Nt, const void *tw,
+                             size_t lds_max, hipStream_t s, bool query)
+{
+    using C = PlaneCfg<T, MY, MZ>;
+    const size_t shm = plane_lds_bytes<T, MY, MZ>(g.nz);
+    if (shm > lds_max) return hipErrorInvalidConfiguration;
+    if (query) {
+        if (shm > 65536)
+            return hipFuncSetAttribute((const void *)k_plane<T, MY, MZ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((k_plane<T, MY, MZ>), dim3(g.hx), dim3(C::NTHR), shm, s, (cpx<T> *)S1,
+                       (const T *)Nt, g.ny, g.nz, (const cpx<T> *)tw + MY,
+                       (const cpx<T> *)tw + MZ);
+    return hipGetLastError();
+}
+
+#define TDGL_PLANE_MZ(T, MY)                                                              \
+    switch (g.mz) {                                                                       \
+    case 8: return plane_impl<T, MY, 8>(g, S1, Nt, tw, lds_max, s, query);                \
+    case 16: return plane_impl<T, MY, 16>(g, S1, Nt, tw, lds_max, s, query);              \
+    case 32: return plane_impl<T, MY, 32>(g, S1, Nt, tw, lds_max, s, query);              \
+    case 64: return plane_impl<T, MY, 64>(g, S1, Nt, tw, lds_max, s, query);              \
+    case 128: return plane_impl<T, MY, 128>(g, S1, Nt, tw, lds_max, s, query);            \
+    default: return hipErrorInvalidValue;                                                 \
+    }
+
+#define TDGL_PLANE_MY(T)                        \
+    switch (g.my) {                             \
+    case 8: TDGL_PLANE_MZ(T, 8)                 \
+    case 16: TDGL_PLANE_MZ(T, 16)               \
+    case 32: TDGL_PLANE_MZ(T, 32)               \
+    case 64: TDGL_PLANE_MZ(T, 64)               \
+    case 128: TDGL_PLANE_MZ(T, 128)             \
+    case 256: TDGL_PLANE_MZ(T, 256)             \
+    default: return hipErrorInvalidValue;       \
+    }
+
+// query = true: check that the plane path fits the device's LDS and set the
+// kernel's dynamic-LDS limit (call once, outside graph capture).
+hipError_t launch_plane(int prec, const Geom &g, void *S1, const void *Nt, const void *tw,
+                        size_t lds_max, hipStream_t s, bool query)
+{
+    if (prec == PREC_F32) {
+        TDGL_PLANE_MY(float)
+    } else {
+        TDGL_PLANE_MY(double)
     }
 }
 

@@ -52,9 +52,15 @@ struct UpdArgs {
     int yt;                // rows per work-group (even)
 };
 
+// spectra are kx-major: x pass output element k of row r at out[k*out_kstride + r]
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
-                     long long in_stride, void *out, long long out_stride,
+                     long long in_stride, void *out, long long out_kstride,
                      const void *tw, hipStream_t s);
+hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long long nlines,
+                      long long in_stride, long long out_stride, int n_in, int n_out,
+                      const void *tw, hipStream_t s);
+hipError_t launch_plane(int prec, const Geom &g, void *S1, const void *Nt, const void *tw,
+                        size_t lds_max, hipStream_t s, bool query);
 hipError_t launch_col(int prec, int M, bool inv, const void *in, void *out, long long C,
                       long long nbatch, long long in_bstride, long long out_bstride,
                       long long lstride, int n_in, int n_out, const void *tw, hipStream_t s);

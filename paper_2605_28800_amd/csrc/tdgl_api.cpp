@@ -76,6 +76,9 @@ struct tdgl_ctx {
     int *flag = nullptr;
     int cur = 0;
     int yt = 2;
+    size_t lds_max = 65536;      // dynamic LDS one work-group may use on this device
+    int fft_path = 0;            // 0: fused plane pass when it fits, 1: three passes
+    bool use_plane = false;
     int nblocks = 1;
     bool P_set = false, tensor_built = false, spec_valid = false, params_dirty = true;
     int mimg = -1;
@@ -187,6 +190,8 @@ std::vector<T> twiddle_table()
     return tw;
 }
 
+void choose_path(tdgl_ctx *c);
+
 tdgl_status ensure_device(tdgl_ctx *c)
 {
     if (c->dev_init) return TDGL_OK;
@@ -226,11 +231,26 @@ tdgl_status ensure_device(tdgl_ctx *c)
     HIP_TRY(c, hipMemcpy(c->twd, twd.data(), twd.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->gl, gl.data(), gl.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemset(c->flag, 0, sizeof(int)));
+    int dev = 0, optin = 0;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) ==
+            hipSuccess && optin > 0)
+        c->lds_max = (size_t)optin;
     c->dev_init = true;
+    choose_path(c);
     return TDGL_OK;
 }
 
 const void *tw(const tdgl_ctx *c) { return c->prec == PREC_F32 ? c->twf : c->twd; }
+
+// The fused plane pass is used when one kx plane of the three components
+// (plus the z-pass scratch) fits in the LDS of one work-group.
+void choose_path(tdgl_ctx *c)
+{
+    c->use_plane = c->fft_path == 0 &&
+                   launch_plane(c->prec, c->g, nullptr, nullptr, nullptr, c->lds_max, nullptr,
+                                true) == hipSuccess;
+}
 
 // ---- reduced parameters (Table 2 with alpha_ref in place of |alpha1|)
 void landau_si(const tdgl_material &m, double T, double out[8])
@@ -343,21 +363,23 @@ bool elec_on(const tdgl_ctx *c) { return (c->terms & TDGL_ELEC) != 0; }
 hipError_t enq_fx(tdgl_ctx *c, const void *P, hipStream_t s)
 {
     const Geom &g = c->g;
-    return launch_fx(c->prec, g.mx, P, 3LL * g.nz * g.ny, g.nx, g.nx, c->S1, g.hx, tw(c), s);
+    return launch_fx(c->prec, g.mx, P, 3LL * g.nz * g.ny, g.nx, g.nx, c->S1,
+                     3LL * g.nz * g.ny, tw(c), s);
 }
 
-// y pass, z pass with the tensor, inverse y pass: S1 (x spectra) -> S1 (field rows)
+// y pass, z pass with the tensor, inverse y pass: S1 (x spectra, kx-major
+// [hx][3][nz][ny]) -> S1 (field rows), fused into one kernel when possible.
 hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
 {
     const Geom &g = c->g;
-    hipError_t e = launch_col(c->prec, g.my, false, c->S1, c->S2, g.hx, 3LL * g.nz,
-                              (long long)g.ny * g.hx, (long long)g.my * g.hx, g.hx, g.ny, g.my,
+    if (c->use_plane) return launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, s, false);
+    const long long nl = (long long)g.hx * 3 * g.nz;
+    hipError_t e = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
                               tw(c), s);
     if (e != hipSuccess) return e;
     e = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), s);
     if (e != hipSuccess) return e;
-    return launch_col(c->prec, g.my, true, c->S2, c->S1, g.hx, 3LL * g.nz,
-                      (long long)g.my * g.hx, (long long)g.ny * g.hx, g.hx, g.my, g.ny, tw(c), s);
+    return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny, tw(c), s);
 }
 
 hipError_t enq_upd(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
@@ -493,7 +515,7 @@ tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream, 
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->layer.assign(n[2], 0);
     c->yt = update_rows_per_block(c->prec, c->g);
-    c->nblocks = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
+    c->nblocks = ((c->g.ny + 1) / 2) * c->g.nz;   // partial sums for any row tile >= 2
     *out = c;
     return TDGL_OK;
 }
@@ -628,16 +650,17 @@ tdgl_status tdgl_build_tensor(tdgl_ctx *c, int mimg)
                                       c->d[2] / l0, c->gl, c->gl + GL_MAXN * GL_MAXN, R,
                                       c->stream);
     if (e == hipSuccess) e = launch_tensor_k0(g, c->pmask, R, nullptr, c->stream);
+    // spectrum C[kx][q][mz][my]: x pass (kx-major), y rows, z columns
+    const long long rows = 6LL * g.mz * g.my;
     if (e == hipSuccess)
-        e = launch_fx(PREC_F64, g.mx, R, 6LL * g.mz * g.my, g.mx, g.mx, C, g.hx, c->twd,
-                      c->stream);
+        e = launch_fx(PREC_F64, g.mx, R, rows, g.mx, g.mx, C, rows, c->twd, c->stream);
     if (e == hipSuccess)
-        e = launch_col(PREC_F64, g.my, false, C, C, g.hx, 6LL * g.mz, (long long)g.my * g.hx,
-                       (long long)g.my * g.hx, g.hx, g.my, g.my, c->twd, c->stream);
+        e = launch_row(PREC_F64, g.my, false, C, C, (long long)g.hx * 6 * g.mz, g.my, g.my, g.my,
+                       g.my, c->twd, c->stream);
     if (e == hipSuccess)
-        e = launch_col(PREC_F64, g.mz, false, C, C, (long long)g.my * g.hx, 6,
-                       (long long)g.mz * g.my * g.hx, (long long)g.mz * g.my * g.hx,
-                       (long long)g.my * g.hx, g.mz, g.mz, c->twd, c->stream);
+        e = launch_col(PREC_F64, g.mz, false, C, C, g.my, (long long)g.hx * 6,
+                       (long long)g.mz * g.my, (long long)g.mz * g.my, g.my, g.mz, g.mz, c->twd,
+                       c->stream);
     if (e == hipSuccess)
         e = launch_tensor_octant(c->prec, g, C, -kappa / (double)nreal, c->Nt, c->stream);
     hipError_t se = hipStreamSynchronize(c->stream);
@@ -716,6 +739,38 @@ tdgl_status tdgl_set_graph_chunk(tdgl_ctx *c, int steps)
     if (!c) return TDGL_E_ARG;
     if (steps < 0 || steps > 100000) return fail(c, TDGL_E_ARG, "graph chunk out of range");
     c->graph_chunk = steps;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_fft_path(tdgl_ctx *c, int path)
+{
+    if (!c) return TDGL_E_ARG;
+    if (path != 0 && path != 1) return fail(c, TDGL_E_ARG, "path must be 0 or 1");
+    c->fft_path = path;
+    drop_graphs(c);
+    if (c->dev_init) choose_path(c);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_update_rows(tdgl_ctx *c, int rows)
+{
+    if (!c) return TDGL_E_ARG;
+    if (rows < 0 || rows > 64 || (rows & 1)) return fail(c, TDGL_E_ARG, "rows must be even, 0..64");
+    const int yt = rows == 0 ? update_rows_per_block(c->prec, c->g) : rows;
+    // the launch checks threads and LDS; probe with a zero-size query here
+    const int nb = ((c->g.ny + yt - 1) / yt) * c->g.nz;
+    if (c->dev_init && nb > c->nblocks)
+        return fail(c, TDGL_E_STATE, "more row groups than the workspace was sized for");
+    c->yt = yt;
+    if (!c->dev_init) c->nblocks = nb > c->nblocks ? nb : c->nblocks;
+    drop_graphs(c);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_fft_path(const tdgl_ctx *c, int *fused)
+{
+    if (!c || !fused) return TDGL_E_ARG;
+    *fused = c->use_plane ? 1 : 0;
     return TDGL_OK;
 }
 
@@ -901,17 +956,21 @@ tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
             hipEvent_t *E = &ev[k];
             k += 5;
             (void)hipEventRecord(E[0], c->stream);
-            if (el) {
-                le = launch_col(c->prec, g.my, false, c->S1, c->S2, g.hx, 3LL * g.nz,
-                                (long long)g.ny * g.hx, (long long)g.my * g.hx, g.hx, g.ny, g.my,
+            if (el && c->use_plane) {
+                le = launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, c->stream, false);
+                (void)hipEventRecord(E[1], c->stream);
+                (void)hipEventRecord(E[2], c->stream);
+                (void)hipEventRecord(E[3], c->stream);
+            } else if (el) {
+                const long long nl = (long long)g.hx * 3 * g.nz;
+                le = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
                                 tw(c), c->stream);
                 (void)hipEventRecord(E[1], c->stream);
                 if (le == hipSuccess) le = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), c->stream);
                 (void)hipEventRecord(E[2], c->stream);
                 if (le == hipSuccess)
-                    le = launch_col(c->prec, g.my, true, c->S2, c->S1, g.hx, 3LL * g.nz,
-                                    (long long)g.my * g.hx, (long long)g.ny * g.hx, g.hx, g.my,
-                                    g.ny, tw(c), c->stream);
+                    le = launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny,
+                                    tw(c), c->stream);
                 (void)hipEventRecord(E[3], c->stream);
             } else {
                 (void)hipEventRecord(E[1], c->stream);
@@ -933,7 +992,7 @@ tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
             k += 5;
             float ms;
             if (el) {
-                for (int q = 0; q < 3; ++q) {
+                for (int q = 0; q < (c->use_plane ? 1 : 3); ++q) {
                     (void)hipEventElapsedTime(&ms, E[q], E[q + 1]);
                     sum[q] += ms;
                     cnt[q]++;

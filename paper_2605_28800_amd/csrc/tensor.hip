@@ -295,30 +295,29 @@ hipError_t launch_tensor_k0(const Geom &g, unsigned pmask, double *R, double *su
     return hipGetLastError();
 }
 
-// Octant of the real spectrum, scaled: Nt[q][kz][ky][kx] = scale * Re C[q][kz][ky][kx],
-// kz <= mz/2, ky <= my/2.
+// Octant of the real spectrum, scaled, kx-major:
+//   Nt[kx][q][kz][ky] = scale * Re C[kx][q][kz][ky],  kz <= mz/2, ky <= my/2,
+// from the full spectrum C[kx][q][mz][my].
 template <typename T>
 __global__ void k_tensor_octant(Geom g, const cpx<double> *__restrict__ C, double scale,
                                 T *__restrict__ Nt)
 {
     const int hy = g.my / 2 + 1, hz = g.mz / 2 + 1;
-    const long long per = (long long)hz * hy * g.hx;
+    const long long total = (long long)g.hx * 6 * hz * hy;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 6 * per) return;
-    const int q = (int)(idx / per);
-    const long long r = idx - q * per;
-    const int kx = (int)(r % g.hx);
-    const int ky = (int)((r / g.hx) % hy);
-    const int kz = (int)(r / ((long long)g.hx * hy));
-    const long long src = (((long long)q * g.mz + kz) * g.my + ky) * g.hx + kx;
+    if (idx >= total) return;
+    const int ky = (int)(idx % hy);
+    const int kz = (int)((idx / hy) % hz);
+    const long long kq = idx / ((long long)hy * hz);      // kx*6 + q
+    const long long src = (kq * g.mz + kz) * g.my + ky;
     Nt[idx] = (T)(scale * C[src].x);
 }
 
 hipError_t launch_tensor_octant(int prec, const Geom &g, const void *C, double scale, void *Nt,
                                 hipStream_t s)
 {
-    const long long per = (long long)(g.mz / 2 + 1) * (g.my / 2 + 1) * g.hx;
-    const long long blocks = (6 * per + 255) / 256;
+    const long long total = (long long)g.hx * 6 * (g.mz / 2 + 1) * (g.my / 2 + 1);
+    const long long blocks = (total + 255) / 256;
     if (prec == PREC_F32)
         hipLaunchKernelGGL((k_tensor_octant<float>), dim3((unsigned)blocks), dim3(256), 0, s, g,
                            (const cpx<double> *)C, scale, (float *)Nt);

@@ -43,19 +43,26 @@ __device__ __forceinline__ T landau_f(const T sq[3], const T *cf)
            cf[6] * (x * x * (y + z) + y * y * (x + z) + z * z * (x + y)) + cf[7] * x * y * z;
 }
 
+template <typename T>
+struct UpdMaxThreads {    // FP64 groups stay at 512 threads (room for 256 VGPRs)
+    static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
+};
+
 template <typename T, int M, int MODE>
-__global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
+__global__ void __launch_bounds__(UpdMaxThreads<T>::v)
+    k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
 {
     constexpr int TPL = M / 8;
     constexpr int LEN = LinePad<M>::len;
     constexpr int CPT = 2;                     // cells per thread, at most
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
-    T *hs = reinterpret_cast<T *>(smem_raw);   // [3][yt][nx], aliases the FFT scratch
+    cpx<T> *raw = lds;                          // [hx][3][yt] spectra staging
+    T *hs = reinterpret_cast<T *>(smem_raw);   // [3][yt][nx] field / new P rows
     const int yt = a.yt, half = yt / 2, nlines = 3 * half;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int z = blockIdx.y, y0 = blockIdx.x * yt;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, hx = g.hx;
     const long long plane = (long long)ny * nx;
     const long long comp = (long long)nz * plane;
     const T *Pin = reinterpret_cast<const T *>(a.P_in);
@@ -64,36 +71,30 @@ __global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> 
     const bool material = coefz[8] != T(0);
     const unsigned terms = a.terms;
     const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
+    const int ny_here = ny - y0 < yt ? ny - y0 : yt;     // rows of this tile inside the grid
 
     // line mapping of the x transforms
     const int l = tid / TPL, t = tid - l * TPL;
     const bool lact = l < nlines;
     const int lc = lact ? l / half : 0, lp = lact ? l - lc * half : 0;
-    const int ya = y0 + 2 * lp, yb = ya + 1;
-    const bool has_a = lact && ya < ny, has_b = lact && yb < ny;
+    const int yya = 2 * lp, yyb = yya + 1;
+    const bool has_a = lact && yya < ny_here, has_b = lact && yyb < ny_here;
     cpx<T> *L = lds + (lact ? l : 0) * LEN;
     cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
+    // S1 element (k, c, z, y) at ((k*3 + c)*nz + z)*ny + y; staging index (k*3 + c)*yt + yy
+    auto s1_index = [&](int e) -> long long {
+        const int yy = e % yt, kc = e / yt;
+        return ((long long)kc * nz + z) * ny + y0 + yy;
+    };
     const IdxPad pad{};
 
-    // ---- prologue: issue every global load of the kernel up front
+    // ---- prologue: issue the global loads up front
     TwReg<T, M> tr;
     if (a.elec_in || do_fx) twiddle_load(tr, tw, t);
-    cpx<T> v[8];
     if (a.elec_in) {
-        const cpx<T> *ra = S1 + (((long long)lc * nz + z) * ny + ya) * g.hx;
-        const cpx<T> *rb = ra + g.hx;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = t + q * TPL;
-            const int kk = k <= M / 2 ? k : M - k;
-            cpx<T> A = has_a ? ra[kk] : cpx<T>{T(0), T(0)};
-            cpx<T> B = has_b ? rb[kk] : cpx<T>{T(0), T(0)};
-            if (kk == 0 || kk == M / 2) {
-                A.y = T(0);
-                B.y = T(0);
-            }
-            // Hermitian extension of two real rows packed as A + iB
-            v[q] = k <= M / 2 ? cpx<T>{A.x - B.y, A.y + B.x} : cpx<T>{A.x + B.y, B.x - A.y};
+        for (int e = tid; e < hx * 3 * yt; e += nthr) {
+            const int yy = e % yt;
+            raw[e] = yy < ny_here ? S1[s1_index(e)] : cpx<T>{T(0), T(0)};
         }
     }
     // z neighbours exist if in range (or periodic) and not vacuum
@@ -149,10 +150,27 @@ __global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> 
 
     // ---- 1. electrostatic field rows (inverse x transform)
     if (a.elec_in) {
+        __syncthreads();
+        cpx<T> v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = t + q * TPL;
+            const int kk = k <= M / 2 ? k : M - k;
+            const int base = (kk * 3 + lc) * yt;
+            cpx<T> A = has_a ? raw[base + yya] : cpx<T>{T(0), T(0)};
+            cpx<T> B = has_b ? raw[base + yyb] : cpx<T>{T(0), T(0)};
+            if (kk == 0 || kk == M / 2) {
+                A.y = T(0);
+                B.y = T(0);
+            }
+            // Hermitian extension of two real rows packed as A + iB
+            v[q] = k <= M / 2 ? cpx<T>{A.x - B.y, A.y + B.x} : cpx<T>{A.x + B.y, B.x - A.y};
+        }
+        __syncthreads();   // staging is reused as FFT scratch
         fft_line<T, M, true>(v, L, pad, t, tr, lact);
         __syncthreads();
         if (lact) {
-            T *ha = hs + ((long long)lc * yt + 2 * lp) * nx;
+            T *ha = hs + ((long long)lc * yt + yya) * nx;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int x = t + q * TPL;
@@ -250,10 +268,11 @@ __global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> 
         }
     }
 
-    // ---- 3. x spectrum of the new rows
+    // ---- 3. x spectrum of the new rows, written back kx-major
     if (do_fx) {
         __syncthreads();
-        const T *ha = hs + ((long long)lc * yt + 2 * lp) * nx;
+        cpx<T> v[8];
+        const T *ha = hs + ((long long)lc * yt + yya) * nx;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int x = t + q * TPL;
@@ -269,14 +288,35 @@ __global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> 
             for (int q = 0; q < 8; ++q) L[pad(t + q * TPL)] = v[q];
         }
         __syncthreads();
+        // split into the two rows' half spectra (at most M/(2 TPL) + 1 k per thread)
+        constexpr int KPT = M / (2 * TPL) + 1;
+        cpx<T> sa[KPT], sb[KPT];
         if (lact) {
-            cpx<T> *ra = S1 + (((long long)lc * nz + z) * ny + ya) * g.hx;
-            cpx<T> *rb = ra + g.hx;
-            for (int k = t; k <= M / 2; k += TPL) {
-                const cpx<T> zk = L[pad(k)], zm = L[pad((M - k) & (M - 1))];
-                if (has_a) ra[k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-                if (has_b) rb[k] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+#pragma unroll
+            for (int j = 0; j < KPT; ++j) {
+                const int k = t + j * TPL;
+                if (k <= M / 2) {
+                    const cpx<T> zk = L[pad(k)], zm = L[pad((M - k) & (M - 1))];
+                    sa[j] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+                    sb[j] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+                }
             }
+        }
+        __syncthreads();   // staging aliases the FFT scratch
+        if (lact) {
+#pragma unroll
+            for (int j = 0; j < KPT; ++j) {
+                const int k = t + j * TPL;
+                if (k <= M / 2) {
+                    raw[(k * 3 + lc) * yt + yya] = sa[j];
+                    raw[(k * 3 + lc) * yt + yyb] = sb[j];
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < hx * 3 * yt; e += nthr) {
+            const int yy = e % yt;
+            if (yy < ny_here) S1[s1_index(e)] = raw[e];
         }
     }
 
@@ -304,34 +344,74 @@ __global__ void __launch_bounds__(512) k_update(UpdArgs a, Geom g, const cpx<T> 
     }
 }
 
-// rows per work-group: even, about one cell per thread of a 256-thread group
-// (enough groups in flight to hide memory latency on small grids)
+// LDS bytes of the update kernel for rows-per-group yt
+template <typename T, int M>
+static size_t update_lds(const Geom &g, int yt)
+{
+    const size_t nlines = 3 * (size_t)(yt / 2);
+    size_t b = nlines * LinePad<M>::len * sizeof(cpx<T>);
+    const size_t raw = (size_t)g.hx * 3 * yt * sizeof(cpx<T>);
+    const size_t hsb = (size_t)3 * yt * g.nx * sizeof(T);
+    if (b < raw) b = raw;
+    if (b < hsb) b = hsb;
+    if (b < 16 * 8 * sizeof(double)) b = 16 * 8 * sizeof(double);
+    return b;
+}
+
+static int update_threads(const Geom &g, int yt, int tpl)
+{
+    int nthr = 3 * (yt / 2) * tpl;
+    if (nthr < 256) nthr = 256;
+    if (nthr < (yt * g.nx + 1) / 2) nthr = (yt * g.nx + 1) / 2;   // <= 2 cells per thread
+    return (nthr + 63) / 64 * 64;
+}
+
+// Rows per work-group: even, up to 16 (128-byte segments of the kx-major
+// spectra for FP32), limited by threads (<= 2 cells per thread, <= 1024 FP32
+// / 512 FP64 threads) and 64 KiB of LDS.
+template <typename T, int M>
+static int rows_for(const Geom &g)
+{
+    const int maxthr = UpdMaxThreads<T>::v;
+    const int ny_even = g.ny + (g.ny & 1);
+    int best = 2;
+    for (int yt = 2; yt <= 16 && yt <= (ny_even > 2 ? ny_even : 2); yt += 2) {
+        if (update_threads(g, yt, M / 8) > maxthr) break;
+        if (update_lds<T, M>(g, yt) > 65536) break;
+        best = yt;
+    }
+    return best;
+}
+
+#define TDGL_ROWS_LEN(T)                                   \
+    switch (g.mx) {                                        \
+    case 8: return rows_for<T, 8>(g);                      \
+    case 16: return rows_for<T, 16>(g);                    \
+    case 32: return rows_for<T, 32>(g);                    \
+    case 64: return rows_for<T, 64>(g);                    \
+    case 128: return rows_for<T, 128>(g);                  \
+    case 256: return rows_for<T, 256>(g);                  \
+    case 512: return rows_for<T, 512>(g);                  \
+    case 1024: return rows_for<T, 1024>(g);                \
+    default: return 2;                                     \
+    }
+
 int update_rows_per_block(int prec, const Geom &g)
 {
-    (void)prec;
-    int yt = 2;
-    while ((yt + 2) * g.nx <= 256) yt += 2;
-    const int ny_even = g.ny + (g.ny & 1);
-    if (yt > ny_even) yt = ny_even;
-    if (yt < 2) yt = 2;
-    return yt;
+    if (prec == PREC_F32) {
+        TDGL_ROWS_LEN(float)
+    } else {
+        TDGL_ROWS_LEN(double)
+    }
 }
 
 template <typename T, int M, int MODE>
 static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, hipStream_t s,
                               int *nblocks_out)
 {
-    constexpr int TPL = M / 8;
-    const int nlines = 3 * (a.yt / 2);
-    int nthr = nlines * TPL;
-    if (nthr < 256) nthr = 256;
-    if (nthr < (a.yt * g.nx + 1) / 2) nthr = (a.yt * g.nx + 1) / 2;   // <= 2 cells per thread
-    nthr = (nthr + 63) / 64 * 64;
-    size_t shm = (size_t)nlines * LinePad<M>::len * sizeof(cpx<T>);
-    const size_t hs_bytes = (size_t)3 * a.yt * g.nx * sizeof(T);
-    if (shm < hs_bytes) shm = hs_bytes;
-    if (shm < 16 * 8 * sizeof(double)) shm = 16 * 8 * sizeof(double);
-    if (shm > 65536 || nthr > 512) return hipErrorInvalidConfiguration;
+    const int nthr = update_threads(g, a.yt, M / 8);
+    const size_t shm = update_lds<T, M>(g, a.yt);
+    if (shm > 65536 || nthr > UpdMaxThreads<T>::v) return hipErrorInvalidConfiguration;
     dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
     hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, a, g,

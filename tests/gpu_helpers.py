@@ -15,11 +15,33 @@ def announce(msg):
     sys.stdout.flush()
 
 
-def gpu_context(cfg, prec, chunk=None):
-    ctx = T.Context(cfg, PREC[prec] if isinstance(prec, str) else prec)
+def gpu_context(cfg, prec, chunk=None, path=0):
+    """Context for cfg.  path 0: fused plane pass where it fits, 1: three passes."""
+    ctx = T.Context(cfg, PREC[prec] if isinstance(prec, str) else prec, build_tensor=False)
+    T.tdgl_set_fft_path(ctx.ctx, path)
+    if cfg.get("terms", 15) & T.TDGL_ELEC:
+        T.tdgl_build_tensor(ctx.ctx, cfg.get("mimg", 16))
     if chunk is not None:
         T.tdgl_set_graph_chunk(ctx.ctx, chunk)
     return ctx
+
+
+def tensor_entry(cfg, offset, mimg):
+    """Oracle interaction tensor for one cell offset (with periodic images,
+    no k = 0 correction), components xx yy zz xy xz yz."""
+    import ctypes
+    from oracle import lib as orc_lib
+    n = cfg["n"]
+    pm = sum(1 << k for k in range(3) if cfg["periodic"][k])
+    idx = [(offset[k] % n[k]) if cfg["periodic"][k] else offset[k] + n[k] - 1 for k in range(3)]
+    t, w = O.gauss_legendre_tables()
+    prob_h = np.asarray(cfg["d"], float) / np.sqrt(cfg["scales"]["G110"] / cfg["scales"]["alpha_ref"])
+    out = np.zeros(6)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    N = (ctypes.c_int * 3)(*n)
+    I3 = (ctypes.c_int * 3)(*idx)
+    orc_lib().orc_offset_entry(N, pm, int(mimg), dp(prob_h), dp(t), dp(w), I3, dp(out))
+    return out
 
 
 def rel_inf(a, b):

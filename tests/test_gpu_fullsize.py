@@ -1,0 +1,199 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (fused plane pass for the 128x128x32 film in FP32, three-pass
+path for the 256x256x64 bilayer).
+
+The oracle cannot build the full periodic interaction table with 16 images
+in test time, so full-size checks use (a) the same film with mimg = 0, where
+the oracle table is cheap, element by element; (b) a point source, whose
+field is one column of the tensor: differences between cells of one z layer
+(the k = 0 correction cancels) against oracle entries computed one by one;
+(c) exact properties: a uniformly polarised film has E_z = -P_z/(eps0 epsB),
+a uniformly polarised box has mean field -N_box P/(eps0 epsB).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_28800_amd as T
+import tdgl_inputs as I
+from oracle import tdgl_oracle as O
+from tests.gpu_helpers import announce, gpu_context, ps_of, rel_inf, tensor_entry
+
+pytestmark = pytest.mark.gpu
+
+ELEC = T.TDGL_ELEC
+
+
+def _field(ctx, P, mask):
+    ctx.set_P(P)
+    return ctx.eval_field(mask).double().cpu().numpy()
+
+
+def test_film_uses_fused_path():
+    cfg = I.config("c2")
+    announce("c2 fused path selection")
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        assert T.tdgl_get_fft_path(ctx.ctx) == 1
+    finally:
+        ctx.close()
+
+
+@pytest.fixture(scope="module")
+def film_mimg0():
+    cfg = I.config("c2")
+    cfg["mimg"] = 0
+    return cfg, O.Problem(cfg)
+
+
+def test_film_full_field_parity_mimg0(film_mimg0):
+    cfg, prob = film_mimg0
+    announce("c2 full-size field parity (mimg 0), fp32")
+    P = I.initial_P(cfg, 0, np.float32)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(P)
+        for mask in (T.TDGL_ELEC, T.TDGL_ALL):
+            got = ctx.eval_field(mask).double().cpu().numpy()
+            ref = O.effective_field(P.astype(np.float64), prob, terms=mask) * prob.field_scale
+            assert rel_inf(got, ref) <= 2e-6, mask
+    finally:
+        ctx.close()
+
+
+def test_film_full_trajectory_mimg0(film_mimg0):
+    cfg, prob = film_mimg0
+    announce("c2 full-size 20 Heun steps (mimg 0), fp32")
+    P0 = I.initial_P(cfg, 0, np.float32)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(P0)
+        ctx.step(20)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    ref = O.run(P0.astype(np.float64), prob, "heun", cfg["dtau"], 20)
+    assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-5
+
+
+def test_film_point_source_mimg16():
+    """Full film with 16 images: field of a point source, sampled."""
+    cfg = I.config("c2")
+    announce("c2 point source mimg 16, fp32")
+    nx, ny, nz = cfg["n"]
+    c0 = (37, 90, 11)
+    p = np.array([0.3, -0.2, 0.5])
+    P = np.zeros((3, nz, ny, nx), np.float32)
+    P[:, c0[2], c0[1], c0[0]] = p
+    ctx = gpu_context(cfg, "f32")
+    try:
+        H = _field(ctx, P, ELEC)
+    finally:
+        ctx.close()
+    prob = O.Problem(cfg, tensor=False)
+    rng = np.random.Generator(np.random.PCG64(2))
+    scale = prob.kappa * prob.field_scale
+    hmax = np.abs(H).max()
+    pairs = 0
+    for z in (c0[2], 0, 31, 20):
+        cells = [(int(rng.integers(nx)), int(rng.integers(ny))) for _ in range(6)] + [(c0[0], c0[1])]
+        ref = []
+        got = []
+        for (x, y) in cells:
+            N6 = tensor_entry(cfg, (x - c0[0], y - c0[1], z - c0[2]), 16)
+            Nm = np.array([[N6[0], N6[3], N6[4]], [N6[3], N6[1], N6[5]], [N6[4], N6[5], N6[2]]])
+            ref.append(-scale * Nm @ p)
+            got.append(H[:, z, y, x])
+        ref = np.array(ref)
+        got = np.array(got)
+        dref = ref - ref[0]
+        dgot = got - got[0]
+        assert np.abs(dgot - dref).max() <= 3e-6 * hmax, z
+        pairs += len(cells)
+    assert pairs > 20
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_film_uniform_slab_exact(path):
+    cfg = I.config("c2")
+    announce("c2 uniform slab, fp32, path %d" % path)
+    nx, ny, nz = cfg["n"]
+    P = np.zeros((3, nz, ny, nx), np.float32)
+    P[2] = 0.26
+    ctx = gpu_context(cfg, "f32", path=path)
+    try:
+        H = _field(ctx, P, ELEC)
+    finally:
+        ctx.close()
+    E = -0.26 / (O.EPS0 * cfg["scales"]["eps_b"])
+    assert np.abs(H[2] / E - 1).max() <= 2e-6
+    assert np.abs(H[:2]).max() <= 2e-6 * abs(E)
+
+
+def test_bilayer_full_point_source():
+    """256x256x64 open bilayer (three-pass path): point-source field, sampled
+    cells against oracle entries (open box: no correction, direct values)."""
+    cfg = I.config("c4")
+    announce("c4 full-size point source, fp32")
+    nx, ny, nz = cfg["n"]
+    c0 = (200, 31, 40)
+    p = np.array([-0.1, 0.25, 0.4])
+    P = np.zeros((3, nz, ny, nx), np.float32)
+    P[:, c0[2], c0[1], c0[0]] = p
+    ctx = gpu_context(cfg, "f32")
+    try:
+        assert T.tdgl_get_fft_path(ctx.ctx) in (0, 1)
+        H = _field(ctx, P, ELEC)
+    finally:
+        ctx.close()
+    prob = O.Problem(cfg, tensor=False)
+    scale = prob.kappa * prob.field_scale
+    hmax = np.abs(H).max()
+    rng = np.random.Generator(np.random.PCG64(3))
+    cells = [c0, (0, 0, 0), (255, 255, 63), (c0[0] + 1, c0[1], c0[2]), (c0[0], c0[1], 47)]
+    cells += [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))) for _ in range(25)]
+    for (x, y, z) in cells:
+        N6 = tensor_entry(cfg, (x - c0[0], y - c0[1], z - c0[2]), 0)
+        Nm = np.array([[N6[0], N6[3], N6[4]], [N6[3], N6[1], N6[5]], [N6[4], N6[5], N6[2]]])
+        ref = -scale * Nm @ p
+        assert np.abs(H[:, z, y, x] - ref).max() <= 2e-6 * hmax, (x, y, z)
+
+
+def test_bilayer_full_uniform_box_mean_field():
+    cfg = I.config("c4")
+    announce("c4 full-size uniform box, fp32")
+    nx, ny, nz = cfg["n"]
+    p = np.array([0.05, -0.1, 0.2])
+    P = np.broadcast_to(p[:, None, None, None], (3, nz, ny, nx)).astype(np.float32)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        H = _field(ctx, P, ELEC)
+    finally:
+        ctx.close()
+    prob = O.Problem(cfg, tensor=False)
+    Nbox = O.newell_tensor((0, 0, 0), (nx, ny, nz))
+    Nm = np.array([[Nbox[0], Nbox[3], Nbox[4]], [Nbox[3], Nbox[1], Nbox[5]],
+                   [Nbox[4], Nbox[5], Nbox[2]]])
+    ref = -prob.kappa * prob.field_scale * Nm @ p
+    mean = H.reshape(3, -1).mean(axis=1)
+    assert np.abs(mean - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_bilayer_downscale_trajectory(prec, tol):
+    """32x32x8 version of the bilayer (layers 6/2), E_ext along z, Heun."""
+    cfg = I.config("c4_small")
+    cfg["eext"] = (0.0, 0.0, 1e8)
+    announce("c4_small trajectory %s" % prec)
+    P0 = I.initial_P(cfg, 0, np.float32 if prec == "f32" else np.float64)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, prec)
+    try:
+        ctx.set_P(P0)
+        ctx.step(100)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    ref = O.run(P0.astype(np.float64), prob, "heun", cfg["dtau"], 100)
+    assert np.abs(got - ref).max() / ps_of(cfg) <= tol

@@ -41,13 +41,14 @@ CASES = {
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_field_parity(case, prec):
+@pytest.mark.parametrize("path", [0, 1])
+def test_field_parity(case, prec, path):
     cfg = _cfg(**CASES[case])
-    announce("field parity %s %s" % (case, prec))
+    announce("field parity %s %s path %d" % (case, prec, path))
     P = I.initial_P(cfg, 3, np.float32 if prec == "f32" else np.float64)
     P64 = P.astype(np.float64)
     prob = O.Problem(cfg)
-    ctx = gpu_context(cfg, prec)
+    ctx = gpu_context(cfg, prec, path=path)
     try:
         ctx.set_P(P)
         tol = 1e-13 if prec == "f64" else 2e-6
@@ -92,14 +93,15 @@ def test_tensor_spectrum_parity(case):
     assert rel_inf(got, ref) <= 1e-13
 
 
-def test_c1_trajectory_fp64():
+@pytest.mark.parametrize("path", [0, 1])
+def test_c1_trajectory_fp64(path):
     """The FP64 parity configuration in full: 16x16x8 open box, BaTiO3 at
     300 K, all terms, Euler, 1000 steps of dtau = 1e-3."""
     cfg = I.config("c1")
-    announce("C1 trajectory fp64 1000 Euler steps")
+    announce("C1 trajectory fp64 1000 Euler steps path %d" % path)
     P0 = I.initial_P(cfg, 0)
     prob = O.Problem(cfg)
-    ctx = gpu_context(cfg, "f64")
+    ctx = gpu_context(cfg, "f64", path=path)
     try:
         ctx.set_P(P0)
         Ps = ps_of(cfg)
@@ -116,12 +118,13 @@ def test_c1_trajectory_fp64():
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_film_heun_trajectory(prec, tol):
+@pytest.mark.parametrize("path", [0, 1])
+def test_film_heun_trajectory(prec, tol, path):
     cfg = I.config("c2_small")
-    announce("c2_small heun trajectory %s" % prec)
+    announce("c2_small heun trajectory %s path %d" % (prec, path))
     P0 = I.initial_P(cfg, 0, np.float32 if prec == "f32" else np.float64)
     prob = O.Problem(cfg)
-    ctx = gpu_context(cfg, prec)
+    ctx = gpu_context(cfg, prec, path=path)
     try:
         ctx.set_P(P0)
         Ps = ps_of(cfg)

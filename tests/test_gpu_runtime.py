@@ -1,0 +1,174 @@
+"""GPU runtime behaviour through the C ABI: HIP graphs vs plain launches,
+bitwise determinism, split step counts, non-finite detection, state
+invalidation by field/energy evaluations, time-dependent E_ext, energy
+descent and caller-owned workspace."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_28800_amd as T
+import tdgl_inputs as I
+from oracle import tdgl_oracle as O
+from tests.gpu_helpers import announce, gpu_context, ps_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(cfg, prec, steps, chunk=None, path=0, seed=0):
+    ctx = gpu_context(cfg, prec, chunk=chunk, path=path)
+    try:
+        ctx.set_P(I.initial_P(cfg, seed, np.float32 if prec == "f32" else np.float64))
+        ctx.step(steps)
+        return ctx.get_P(T.TDGL_FP64 if prec == "f64" else T.TDGL_FP32)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("scheme", ["heun", "euler"])
+def test_graph_chunks_equal_plain_launches(scheme):
+    cfg = I.config("c2_small")
+    cfg["scheme"] = scheme
+    announce("graph vs plain %s" % scheme)
+    a = _run(cfg, "f32", 131, chunk=0)
+    b = _run(cfg, "f32", 131, chunk=64)
+    c = _run(cfg, "f32", 131, chunk=7)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_split_steps_and_rerun_bitwise():
+    cfg = I.config("c2_small")
+    announce("split steps bitwise")
+    whole = _run(cfg, "f32", 130)
+    again = _run(cfg, "f32", 130)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        ctx.step(50)
+        ctx.step(80)
+        split = ctx.get_P(T.TDGL_FP32)
+    finally:
+        ctx.close()
+    assert np.array_equal(whole, again)
+    assert np.array_equal(whole, split)
+
+
+def test_field_and_energy_calls_do_not_disturb_the_run():
+    cfg = I.config("c2_small")
+    announce("eval/energies between steps")
+    ref = _run(cfg, "f32", 60)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        ctx.step(20)
+        ctx.eval_field(T.TDGL_ALL)
+        ctx.energies()
+        ctx.step(25)
+        ctx.get_P()
+        ctx.eval_field(T.TDGL_ELEC)
+        ctx.step(15)
+        got = ctx.get_P(T.TDGL_FP32)
+    finally:
+        ctx.close()
+    assert np.array_equal(ref, got)
+
+
+def test_nonfinite_detected_and_cleared():
+    cfg = I.config("c1")
+    announce("non-finite flag")
+    ctx = gpu_context(cfg, "f64")
+    try:
+        P = I.initial_P(cfg, 0)
+        bad = P.copy()
+        bad[1, 3, 4, 5] = np.nan
+        ctx.set_P(bad)
+        ctx.step(3)
+        with pytest.raises(T.TdglError) as e:
+            ctx.sync()
+        assert e.value.status == T.TDGL_E_NONFINITE
+        ctx.set_P(P)            # a fresh state clears the flag
+        ctx.step(3)
+        ctx.sync()
+    finally:
+        ctx.close()
+
+
+def test_unstable_time_step_reported():
+    """dtau far above the explicit stability bound (about 2/320 here) blows
+    up; the step kernel flags it and sync reports it."""
+    cfg = I.config("c1")
+    cfg["dtau"] = 0.05
+    announce("unstable dtau")
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        ctx.step(200)
+        with pytest.raises(T.TdglError) as e:
+            ctx.sync()
+        assert e.value.status == T.TDGL_E_NONFINITE
+    finally:
+        ctx.close()
+
+
+def test_time_dependent_field_matches_oracle():
+    cfg = I.config("c4_small")
+    announce("E_ext changed between step calls")
+    prob = O.Problem(cfg)
+    P = I.initial_P(cfg, 1)
+    ctx = gpu_context(cfg, "f64")
+    try:
+        ctx.set_P(P)
+        for ez in (0.0, 5e7, 1e8, -5e7):
+            T.tdgl_set_eext(ctx.ctx, 0.0, 0.0, ez)
+            ctx.step(20)
+            prob.eext = np.array([0.0, 0.0, ez]) / prob.field_scale
+            P = O.run(P, prob, "heun", cfg["dtau"], 20)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    assert np.abs(got - P).max() / ps_of(cfg) <= 1e-12
+
+
+def test_energy_descends_on_gpu():
+    cfg = I.config("c2_small")
+    announce("energy descent")
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        F = []
+        for _ in range(12):
+            F.append(ctx.energies()[0][4])
+            ctx.step(25)
+    finally:
+        ctx.close()
+    assert np.all(np.diff(F) < 0), F
+
+
+def test_library_and_torch_workspaces_agree():
+    cfg = I.config("c2_small")
+    announce("workspace ownership")
+    a = _run(cfg, "f32", 40)
+    ctx = T.Context(cfg, T.TDGL_FP32, torch_workspace=False)
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        ctx.step(40)
+        b = ctx.get_P(T.TDGL_FP32)
+    finally:
+        ctx.close()
+    assert np.array_equal(a, b)
+
+
+def test_device_set_get_and_precision_conversion():
+    cfg = I.config("c2_small")
+    announce("set/get P on device")
+    P = I.initial_P(cfg, 4)
+    ctx = gpu_context(cfg, "f64")
+    try:
+        ctx.set_P(torch.from_numpy(P).cuda())
+        back = ctx.get_P_device(T.TDGL_FP64).cpu().numpy()
+        assert np.array_equal(back, P)
+        f32 = ctx.get_P_device(T.TDGL_FP32).cpu().numpy()
+        assert np.array_equal(f32, P.astype(np.float32))
+        ctx.set_P(torch.from_numpy(P.astype(np.float32)).cuda())
+        assert np.array_equal(ctx.get_P(), P.astype(np.float32).astype(np.float64))
+    finally:
+        ctx.close()
