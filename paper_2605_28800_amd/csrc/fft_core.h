@@ -114,6 +114,11 @@ struct IdxStride {      // element e of the line at e * s (lines interleaved)
 struct IdxPad {         // contiguous line, one pad slot after every 8 elements
     __device__ __forceinline__ int operator()(int e) const { return e + (e >> 3); }
 };
+struct IdxStridePad {   // lines interleaved at stride s, one pad row after every 8
+    int s;              // elements: 64 lanes of 8-byte accesses hit the minimum of
+                        // two LDS bank cycles in every radix stage
+    __device__ __forceinline__ int operator()(int e) const { return (e + (e >> 3)) * s; }
+};
 
 template <int M>
 struct LinePad {
@@ -138,7 +143,7 @@ struct Stage {
 template <int M>
 struct Stage<M, 0> {
     static constexpr int P = 1, R = 8, NB = 1, NTW = 0, OFF = 0;
-    static constexpr bool LAST = (M == 8);
+    static constexpr bool LAST = (M <= 8);
 };
 
 template <int M, int S = 0>
@@ -244,6 +249,50 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, i
         }
         fft_stages<T, M, 1, INV, Idx>(v, lds, idx, t, tr, act);
     }
+}
+
+// Real lines through complex transforms of half length.  A real line x of M
+// points is the complex line z[n] = x[2n] + i x[2n+1] of M/2 points; with
+// Z = DFT_{M/2}(z), E[k] = (Z[k] + conj Z[M/2-k])/2 and
+// O[k] = (Z[k] - conj Z[M/2-k])/(2i) are the DFTs of the even and odd samples,
+// and X[k] = E[k] + W_M^k O[k], X[k + M/2] = E[k] - W_M^k O[k].
+// real_split returns X[k] and sets xh = X[k + M/2] (needed at k = 0 only).
+template <typename T>
+__device__ __forceinline__ cpx<T> real_split(cpx<T> zk, cpx<T> zm, cpx<T> wk, cpx<T> &xh)
+{
+    const cpx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    const cpx<T> od = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+    const cpx<T> wo = cmul(od, wk);
+    xh = csub(ev, wo);
+    return cadd(ev, wo);
+}
+
+// The inverse: from the half spectrum X[0..M/2] of a real line (a = X[k],
+// b = X[M/2-k]) the complex line Z'[k] = (a + conj b) + i W_M^-k (a - conj b)
+// = 2 (E[k] + i O[k]), whose unnormalised inverse DFT of length M/2 is
+// M (x[2n] + i x[2n+1]), the unnormalised inverse real DFT of length M.
+template <typename T>
+__device__ __forceinline__ cpx<T> real_merge(cpx<T> a, cpx<T> b, cpx<T> wk)
+{
+    const cpx<T> e = {a.x + b.x, a.y - b.y};
+    const cpx<T> d = cmulc(cpx<T>{a.x - b.x, a.y + b.y}, wk);
+    return {e.x - d.y, e.y + d.x};
+}
+
+// Complex transform of one line of M2 points: M2/8 threads of eight points
+// each, or, for M2 = 4, one thread's registers.
+template <int M2>
+struct HalfLine {
+    static constexpr int PPT = M2 >= 8 ? 8 : M2;   // points per thread
+    static constexpr int TPL = M2 / PPT;           // threads per line
+};
+
+template <typename T, int M2, bool INV>
+__device__ __forceinline__ void half_fft(cpx<T> (&v)[8], cpx<T> *lds, int t,
+                                         const TwReg<T, M2> &tr, bool act)
+{
+    if constexpr (M2 >= 8) fft_line<T, M2, INV>(v, lds, IdxPad{}, t, tr, act);
+    else if (act) dft4<T, INV>(v);
 }
 
 }  // namespace tdgl

@@ -7,9 +7,9 @@
 // field at ((kx*3 + c)*nz + z)*L + y with L = ny (physical rows) or my
 // (after the y pass), so one kx plane of all components is contiguous.
 //
-//   k_fx    : real rows -> half spectra along x (two rows per complex line),
-//             zero padding beyond n_in implicit; output written kx-major
-//             through an LDS transpose.
+//   k_fx    : real rows -> half spectra along x (each row one complex line
+//             of half length), zero padding beyond n_in implicit; output
+//             written kx-major through an LDS transpose.
 //   k_row   : complex FFT of contiguous lines (y passes; tensor y pass).
 //   k_col   : complex FFT along a strided axis for tiles of adjacent columns
 //             (tensor z pass).
@@ -26,57 +26,62 @@ namespace tdgl {
 
 // ---------------------------------------------------------------- x pass
 // Rows r of n_in reals (stride in_stride) -> out[k * out_kstride + r],
-// k = 0..M/2.  Each work-group transforms 2*lpw consecutive rows.
+// k = 0..M/2.  Each row is one complex line of M/2 points (real_split); a
+// work-group transforms lpw consecutive rows and writes the spectra through
+// an LDS staging area, so that stores along r are contiguous.  tw: base of
+// the twiddle tables (table of length L at offset L).
 template <typename T, int M>
 __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long long in_stride,
                      cpx<T> *__restrict__ out, long long out_kstride,
                      const cpx<T> *__restrict__ tw, int lpw)
 {
-    constexpr int TPL = M / 8;
-    constexpr int LEN = LinePad<M>::len;
-    constexpr int H = M / 2 + 1;
+    constexpr int M2 = M / 2;
+    constexpr int PPT = HalfLine<M2>::PPT, TPL = HalfLine<M2>::TPL;
+    constexpr int LEN = LinePad<M2>::len;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
-    cpx<T> *stg = lds + lpw * LEN;                  // [H][2*lpw] output staging
+    cpx<T> *stg = lds + lpw * LEN;                  // [M2 + 1][lpw] output staging
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int l = tid / TPL, t = tid - l * TPL;
-    const long long r0 = (long long)blockIdx.x * 2 * lpw;
-    const long long ra = r0 + 2 * l;
-    const long long rb = ra + 1;
-    const bool act = (l < lpw) && (ra < nrows);
-    const bool hasb = act && (rb < nrows);
-    TwReg<T, M> tr;
-    twiddle_load(tr, tw, t);
-    cpx<T> v[8];
+    const long long r0 = (long long)blockIdx.x * lpw;
+    const long long r = r0 + l;
+    const bool act = (l < lpw) && (r < nrows);
+    TwReg<T, M2> tr;
+    twiddle_load(tr, tw + M2, t);
+    cpx<T> wk[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int x = t + q * TPL;
-        T av = T(0), bv = T(0);
-        if (act && x < n_in) av = in[ra * in_stride + x];
-        if (hasb && x < n_in) bv = in[rb * in_stride + x];
-        v[q] = {av, bv};
+    for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
+    cpx<T> v[8];
+    const T *row = in + (act ? r : 0) * in_stride;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int n = t + q * TPL;
+        const T ev = (act && 2 * n < n_in) ? row[2 * n] : T(0);
+        const T od = (act && 2 * n + 1 < n_in) ? row[2 * n + 1] : T(0);
+        v[q] = {ev, od};
     }
     cpx<T> *L = lds + (l < lpw ? l : 0) * LEN;
-    const IdxPad pad{};
-    fft_line<T, M, false>(v, L, pad, t, tr, act);
+    half_fft<T, M2, false>(v, L, t, tr, act);
+    __syncthreads();                                // scratch becomes the exchange buffer
+    cpx<T> *zx = lds + (l < lpw ? l : 0) * M2;
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) zx[t + q * TPL] = v[q];
+    }
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) L[pad(t + q * TPL)] = v[q];
-    }
-    __syncthreads();
-    if (l < lpw) {
-        for (int k = t; k <= M / 2; k += TPL) {
-            const cpx<T> zk = L[pad(k)], zm = L[pad((M - k) & (M - 1))];
-            // A = (Z[k] + conj Z[M-k]) / 2,  B = (Z[k] - conj Z[M-k]) / (2i)
-            stg[k * 2 * lpw + 2 * l] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-            stg[k * 2 * lpw + 2 * l + 1] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+        for (int q = 0; q < PPT; ++q) {
+            const int k = t + q * TPL;
+            cpx<T> xh;
+            stg[k * lpw + l] = real_split(zx[k], zx[(M2 - k) & (M2 - 1)], wk[q], xh);
+            if (k == 0) stg[M2 * lpw + l] = xh;
         }
     }
     __syncthreads();
-    const int rows_here = (int)((nrows - r0) < 2 * lpw ? (nrows - r0) : 2 * lpw);
-    for (int e = tid; e < H * 2 * lpw; e += nthr) {
-        const int k = e / (2 * lpw), rl = e - k * 2 * lpw;
+    const int rows_here = (int)((nrows - r0) < lpw ? (nrows - r0) : lpw);
+    for (int e = tid; e < (M2 + 1) * lpw; e += nthr) {
+        const int k = e / lpw, rl = e - k * lpw;
         if (rl < rows_here) out[k * out_kstride + r0 + rl] = stg[e];
     }
 }
@@ -142,7 +147,7 @@ __global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, long long ncol
         const int e = t + q * TPL;
         v[q] = (act && e < n_in) ? src[(long long)e * lstride] : cpx<T>{T(0), T(0)};
     }
-    fft_line<T, M, INV>(v, lds + cc, IdxStride{CT}, t, tr, act);
+    fft_line<T, M, INV>(v, lds + cc, IdxStridePad{CT}, t, tr, act);
     cpx<T> *dst = out + b * out_bstride + col;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -212,39 +217,43 @@ __global__ void __launch_bounds__(ZmulMaxThreads<T>::v)
     cpx<T> *col = S + ((long long)kx * 3 + c) * nz * zst + (act ? ky : 0);
     TwReg<T, MZ> tr;
     twiddle_load(tr, tw, t);
-    const TensorRow trow(c, 0);
-    const int kyc = act ? ky : 0;
-    T nrow[8][3];
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        tensor_row(Nt, kx, kyc, t + q * TPL, my, MZ, trow, nrow[q][0], nrow[q][1], nrow[q][2]);
+    // data first: the forward transform waits for these loads only, the
+    // tensor loads behind them complete during the transform
     cpx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
         v[q] = (act && z < nz) ? col[(long long)z * zst] : cpx<T>{T(0), T(0)};
     }
-    cpx<T> *L = lds + c * MZ * CT + cc;
-    fft_line<T, MZ, false>(v, L, IdxStride{CT}, t, tr, act);
+    const TensorRow trow(c, 0);
+    const int kyc = act ? ky : 0;
+    T nrow[8][3];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        tensor_row(Nt, kx, kyc, t + q * TPL, my, MZ, trow, nrow[q][0], nrow[q][1], nrow[q][2]);
+    constexpr int LZ = LinePad<MZ>::len;
+    const IdxStridePad ip{CT};
+    cpx<T> *L = lds + c * LZ * CT + cc;
+    fft_line<T, MZ, false>(v, L, ip, t, tr, act);
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) L[(t + q * TPL) * CT] = v[q];
+        for (int q = 0; q < 8; ++q) L[ip(t + q * TPL)] = v[q];
     }
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int kz = t + q * TPL;
-            const cpx<T> p0 = lds[(0 * MZ + kz) * CT + cc];
-            const cpx<T> p1 = lds[(1 * MZ + kz) * CT + cc];
-            const cpx<T> p2 = lds[(2 * MZ + kz) * CT + cc];
+            const cpx<T> p0 = lds[0 * LZ * CT + ip(kz) + cc];
+            const cpx<T> p1 = lds[1 * LZ * CT + ip(kz) + cc];
+            const cpx<T> p2 = lds[2 * LZ * CT + ip(kz) + cc];
             const T n0 = nrow[q][0], n1 = nrow[q][1], n2 = nrow[q][2];
             v[q] = {n0 * p0.x + n1 * p1.x + n2 * p2.x, n0 * p0.y + n1 * p1.y + n2 * p2.y};
         }
     }
     __syncthreads();
-    fft_line<T, MZ, true>(v, L, IdxStride{CT}, t, tr, act);
+    fft_line<T, MZ, true>(v, L, ip, t, tr, act);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
@@ -272,7 +281,7 @@ template <typename T, int MY, int MZ>
 size_t plane_lds_bytes(int nz)
 {
     using C = PlaneCfg<T, MY, MZ>;
-    return (size_t)(3 * nz * C::LINE + 3 * MZ * C::CK) * sizeof(cpx<T>);
+    return (size_t)(3 * nz * C::LINE + 3 * LinePad<MZ>::len * C::CK) * sizeof(cpx<T>);
 }
 
 template <typename T, int MY, int MZ>
@@ -285,7 +294,9 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     static_assert(C::YROUND >= 1 && C::NTHR <= 1024, "plane configuration");
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *pl = reinterpret_cast<cpx<T> *>(smem_raw);        // [3*nz][LINE]
-    cpx<T> *zs = pl + 3 * nz * LINE;                            // [3][MZ][CK]
+    cpx<T> *zs = pl + 3 * nz * LINE;                            // [3][MZ + MZ/8][CK]
+    constexpr int LZ = LinePad<MZ>::len;
+    const IdxStridePad ipz{CK};
     const int tid = threadIdx.x;
     const int kx = blockIdx.x;
     const IdxPad pad{};
@@ -344,23 +355,23 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
             const int z = tz + q * TPLZ;
             v[q] = z < nz ? colp[z * LINE] : cpx<T>{T(0), T(0)};
         }
-        cpx<T> *L = zs + cz * MZ * CK + cc;
-        fft_line<T, MZ, false>(v, L, IdxStride{CK}, tz, twz_r, true);
+        cpx<T> *L = zs + cz * LZ * CK + cc;
+        fft_line<T, MZ, false>(v, L, ipz, tz, twz_r, true);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) L[(tz + q * TPLZ) * CK] = v[q];
+        for (int q = 0; q < 8; ++q) L[ipz(tz + q * TPLZ)] = v[q];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int kz = tz + q * TPLZ;
-            const cpx<T> p0 = zs[(0 * MZ + kz) * CK + cc];
-            const cpx<T> p1 = zs[(1 * MZ + kz) * CK + cc];
-            const cpx<T> p2 = zs[(2 * MZ + kz) * CK + cc];
+            const cpx<T> p0 = zs[0 * LZ * CK + ipz(kz) + cc];
+            const cpx<T> p1 = zs[1 * LZ * CK + ipz(kz) + cc];
+            const cpx<T> p2 = zs[2 * LZ * CK + ipz(kz) + cc];
             const T n0 = nrow[q][0], n1 = nrow[q][1], n2 = nrow[q][2];
             v[q] = {n0 * p0.x + n1 * p1.x + n2 * p2.x, n0 * p0.y + n1 * p1.y + n2 * p2.y};
         }
         __syncthreads();
-        fft_line<T, MZ, true>(v, L, IdxStride{CK}, tz, twz_r, true);
+        fft_line<T, MZ, true>(v, L, ipz, tz, twz_r, true);
         cpx<T> *colw = pl + (cz * nz) * LINE + pad(ky);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -395,16 +406,17 @@ template <typename T, int M>
 static hipError_t fx_impl(const void *in, long long nrows, int n_in, long long in_stride,
                           void *out, long long out_kstride, const void *tw, hipStream_t s)
 {
-    constexpr int TPL = M / 8;
+    constexpr int M2 = M / 2;
+    constexpr int TPL = HalfLine<M2>::TPL;
     const int lpw = TPL >= 256 ? 1 : 256 / TPL;
-    const long long nlines = (nrows + 1) / 2;
-    const long long blocks = (nlines + lpw - 1) / lpw;
+    const long long blocks = (nrows + lpw - 1) / lpw;
     if (blocks <= 0) return hipSuccess;
-    const size_t shm = ((size_t)lpw * LinePad<M>::len + (size_t)(M / 2 + 1) * 2 * lpw) *
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t shm = ((size_t)lpw * LinePad<M2>::len + (size_t)(M2 + 1) * lpw) *
                        sizeof(cpx<T>);
     hipLaunchKernelGGL((k_fx<T, M>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
                        (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_kstride,
-                       (const cpx<T> *)tw + M, lpw);
+                       (const cpx<T> *)tw, lpw);
     return hipGetLastError();
 }
 
@@ -462,7 +474,8 @@ static int col_tile()
 {
     constexpr int TPL = M / 8;
     int ct = 128 / (int)sizeof(cpx<T>);
-    while (ct > 1 && (ct * TPL > 1024 || (size_t)ct * M * sizeof(cpx<T>) > 65536)) ct /= 2;
+    while (ct > 1 && (ct * TPL > 1024 || (size_t)ct * LinePad<M>::len * sizeof(cpx<T>) > 65536))
+        ct /= 2;
     return ct;
 }
 
@@ -477,7 +490,7 @@ static hipError_t col_impl(bool inv, const void *in, void *out, long long C, lon
     const long long gx = (ncols + ct - 1) / ct;
     if (gx <= 0) return hipSuccess;
     if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t shm = (size_t)ct * M * sizeof(cpx<T>);
+    const size_t shm = (size_t)ct * LinePad<M>::len * sizeof(cpx<T>);
     dim3 grid((unsigned)gx);
     if (inv)
         hipLaunchKernelGGL((k_col<T, M, true>), grid, dim3(ct * TPL), shm, s,
@@ -512,11 +525,11 @@ static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *
     constexpr int TPL = MZ / 8;
     int ct = 128 / (int)sizeof(cpx<T>);
     while (ct > 1 && (3 * ct * TPL > ZmulMaxThreads<T>::v ||
-                      (size_t)3 * ct * MZ * sizeof(cpx<T>) > 65536))
+                      (size_t)3 * ct * LinePad<MZ>::len * sizeof(cpx<T>) > 65536))
         ct /= 2;
     const int gx = (g.my + ct - 1) / ct;
     if (g.hx > 65535) return hipErrorInvalidValue;
-    const size_t shm = (size_t)3 * ct * MZ * sizeof(cpx<T>);
+    const size_t shm = (size_t)3 * ct * LinePad<MZ>::len * sizeof(cpx<T>);
     hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx), dim3(3 * ct * TPL), shm, s,
                        (cpx<T> *)S, (const T *)Nt, g.nz, g.my, ct, (const cpx<T> *)tw + MZ);
     return hipGetLastError();

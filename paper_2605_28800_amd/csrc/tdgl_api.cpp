@@ -895,7 +895,9 @@ tdgl_status tdgl_energies(tdgl_ctx *c, double F[5], double meanP[3])
     HIP_TRY(c, enq_eval(c, UPD_ENERGY, c->P[c->cur], nullptr, nullptr, 0, c->terms, el, false,
                         c->stream));
     if (el) c->spec_valid = false;
-    HIP_TRY(c, launch_reduce_partials(c->partials, c->nblocks, c->res, c->stream));
+    // one partial per work-group of the launch just made
+    const int ngroups = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
+    HIP_TRY(c, launch_reduce_partials(c->partials, ngroups, c->res, c->stream));
     double r[8];
     HIP_TRY(c, hipMemcpyAsync(r, c->res, sizeof r, hipMemcpyDeviceToHost, c->stream));
     st = read_flag(c);

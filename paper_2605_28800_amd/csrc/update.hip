@@ -2,8 +2,9 @@
 //
 // One work-group owns yt consecutive rows (all x) of one z layer, for all
 // three components.  In order:
-//   1. inverse x transform of the electrostatic field rows (two rows of one
-//      component per complex line, Hermitian extension on the fly);
+//   1. inverse x transform of the electrostatic field rows: each real row of
+//      padded length M is one complex line of M/2 points (even samples real,
+//      odd samples imaginary), built from the half spectrum on the fly;
 //   2. per cell: Landau field (minus the P-derivative of eq 3), gradient
 //      field (eq 4, diagonal part, 7-point stencil; neighbours across an open
 //      surface or in vacuum are dropped, periodic dimensions wrap), applied
@@ -13,7 +14,8 @@
 //                stage 1  P_out = (P_old + P_in)/2 + dtau/2 E   (Heun corrector)
 //        FIELD : E written out in V/m
 //        ENERGY: FP64 partial sums of the energy terms and of P;
-//   3. STEP with fx_out: forward x transform of the new rows, written over
+//   3. STEP with fx_out: forward x transform of the new rows (again M/2
+//      complex points per row, split into the half spectrum), written over
 //      the spectra rows read in step 1, so the next field evaluation starts
 //      at the y pass.
 #include "fft_core.h"
@@ -52,17 +54,30 @@ template <typename T, int M, int MODE>
 __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
 {
-    constexpr int TPL = M / 8;
-    constexpr int LEN = LinePad<M>::len;
+    // The x transforms of real rows run as complex transforms of length M/2
+    // (real_split / real_merge).
+    constexpr int M2 = M / 2;
+    constexpr int PPT = HalfLine<M2>::PPT;     // points per thread
+    constexpr int TPL = HalfLine<M2>::TPL;     // threads per row
+    constexpr int LEN = LinePad<M2>::len;
     constexpr int CPT = 2;                     // cells per thread, at most
     extern __shared__ unsigned char smem_raw[];
-    cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
-    cpx<T> *raw = lds;                          // [hx][3][yt] spectra staging
-    T *hs = reinterpret_cast<T *>(smem_raw);   // [3][yt][nx] field / new P rows
-    const int yt = a.yt, half = yt / 2, nlines = 3 * half;
+    const int yt = a.yt;
+    const int nrows = 3 * yt;                  // (component, row) lines
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int z = blockIdx.y, y0 = blockIdx.x * yt;
     const int nx = g.nx, ny = g.ny, nz = g.nz, hx = g.hx;
+    // LDS: region A = spectra staging raw[(k*3 + c)*RS + yy] (RS = yt + 1),
+    // also the rows hs[(c*yt + yy)*HS + x] (HS = nx + 1); region B = FFT
+    // scratch per line (and the forward exchange zx[line*M2 + k]).
+    const int RS = yt + 1, HS = nx + 1;
+    size_t abytes = (size_t)hx * 3 * RS * sizeof(cpx<T>);
+    const size_t hbytes = (size_t)nrows * HS * sizeof(T);
+    if (hbytes > abytes) abytes = hbytes;
+    abytes = (abytes + 15) / 16 * 16;
+    cpx<T> *raw = reinterpret_cast<cpx<T> *>(smem_raw);
+    T *hs = reinterpret_cast<T *>(smem_raw);
+    cpx<T> *scr = reinterpret_cast<cpx<T> *>(smem_raw + abytes);
     const long long plane = (long long)ny * nx;
     const long long comp = (long long)nz * plane;
     const T *Pin = reinterpret_cast<const T *>(a.P_in);
@@ -71,30 +86,37 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const bool material = coefz[8] != T(0);
     const unsigned terms = a.terms;
     const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
-    const int ny_here = ny - y0 < yt ? ny - y0 : yt;     // rows of this tile inside the grid
+    const int ny_here = ny - y0 < yt ? ny - y0 : yt;
 
-    // line mapping of the x transforms
+    // line mapping of the x transforms: line = c*yt + yy
     const int l = tid / TPL, t = tid - l * TPL;
-    const bool lact = l < nlines;
-    const int lc = lact ? l / half : 0, lp = lact ? l - lc * half : 0;
-    const int yya = 2 * lp, yyb = yya + 1;
-    const bool has_a = lact && yya < ny_here, has_b = lact && yyb < ny_here;
-    cpx<T> *L = lds + (lact ? l : 0) * LEN;
+    const bool lact = l < nrows;
+    const int lc = lact ? l / yt : 0, lyy = lact ? l - lc * yt : 0;
+    cpx<T> *L = scr + (lact ? l : 0) * LEN;
     cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
-    // S1 element (k, c, z, y) at ((k*3 + c)*nz + z)*ny + y; staging index (k*3 + c)*yt + yy
-    auto s1_index = [&](int e) -> long long {
-        const int yy = e % yt, kc = e / yt;
+    auto s1_index = [&](int kc, int yy) -> long long {
         return ((long long)kc * nz + z) * ny + y0 + yy;
     };
-    const IdxPad pad{};
-
     // ---- prologue: issue the global loads up front
-    TwReg<T, M> tr;
-    if (a.elec_in || do_fx) twiddle_load(tr, tw, t);
+    TwReg<T, M2> tr;
+    cpx<T> wk[8];                              // W_M^k, k = t + q*TPL
+    if (a.elec_in || do_fx) {
+        twiddle_load(tr, tw + M2, t);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
+    }
+    // spectra of the group: the first RPT*nthr elements are loaded into
+    // registers as one batch of independent loads, stored to LDS only after
+    // the cell loads below have been issued
+    constexpr int RPT = 4;
+    const int nraw = hx * 3 * yt;
+    cpx<T> rv[RPT];
     if (a.elec_in) {
-        for (int e = tid; e < hx * 3 * yt; e += nthr) {
-            const int yy = e % yt;
-            raw[e] = yy < ny_here ? S1[s1_index(e)] : cpx<T>{T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int e = tid + j * nthr;
+            const int kc = e / yt, yy = e - kc * yt;
+            rv[j] = (e < nraw && yy < ny_here) ? S1[s1_index(kc, yy)] : cpx<T>{T(0), T(0)};
         }
     }
     // z neighbours exist if in range (or periodic) and not vacuum
@@ -148,36 +170,42 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         }
     }
 
-    // ---- 1. electrostatic field rows (inverse x transform)
+    // ---- 1. electrostatic field rows (inverse x transform, half length)
     if (a.elec_in) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int e = tid + j * nthr;
+            const int kc = e / yt, yy = e - kc * yt;
+            if (e < nraw) raw[kc * RS + yy] = rv[j];
+        }
+        for (int e = tid + RPT * nthr; e < nraw; e += nthr) {     // long rows only
+            const int kc = e / yt, yy = e - kc * yt;
+            raw[kc * RS + yy] = yy < ny_here ? S1[s1_index(kc, yy)] : cpx<T>{T(0), T(0)};
+        }
         __syncthreads();
         cpx<T> v[8];
+        const bool has = lact && lyy < ny_here;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = t + q * TPL;
-            const int kk = k <= M / 2 ? k : M - k;
-            const int base = (kk * 3 + lc) * yt;
-            cpx<T> A = has_a ? raw[base + yya] : cpx<T>{T(0), T(0)};
-            cpx<T> B = has_b ? raw[base + yyb] : cpx<T>{T(0), T(0)};
-            if (kk == 0 || kk == M / 2) {
+        for (int q = 0; q < PPT; ++q) {
+            const int k = t + q * TPL;                 // 0 .. M2-1
+            const int km = M2 - k;                     // 1 .. M2
+            cpx<T> A = has ? raw[(k * 3 + lc) * RS + lyy] : cpx<T>{T(0), T(0)};
+            cpx<T> B = has ? raw[(km * 3 + lc) * RS + lyy] : cpx<T>{T(0), T(0)};
+            if (k == 0) {                              // X[0], X[M/2] are real
                 A.y = T(0);
                 B.y = T(0);
             }
-            // Hermitian extension of two real rows packed as A + iB
-            v[q] = k <= M / 2 ? cpx<T>{A.x - B.y, A.y + B.x} : cpx<T>{A.x + B.y, B.x - A.y};
+            v[q] = real_merge(A, B, wk[q]);
         }
-        __syncthreads();   // staging is reused as FFT scratch
-        fft_line<T, M, true>(v, L, pad, t, tr, lact);
-        __syncthreads();
+        half_fft<T, M2, true>(v, L, t, tr, lact);
+        if constexpr (M2 <= 8) __syncthreads();   // no barrier inside: raw is still read
         if (lact) {
-            T *ha = hs + ((long long)lc * yt + yya) * nx;
+            T *ha = hs + (lc * yt + lyy) * HS;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int x = t + q * TPL;
-                if (x < nx) {
-                    ha[x] = v[q].x;
-                    ha[nx + x] = v[q].y;
-                }
+            for (int q = 0; q < PPT; ++q) {
+                const int n = t + q * TPL;
+                if (2 * n < nx) ha[2 * n] = v[q].x;
+                if (2 * n + 1 < nx) ha[2 * n + 1] = v[q].y;
             }
         }
         __syncthreads();
@@ -200,7 +228,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         T hel[3] = {T(0), T(0), T(0)};
         if (a.elec_in) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) hel[c] = hs[((long long)c * yt + yy) * nx + x];
+            for (int c = 0; c < 3; ++c) hel[c] = hs[(c * yt + yy) * HS + x];
         }
         T fg = T(0);
         if (material) {
@@ -245,7 +273,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             for (int c = 0; c < 3; ++c) {
                 Pout[c * comp + cell] = o[c];
                 if (!isfinite(o[c])) atomicOr(a.flag, 1);
-                if (do_fx) hs[((long long)c * yt + yy) * nx + x] = o[c];
+                if (do_fx) hs[(c * yt + yy) * HS + x] = o[c];
             }
         } else if constexpr (MODE == UPD_FIELD) {
             const T sc = kp->out_scale;
@@ -268,55 +296,40 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         }
     }
 
-    // ---- 3. x spectrum of the new rows, written back kx-major
+    // ---- 3. x spectrum of the new rows (half length), written back kx-major
     if (do_fx) {
         __syncthreads();
         cpx<T> v[8];
-        const T *ha = hs + ((long long)lc * yt + yya) * nx;
+        const bool has = lact && lyy < ny_here;
+        const T *ha = hs + (lc * yt + lyy) * HS;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int x = t + q * TPL;
-            const T av = (has_a && x < nx) ? ha[x] : T(0);
-            const T bv = (has_b && x < nx) ? ha[nx + x] : T(0);
-            v[q] = {av, bv};
+        for (int q = 0; q < PPT; ++q) {
+            const int n = t + q * TPL;
+            const T ev = (has && 2 * n < nx) ? ha[2 * n] : T(0);
+            const T od = (has && 2 * n + 1 < nx) ? ha[2 * n + 1] : T(0);
+            v[q] = {ev, od};
         }
-        __syncthreads();
-        fft_line<T, M, false>(v, L, pad, t, tr, lact);
+        half_fft<T, M2, false>(v, L, t, tr, lact);
+        __syncthreads();                       // scratch becomes the exchange buffer
+        cpx<T> *zx = scr + (lact ? l : 0) * M2;
+        if (lact) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) zx[t + q * TPL] = v[q];
+        }
         __syncthreads();
         if (lact) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) L[pad(t + q * TPL)] = v[q];
-        }
-        __syncthreads();
-        // split into the two rows' half spectra (at most M/(2 TPL) + 1 k per thread)
-        constexpr int KPT = M / (2 * TPL) + 1;
-        cpx<T> sa[KPT], sb[KPT];
-        if (lact) {
-#pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                const int k = t + j * TPL;
-                if (k <= M / 2) {
-                    const cpx<T> zk = L[pad(k)], zm = L[pad((M - k) & (M - 1))];
-                    sa[j] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-                    sb[j] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
-                }
-            }
-        }
-        __syncthreads();   // staging aliases the FFT scratch
-        if (lact) {
-#pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                const int k = t + j * TPL;
-                if (k <= M / 2) {
-                    raw[(k * 3 + lc) * yt + yya] = sa[j];
-                    raw[(k * 3 + lc) * yt + yyb] = sb[j];
-                }
+            for (int q = 0; q < PPT; ++q) {
+                const int k = t + q * TPL;
+                cpx<T> xh;
+                raw[(k * 3 + lc) * RS + lyy] = real_split(zx[k], zx[(M2 - k) & (M2 - 1)], wk[q], xh);
+                if (k == 0) raw[(M2 * 3 + lc) * RS + lyy] = xh;
             }
         }
         __syncthreads();
         for (int e = tid; e < hx * 3 * yt; e += nthr) {
-            const int yy = e % yt;
-            if (yy < ny_here) S1[s1_index(e)] = raw[e];
+            const int kc = e / yt, yy = e - kc * yt;
+            if (yy < ny_here) S1[s1_index(kc, yy)] = raw[kc * RS + yy];
         }
     }
 
@@ -344,23 +357,27 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     }
 }
 
-// LDS bytes of the update kernel for rows-per-group yt
+// LDS bytes of the update kernel for rows-per-group yt: region A holds the
+// x-spectra staging [hx][3][yt+1] and, at other times, the rows [3][yt][nx+1];
+// region B the half-length FFT scratch [3 yt][M/2 + M/16] and, at other
+// times, the forward-transform exchange [3 yt][M/2].
 template <typename T, int M>
 static size_t update_lds(const Geom &g, int yt)
 {
-    const size_t nlines = 3 * (size_t)(yt / 2);
-    size_t b = nlines * LinePad<M>::len * sizeof(cpx<T>);
-    const size_t raw = (size_t)g.hx * 3 * yt * sizeof(cpx<T>);
-    const size_t hsb = (size_t)3 * yt * g.nx * sizeof(T);
-    if (b < raw) b = raw;
-    if (b < hsb) b = hsb;
-    if (b < 16 * 8 * sizeof(double)) b = 16 * 8 * sizeof(double);
-    return b;
+    const size_t raw = (size_t)g.hx * 3 * (yt + 1) * sizeof(cpx<T>);
+    const size_t hsb = (size_t)3 * yt * (g.nx + 1) * sizeof(T);
+    size_t a = raw > hsb ? raw : hsb;
+    a = (a + 15) / 16 * 16;
+    const size_t b = (size_t)3 * yt * LinePad<M / 2>::len * sizeof(cpx<T>);
+    size_t tot = a + b;
+    if (tot < 16 * 8 * sizeof(double)) tot = 16 * 8 * sizeof(double);
+    return tot;
 }
 
+// tpl: threads per line of the half-length transform
 static int update_threads(const Geom &g, int yt, int tpl)
 {
-    int nthr = 3 * (yt / 2) * tpl;
+    int nthr = 3 * yt * tpl;                // one row per line of M/2 points
     if (nthr < 256) nthr = 256;
     if (nthr < (yt * g.nx + 1) / 2) nthr = (yt * g.nx + 1) / 2;   // <= 2 cells per thread
     return (nthr + 63) / 64 * 64;
@@ -376,7 +393,7 @@ static int rows_for(const Geom &g)
     const int ny_even = g.ny + (g.ny & 1);
     int best = 2;
     for (int yt = 2; yt <= 16 && yt <= (ny_even > 2 ? ny_even : 2); yt += 2) {
-        if (update_threads(g, yt, M / 8) > maxthr) break;
+        if (update_threads(g, yt, M >= 16 ? M / 16 : 1) > maxthr) break;
         if (update_lds<T, M>(g, yt) > 65536) break;
         best = yt;
     }
@@ -409,13 +426,13 @@ template <typename T, int M, int MODE>
 static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, hipStream_t s,
                               int *nblocks_out)
 {
-    const int nthr = update_threads(g, a.yt, M / 8);
+    const int nthr = update_threads(g, a.yt, M >= 16 ? M / 16 : 1);
     const size_t shm = update_lds<T, M>(g, a.yt);
     if (shm > 65536 || nthr > UpdMaxThreads<T>::v) return hipErrorInvalidConfiguration;
     dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
     hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, a, g,
-                       (const cpx<T> *)tw + M);
+                       (const cpx<T> *)tw);
     return hipGetLastError();
 }
 

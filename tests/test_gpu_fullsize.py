@@ -29,13 +29,17 @@ def _field(ctx, P, mask):
     return ctx.eval_field(mask).double().cpu().numpy()
 
 
-def test_film_uses_fused_path():
-    cfg = I.config("c2")
-    announce("c2 fused path selection")
+@pytest.mark.parametrize("name,fused", [("c2_small", 1), ("c2", 0)])
+def test_fft_path_selection(name, fused):
+    """The fused plane pass is chosen where one kx plane of the three
+    components fits one work-group's LDS (32x32x8 film), the three passes
+    where it does not (128x128x32 film)."""
+    cfg = I.config(name)
+    announce("%s fft path selection" % name)
     ctx = gpu_context(cfg, "f32")
     try:
         ctx.set_P(I.initial_P(cfg, 0, np.float32))
-        assert T.tdgl_get_fft_path(ctx.ctx) == 1
+        assert T.tdgl_get_fft_path(ctx.ctx) == fused
     finally:
         ctx.close()
 
