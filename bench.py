@@ -69,7 +69,8 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0):
+def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0, chunk=None,
+            kernel_reps=0):
     import numpy as np
     import torch
 
@@ -81,6 +82,8 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0):
     ctx = T.Context(cfg, precision, stream=stream, build_tensor=False)
     T.tdgl_set_fft_path(ctx.ctx, fft_path)
     T.tdgl_set_update_rows(ctx.ctx, rows)
+    if chunk is not None:
+        T.tdgl_set_graph_chunk(ctx.ctx, chunk)
     T.tdgl_build_tensor(ctx.ctx, cfg["mimg"])
     torch.cuda.synchronize()
     setup_s = time.time() - t0
@@ -99,12 +102,78 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0):
     ctx.sync()
     ms = ev0.elapsed_time(ev1)
     prof = T.tdgl_profile_step(ctx.ctx, profile_steps) if profile_steps else None
+    kprof = T.tdgl_profile_kernels(ctx.ctx, kernel_reps) if kernel_reps else None
     F, meanP = ctx.energies()
     dims = ctx.dims
     fused = T.tdgl_get_fft_path(ctx.ctx)
     ctx.close()
-    return dict(ms=ms, wall=wall, setup_s=setup_s, prof=prof, dims=dims, F=F, meanP=meanP,
-                fused=fused)
+    return dict(ms=ms, wall=wall, setup_s=setup_s, prof=prof, kprof=kprof, dims=dims, F=F,
+                meanP=meanP, fused=fused)
+
+
+def copy_calibration(mib=256, reps=3):
+    """A plain device copy of known size (torch's copy kernel), for scaling
+    the FETCH_SIZE / WRITE_SIZE counters: each launch reads and writes
+    mib MiB, far more than the L2 holds."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes": n * 4, "launches": reps}
+
+
+KERNEL_KEYS = {        # rocprofv3 kernel-name fragments of the step kernels
+    "y_forward": "k_row<float, 128, false>",
+    "z_tensor": "k_zmul<float, 64>",
+    "y_inverse": "k_row<float, 128, true>",
+    "update": "k_update<float, 128, 0>",
+}
+
+
+def _pmc_means(path, counter):
+    """Mean counter value (KiB) per dispatch, by kernel-name fragment, from a
+    rocprofv3 counter_collection.csv."""
+    import csv
+    sums, cnts = {}, {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row.get("Kernel_Name", "")
+            v = float(row["Counter_Value"])
+            for key, frag in list(KERNEL_KEYS.items()) + [("copy", "copy")]:
+                if frag in name.replace("  ", " "):
+                    sums[key] = sums.get(key, 0.0) + v
+                    cnts[key] = cnts.get(key, 0) + 1
+    return {k: sums[k] / cnts[k] for k in sums}, cnts
+
+
+def traffic_from(fetch_kernels, write_kernels, fetch_copy, write_copy, copy_bytes, out):
+    """HBM bytes per launch of each step kernel: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) scaled by the factor that maps the same counters of a
+    plain copy of copy_bytes onto copy_bytes."""
+    fk, fc = _pmc_means(fetch_kernels, "FETCH_SIZE")
+    wk, wc = _pmc_means(write_kernels, "WRITE_SIZE")
+    cf, _ = _pmc_means(fetch_copy, "FETCH_SIZE")
+    cw, _ = _pmc_means(write_copy, "WRITE_SIZE")
+    f_scale = copy_bytes / (cf["copy"] * 1024.0)
+    w_scale = copy_bytes / (cw["copy"] * 1024.0)
+    res = {"source_hash": source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "copy_bytes": copy_bytes, "bytes_per_launch": {}, "fetch_bytes": {},
+           "write_bytes": {}, "dispatches": {"fetch": fc, "write": wc}}
+    for k in KERNEL_KEYS:
+        if k in fk and k in wk:
+            fb, wb = fk[k] * 1024.0 * f_scale, wk[k] * 1024.0 * w_scale
+            res["fetch_bytes"][k] = fb
+            res["write_bytes"][k] = wb
+            res["bytes_per_launch"][k] = fb + wb
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
 
 
 def cpu_baseline(cfg, nsteps):
@@ -119,11 +188,13 @@ def cpu_baseline(cfg, nsteps):
     c["mimg"] = 0
     prob = O.Problem(c)
     P = I.initial_P(c, 0).astype(np.float64)
-    P = O.step_heun(P, prob, c["dtau"])          # first call outside the timing
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        P = O.step_heun(P, prob, c["dtau"])
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):            # BLAS / OpenMP pools: one thread
+        P = O.step_heun(P, prob, c["dtau"])      # first call outside the timing
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            P = O.step_heun(P, prob, c["dtau"])
+        dt = time.perf_counter() - t0
     ncell = int(np.prod(c["n"]))
     return dict(value=ncell * nsteps / dt, unit="cell-steps/s", cores=1, kind="oracle",
                 sample="%d Heun steps of the %dx%dx%d film (numpy FP64, single thread; "
@@ -139,16 +210,37 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2000)
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--c4-steps", type=int, default=200,
+                    help="FP32 Heun steps of the 256x256x64 open bilayer (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fft-path", type=int, default=0, help="0 auto (fused if it fits), 1 three passes")
     ap.add_argument("--rows", type=int, default=0, help="update-kernel rows per group (0 auto)")
+    ap.add_argument("--graph-chunk", type=int, default=None,
+                    help="steps per captured graph (0: plain launches; default: library's)")
+    ap.add_argument("--kernel-reps", type=int, default=200,
+                    help="launches per kernel in the per-kernel timing graphs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy used to scale the traffic counters")
+    ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV",
+                                                         "COPY_FETCH_CSV", "COPY_WRITE_CSV",
+                                                         "COPY_BYTES"),
+                    help="turn rocprofv3 counter CSVs into profiles/traffic_c2_fp32.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        a = args.traffic_from
+        res = traffic_from(a[0], a[1], a[2], a[3], int(a[4]),
+                           os.path.join(ROOT, "profiles", "traffic_c2_fp32.json"))
+        print(json.dumps(res["bytes_per_launch"]))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (each simulation fits one "
               "MI355X; --gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.steps < 1:
         sys.exit("--steps must be >= 1")
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration()), flush=True)
+        return
 
     import paper_2605_28800_amd as T
     if not os.path.exists(T.LIB_PATH):
@@ -160,20 +252,22 @@ def main():
     ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     log("fp32 run: %d warmup + %d timed Heun steps" % (args.warmup, args.steps))
     r32 = run_gpu(cfg, T.TDGL_FP32, args.steps, args.warmup, args.profile_steps,
-                  args.fft_path, args.rows)
+                  args.fft_path, args.rows, args.graph_chunk, args.kernel_reps)
     ms_step = r32["ms"] / args.steps
     value = ncell * args.steps / (r32["ms"] / 1e3)
     log("fp32: %.4f ms/step, %.3e cell-steps/s (wall %.3f s, setup %.2f s, fused=%d)"
         % (ms_step, value, r32["wall"], r32["setup_s"], r32["fused"]))
 
-    if r32["prof"] is None:
+    if r32["prof"] is None or r32["kprof"] is None:
         print(json.dumps({"metric": "TDGL cell-steps/s", "value": value, "unit": "cell-steps/s",
                           "ms_per_step": ms_step, "note": "profiling leg skipped"}), flush=True)
         return
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: mean launch durations from graphs of
+    # back-to-back launches of each kernel (HIP events on the library stream)
     kb = kernel_bytes(r32["dims"], 4)
     names = ["y_forward", "z_tensor", "y_inverse", "update_predictor", "update_corrector"]
-    prof = dict(zip(names, r32["prof"]))
+    prof = dict(zip(names, r32["kprof"]))
+    prof_ev = dict(zip(names, r32["prof"]))
     per_step = {"y_forward": 2 * prof["y_forward"], "z_tensor": 2 * prof["z_tensor"],
                 "y_inverse": 2 * prof["y_inverse"],
                 "update": prof["update_predictor"] + prof["update_corrector"]}
@@ -191,7 +285,8 @@ def main():
         tj = json.load(open(tfile))
         if tj.get("source_hash") == source_hash() and dom in tj.get("bytes_per_launch", {}):
             traffic = tj["bytes_per_launch"][dom]
-    kernels = {k: {"ms": round(prof[k], 5), "alg_bytes": kb[k],
+    kernels = {k: {"ms": round(prof[k], 5), "ms_eager_events": round(prof_ev[k], 5),
+                   "alg_bytes": kb[k],
                    "GBps": round(kb[k] / (prof[k] * 1e-3) / 1e9, 1) if prof[k] else None}
                for k in names}
     step_bytes = survey_bytes_per_cell_step(r32["dims"], 4)
@@ -207,6 +302,26 @@ def main():
                 "roofline_frac_step": v64 * survey_bytes_per_cell_step(r64["dims"], 8)
                 / (HBM_PEAK_GBS * 1e9)}
         log("fp64: %.4f ms/step, %.3e cell-steps/s" % (fp64["ms_per_step"], v64))
+
+    c4 = None
+    if args.c4_steps > 0:
+        cfg4 = I.config("c4")
+        n4 = cfg4["n"][0] * cfg4["n"][1] * cfg4["n"][2]
+        log("c4 fp32 run: %d timed Heun steps" % args.c4_steps)
+        r4 = run_gpu(cfg4, T.TDGL_FP32, args.c4_steps, 20, 0, kernel_reps=20)
+        v4 = n4 * args.c4_steps / (r4["ms"] / 1e3)
+        b4 = survey_bytes_per_cell_step(r4["dims"], 4)
+        kb4 = kernel_bytes(r4["dims"], 4)
+        k4 = {k: {"ms": round(ms, 5), "alg_bytes": kb4[k],
+                  "GBps": round(kb4[k] / (ms * 1e-3) / 1e9, 1) if ms else None}
+              for k, ms in zip(names, r4["kprof"])}
+        c4 = {"workload": "PbTiO3/SrTiO3 bilayer 256x256x64 (48+16 layers), open, padded "
+                          "512x512x128, uniform random start, all terms, Heun dtau=1e-3",
+              "value": v4, "unit": "cell-steps/s", "steps": args.c4_steps,
+              "ms_per_step": r4["ms"] / args.c4_steps, "bytes_per_cell_step": round(b4, 1),
+              "roofline_frac_step": round(v4 * b4 / (HBM_PEAK_GBS * 1e9), 4), "kernels": k4}
+        log("c4: %.4f ms/step, %.3e cell-steps/s, step roofline %.3f"
+            % (c4["ms_per_step"], v4, c4["roofline_frac_step"]))
 
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:
@@ -238,6 +353,7 @@ def main():
                      "alg_bytes_per_launch": dom_bytes, "mean_launch_ms": dom_ms},
         "cpu_baseline": cpu,
         "fp64": fp64,
+        "c4_large_grid": c4,
         "kernels": kernels,
         "step_roofline": {"bytes_per_cell_step": round(step_bytes, 1),
                           "frac": round(value * step_bytes / (HBM_PEAK_GBS * 1e9), 4),

@@ -234,6 +234,18 @@ tdgl_status tdgl_get_reduced(const tdgl_ctx *ctx, double *coef, double scal[8]);
  * For benchmarks and profiling; the state advances like tdgl_step. */
 tdgl_status tdgl_profile_step(tdgl_ctx *ctx, int nsteps, double ms_out[5]);
 
+/* Time every kernel of one field evaluation on its own: for each kernel a
+ * HIP graph of nrep launches of that kernel alone, on the context's live
+ * buffers, is replayed once to warm up and once between two HIP events on
+ * the context's stream; ms_out[5] receives the mean duration (ms) per launch
+ * in the order of tdgl_profile_step (0 for kernels the configuration does
+ * not use).  The kernels then run back to back as in a step, without
+ * event markers between them.  P is saved before and restored after, the
+ * non-finite flag is kept, and the next step rebuilds its spectra, so the
+ * simulation state is unchanged; intermediate spectra are not.  Allocates
+ * and frees one P-sized device buffer; synchronising.  1 <= nrep <= 100000. */
+tdgl_status tdgl_profile_kernels(tdgl_ctx *ctx, int nrep, double ms_out[5]);
+
 /* Wait for all work of the context; returns TDGL_E_NONFINITE if a step
  * produced a non-finite P. */
 tdgl_status tdgl_sync(tdgl_ctx *ctx);

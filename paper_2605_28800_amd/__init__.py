@@ -78,6 +78,7 @@ _SIGS = {
     "tdgl_energies": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_get_reduced": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_profile_step": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
+    "tdgl_profile_kernels": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_set_fft_path": ([_ctx_p, c_int], c_int),
     "tdgl_get_fft_path": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_set_update_rows": ([_ctx_p, c_int], c_int),
@@ -245,6 +246,12 @@ def tdgl_get_reduced(ctx, nz: int):
 def tdgl_profile_step(ctx, nsteps: int):
     ms = (c_double * 5)()
     _check(ctx, lib().tdgl_profile_step(ctx, nsteps, ms))
+    return tuple(ms)
+
+
+def tdgl_profile_kernels(ctx, nrep: int):
+    ms = (c_double * 5)()
+    _check(ctx, lib().tdgl_profile_kernels(ctx, nrep, ms))
     return tuple(ms)
 
 

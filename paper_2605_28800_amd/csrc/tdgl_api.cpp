@@ -1011,6 +1011,94 @@ tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
     return TDGL_OK;
 }
 
+tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
+{
+    if (!c) return TDGL_E_ARG;
+    if (!ms_out || nrep < 1 || nrep > 100000)
+        return fail(c, TDGL_E_ARG, "need 1 <= nrep <= 100000 and ms_out");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    const bool el = elec_on(c);
+    if (el && !c->tensor_built)
+        return fail(c, TDGL_E_STATE, "electrostatic term on but tensor not built");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    for (int q = 0; q < 5; ++q) ms_out[q] = 0.0;
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int flag0 = 0;
+    HIP_TRY(c, hipMemcpy(&flag0, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+    const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->esz;
+    void *save = nullptr;
+    HIP_TRY(c, hipMalloc(&save, pbytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipMemcpyAsync(save, c->P[c->cur], pbytes, hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    void *A = c->P[c->cur], *B = c->P[1 - c->cur];
+    const Geom &g = c->g;
+    const long long nl = (long long)g.hx * 3 * g.nz;
+    const unsigned t = c->terms;
+    // one kernel, nrep times, as one graph; returns ms per launch
+    auto time_kernel = [&](int which, double *out) -> hipError_t {
+        auto launch = [&](hipStream_t s) -> hipError_t {
+            switch (which) {
+            case 0:
+                if (c->use_plane)
+                    return launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, s, false);
+                return launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
+                                  tw(c), s);
+            case 1: return launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), s);
+            case 2:
+                return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny,
+                                  tw(c), s);
+            case 3: return enq_upd(c, UPD_STEP, A, nullptr, B, 0, t, el, el, s);
+            default: return enq_upd(c, UPD_STEP, B, A, A, 1, t, el, el, s);
+            }
+        };
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t r = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+        if (r != hipSuccess) return r;
+        hipError_t le = hipSuccess;
+        for (int i = 0; i < nrep && le == hipSuccess; ++i) le = launch(c->cap);
+        r = hipStreamEndCapture(c->cap, &graph);
+        if (le != hipSuccess) r = le;
+        if (r == hipSuccess) r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (r == hipSuccess) r = hipGraphLaunch(exec, c->stream);
+        if (r == hipSuccess) r = hipEventRecord(e0, c->stream);
+        if (r == hipSuccess) r = hipGraphLaunch(exec, c->stream);
+        if (r == hipSuccess) r = hipEventRecord(e1, c->stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+        float ms = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (r == hipSuccess) *out = (double)ms / nrep;
+        return r;
+    };
+    // the update first (it reads the live spectra), the y passes next (each
+    // launch recomputes the same output), the in-place z pass last
+    if (he == hipSuccess) he = time_kernel(3, &ms_out[3]);
+    if (he == hipSuccess && c->scheme == TDGL_HEUN) he = time_kernel(4, &ms_out[4]);
+    if (el) {
+        if (he == hipSuccess) he = time_kernel(0, &ms_out[0]);
+        if (he == hipSuccess && !c->use_plane) he = time_kernel(2, &ms_out[2]);
+        if (he == hipSuccess && !c->use_plane) he = time_kernel(1, &ms_out[1]);
+    }
+    // restore P and the flag whatever happened above
+    hipError_t re = hipMemcpyAsync(c->P[c->cur], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+    if (re == hipSuccess)
+        re = hipMemcpyAsync(c->flag, &flag0, sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (re == hipSuccess) re = hipStreamSynchronize(c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    c->spec_valid = false;
+    if (he != hipSuccess) return fail(c, TDGL_E_HIP, "kernel profile: %s", hipGetErrorString(he));
+    if (re != hipSuccess) return fail(c, TDGL_E_HIP, "state restore: %s", hipGetErrorString(re));
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_sync(tdgl_ctx *c)
 {
     if (!c) return TDGL_E_ARG;

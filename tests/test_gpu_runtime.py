@@ -172,3 +172,26 @@ def test_device_set_get_and_precision_conversion():
         assert np.array_equal(ctx.get_P(), P.astype(np.float32).astype(np.float64))
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("name,path", [("c2_small", 0), ("c2_small", 1)])
+def test_kernel_profile_keeps_the_state(name, path):
+    """tdgl_profile_kernels times every kernel and leaves the run as it was:
+    the trajectory continues bit for bit."""
+    cfg = I.config(name)
+    announce("kernel profile %s path %d" % (name, path))
+    ref = _run(cfg, "f32", 60, path=path)
+    ctx = gpu_context(cfg, "f32", path=path)
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        ctx.step(30)
+        ms = T.tdgl_profile_kernels(ctx.ctx, 5)
+        fused = T.tdgl_get_fft_path(ctx.ctx)
+        ctx.step(30)
+        got = ctx.get_P(T.TDGL_FP32)
+    finally:
+        ctx.close()
+    used = [0, 3, 4] if fused else [0, 1, 2, 3, 4]
+    assert all(ms[i] > 0 for i in used), ms
+    assert all(ms[i] == 0 for i in range(5) if i not in used), ms
+    assert np.array_equal(ref, got)
