@@ -97,7 +97,8 @@ int tdgl_abi_version(void);
  * (arithmetic of the step; tensor construction and energy sums are always
  * FP64).  hip_stream: a hipStream_t (NULL = default stream).  No device
  * memory is touched until the first call that needs it.
- * Errors: TDGL_E_ARG (bad sizes or mask), TDGL_E_UNSUPPORTED (FFT length). */
+ * Errors: TDGL_E_ARG (bad sizes or mask), TDGL_E_UNSUPPORTED (FFT length,
+ * or 2^31 cells or more). */
 tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream,
                         tdgl_ctx **out);
 
@@ -182,8 +183,8 @@ tdgl_status tdgl_set_graph_chunk(tdgl_ctx *ctx, int steps);
 tdgl_status tdgl_set_fft_path(tdgl_ctx *ctx, int path);
 tdgl_status tdgl_get_fft_path(const tdgl_ctx *ctx, int *fused);
 
-/* Rows of one z layer handled by one work-group of the update kernel (even,
- * 2..64; 0 restores the built-in choice).  A tuning knob: results do not
+/* Rows of one z layer handled by one work-group of the update kernel (a
+ * power of two, 2..64; 0 restores the built-in choice).  A tuning knob: results do not
  * depend on it.  Launches that would exceed the device's work-group limits
  * fail with TDGL_E_HIP at the next step. */
 tdgl_status tdgl_set_update_rows(tdgl_ctx *ctx, int rows);

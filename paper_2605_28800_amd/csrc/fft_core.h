@@ -251,20 +251,38 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, i
     }
 }
 
+// Work-groups of a launch are dealt round-robin to the eight XCDs of the
+// chip, each with its own L2.  xcd_tile maps the linear work-group index b
+// (of n) to a tile index such that every XCD receives one contiguous range
+// of tiles, so tiles that share cache lines (neighbouring rows, mirrored
+// tensor columns) meet in the same L2.  A bijection of [0, n).
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned n)
+{
+    constexpr unsigned X = 8;
+    const unsigned q = n / X, r = n % X;
+    const unsigned x = b % X, i = b / X;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Real lines through complex transforms of half length.  A real line x of M
 // points is the complex line z[n] = x[2n] + i x[2n+1] of M/2 points; with
 // Z = DFT_{M/2}(z), E[k] = (Z[k] + conj Z[M/2-k])/2 and
 // O[k] = (Z[k] - conj Z[M/2-k])/(2i) are the DFTs of the even and odd samples,
 // and X[k] = E[k] + W_M^k O[k], X[k + M/2] = E[k] - W_M^k O[k].
 // real_split returns X[k] and sets xh = X[k + M/2] (needed at k = 0 only).
+// Both helpers round every operation separately (no contraction into FMAs),
+// so that a spectrum computed here does not depend on which of the results
+// the calling kernel keeps: the x pass and the update kernel's forward
+// transform must agree bit for bit.
 template <typename T>
 __device__ __forceinline__ cpx<T> real_split(cpx<T> zk, cpx<T> zm, cpx<T> wk, cpx<T> &xh)
 {
+#pragma clang fp contract(off)
     const cpx<T> ev = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     const cpx<T> od = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
-    const cpx<T> wo = cmul(od, wk);
-    xh = csub(ev, wo);
-    return cadd(ev, wo);
+    const cpx<T> wo = {od.x * wk.x - od.y * wk.y, od.x * wk.y + od.y * wk.x};
+    xh = {ev.x - wo.x, ev.y - wo.y};
+    return {ev.x + wo.x, ev.y + wo.y};
 }
 
 // The inverse: from the half spectrum X[0..M/2] of a real line (a = X[k],
@@ -274,8 +292,10 @@ __device__ __forceinline__ cpx<T> real_split(cpx<T> zk, cpx<T> zm, cpx<T> wk, cp
 template <typename T>
 __device__ __forceinline__ cpx<T> real_merge(cpx<T> a, cpx<T> b, cpx<T> wk)
 {
+#pragma clang fp contract(off)
     const cpx<T> e = {a.x + b.x, a.y - b.y};
-    const cpx<T> d = cmulc(cpx<T>{a.x - b.x, a.y + b.y}, wk);
+    const cpx<T> f = {a.x - b.x, a.y + b.y};
+    const cpx<T> d = {f.x * wk.x + f.y * wk.y, f.y * wk.x - f.x * wk.y};   // f conj(wk)
     return {e.x - d.y, e.y + d.x};
 }
 

@@ -192,46 +192,79 @@ __device__ __forceinline__ void tensor_row(const T *__restrict__ Nt, int kx, int
 
 // ------------------------------------------------- z pass with multiply
 // S: [hx][3][nz][my] complex (in place); work-group = (kx, tile of CT ky
-// columns) x 3 components.
-template <typename T>
-struct ZmulMaxThreads {   // FP64 groups stay small so a wave may hold 256 VGPRs
-    static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
+// columns) x 3 components.  Columns per group: 128-byte rows where threads
+// (<= 1024 FP32 / 512 FP64) and LDS (<= 64 KiB) allow.
+template <typename T, int MZ>
+struct ZmulCfg {
+    static constexpr int TPL = MZ / 8;
+    static constexpr int MAXT = sizeof(T) == 8 ? 512 : 1024;
+    static constexpr int fit(int ct)
+    {
+        return (ct > 1 && (3 * ct * TPL > MAXT ||
+                           (size_t)3 * ct * LinePad<MZ>::len * sizeof(cpx<T>) > 65536))
+                   ? fit(ct / 2)
+                   : ct;
+    }
+    static constexpr int CT = fit(128 / (int)sizeof(cpx<T>));
+    static constexpr int NTHR = 3 * CT * TPL;
 };
 
 template <typename T, int MZ>
-__global__ void __launch_bounds__(ZmulMaxThreads<T>::v)
-    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int CT,
-           const cpx<T> *__restrict__ tw)
+__global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
+    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, const cpx<T> *__restrict__ tw)
 {
-    constexpr int TPL = MZ / 8;
+    using C = ZmulCfg<T, MZ>;
+    constexpr int TPL = C::TPL, CT = C::CT;
+    constexpr int LZ = LinePad<MZ>::len;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     const int tid = threadIdx.x;
     const int cc = tid % CT;
     const int t = (tid / CT) % TPL;
     const int c = tid / (CT * TPL);
-    const int kx = blockIdx.y;
-    const int ky = blockIdx.x * CT + cc;
+    const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int kx = (int)(tile / gridDim.x);
+    const int ky = (int)(tile % gridDim.x) * CT + cc;
     const bool act = ky < my;
-    const long long zst = my;
-    cpx<T> *col = S + ((long long)kx * 3 + c) * nz * zst + (act ? ky : 0);
-    TwReg<T, MZ> tr;
-    twiddle_load(tr, tw, t);
+    const int kyc = act ? ky : 0;
+    // uniform bases, unsigned 32-bit offsets within one kx plane
+    cpx<T> *plane = S + (long long)kx * 3 * nz * my;
+    const int hy = my / 2 + 1, hz = MZ / 2 + 1;
+    const unsigned qs = (unsigned)hz * hy;
+    const T *tplane = Nt + (long long)kx * 6 * qs;
+    const unsigned col = (unsigned)(c * nz) * my + kyc;
     // data first: the forward transform waits for these loads only, the
     // tensor loads behind them complete during the transform
     cpx<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
-        v[q] = (act && z < nz) ? col[(long long)z * zst] : cpx<T>{T(0), T(0)};
+        v[q] = (act && z < nz) ? plane[col + (unsigned)z * my] : cpx<T>{T(0), T(0)};
     }
-    const TensorRow trow(c, 0);
-    const int kyc = act ? ky : 0;
+    // row c of the tensor: components (c,x) (c,y) (c,z) of the octant store
+    // Nt[kx][comp][kz'][ky'] (comp: xx yy zz xy xz yz); xy is odd in ky, xz
+    // odd in kz, yz odd in both
+    const int i0 = c == 0 ? 0 : (c == 1 ? 3 : 4);
+    const int i1 = c == 0 ? 3 : (c == 1 ? 1 : 5);
+    const int i2 = c == 0 ? 4 : (c == 1 ? 5 : 2);
+    const bool yneg = kyc > my / 2;
+    const unsigned kyo = yneg ? my - kyc : kyc;
+    auto ysign = [&](int i) { return (yneg && (i == 3 || i == 5)) ? T(-1) : T(1); };
+    const T ys0 = ysign(i0), ys1 = ysign(i1), ys2 = ysign(i2);
+    const bool zo0 = i0 == 4 || i0 == 5, zo1 = i1 == 4 || i1 == 5, zo2 = i2 == 4 || i2 == 5;
+    const unsigned o0 = i0 * qs + kyo, o1 = i1 * qs + kyo, o2 = i2 * qs + kyo;
     T nrow[8][3];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        tensor_row(Nt, kx, kyc, t + q * TPL, my, MZ, trow, nrow[q][0], nrow[q][1], nrow[q][2]);
-    constexpr int LZ = LinePad<MZ>::len;
+    for (int q = 0; q < 8; ++q) {
+        const int kz = t + q * TPL;
+        const bool zneg = kz > MZ / 2;
+        const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy;
+        nrow[q][0] = tplane[o0 + kzo] * ((zneg && zo0) ? -ys0 : ys0);
+        nrow[q][1] = tplane[o1 + kzo] * ((zneg && zo1) ? -ys1 : ys1);
+        nrow[q][2] = tplane[o2 + kzo] * ((zneg && zo2) ? -ys2 : ys2);
+    }
+    TwReg<T, MZ> tr;
+    twiddle_load(tr, tw, t);
     const IdxStridePad ip{CT};
     cpx<T> *L = lds + c * LZ * CT + cc;
     fft_line<T, MZ, false>(v, L, ip, t, tr, act);
@@ -257,7 +290,7 @@ __global__ void __launch_bounds__(ZmulMaxThreads<T>::v)
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
-        if (act && z < nz) col[(long long)z * zst] = v[q];
+        if (act && z < nz) plane[col + (unsigned)z * my] = v[q];
     }
 }
 
@@ -522,16 +555,12 @@ template <typename T, int MZ>
 static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *tw,
                             hipStream_t s)
 {
-    constexpr int TPL = MZ / 8;
-    int ct = 128 / (int)sizeof(cpx<T>);
-    while (ct > 1 && (3 * ct * TPL > ZmulMaxThreads<T>::v ||
-                      (size_t)3 * ct * LinePad<MZ>::len * sizeof(cpx<T>) > 65536))
-        ct /= 2;
-    const int gx = (g.my + ct - 1) / ct;
+    using C = ZmulCfg<T, MZ>;
+    const int gx = (g.my + C::CT - 1) / C::CT;
     if (g.hx > 65535) return hipErrorInvalidValue;
-    const size_t shm = (size_t)3 * ct * LinePad<MZ>::len * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx), dim3(3 * ct * TPL), shm, s,
-                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, ct, (const cpx<T> *)tw + MZ);
+    const size_t shm = (size_t)3 * C::CT * LinePad<MZ>::len * sizeof(cpx<T>);
+    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx), dim3(C::NTHR), shm, s, (cpx<T> *)S,
+                       (const T *)Nt, g.nz, g.my, (const cpx<T> *)tw + MZ);
     return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ struct UpdArgs {
     const void *P_in;      // state the field is evaluated at
     const void *P_old;     // Heun corrector: state at the start of the step
     void *P_out;           // new state (STEP) or field (FIELD)
-    void *S1;              // x-spectra rows [3][nz][ny][hx]: field in, new P spectrum out
+    void *S1;              // x spectra, kx-major [hx][3][nz][ny]: field in, new P spectrum out
     const void *coef;      // [nz][NCOEF]
     const void *kp;        // KParams<T>
     double *partials;      // ENERGY: [grid][8]

@@ -489,6 +489,9 @@ tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream, 
     const double d[3] = {grid->dx, grid->dy, grid->dz};
     for (int k = 0; k < 3; ++k) {
         if (n[k] < 1 || n[k] > 4096) return TDGL_E_ARG;
+    }
+    if ((long long)n[0] * n[1] * n[2] >= (1LL << 31)) return TDGL_E_UNSUPPORTED;
+    for (int k = 0; k < 3; ++k) {
         if (!(d[k] > 0.0) || !std::isfinite(d[k])) return TDGL_E_ARG;
     }
     const unsigned pm = grid->periodic_mask;
@@ -755,7 +758,8 @@ tdgl_status tdgl_set_fft_path(tdgl_ctx *c, int path)
 tdgl_status tdgl_set_update_rows(tdgl_ctx *c, int rows)
 {
     if (!c) return TDGL_E_ARG;
-    if (rows < 0 || rows > 64 || (rows & 1)) return fail(c, TDGL_E_ARG, "rows must be even, 0..64");
+    if (rows < 0 || rows > 64 || rows == 1 || (rows & (rows - 1)))
+        return fail(c, TDGL_E_ARG, "rows must be 0 or a power of two in 2..64");
     const int yt = rows == 0 ? update_rows_per_block(c->prec, c->g) : rows;
     // the launch checks threads and LDS; probe with a zero-size query here
     const int nb = ((c->g.ny + yt - 1) / yt) * c->g.nz;

@@ -55,32 +55,32 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
 {
     // The x transforms of real rows run as complex transforms of length M/2
-    // (real_split / real_merge).
+    // (real_split / real_merge).  Line l = c*yt + yy (component c, row yy)
+    // is owned by TPL consecutive lanes of one wave; the partner values
+    // X[M/2-k] and Z[M/2-k] of the split and the merge come from the lane
+    // TPL - t of the same line (lane permutes, no LDS round trip).
     constexpr int M2 = M / 2;
     constexpr int PPT = HalfLine<M2>::PPT;     // points per thread
     constexpr int TPL = HalfLine<M2>::TPL;     // threads per row
     constexpr int LEN = LinePad<M2>::len;
     constexpr int CPT = 2;                     // cells per thread, at most
+    static_assert(64 % TPL == 0, "a line must not straddle waves");
     extern __shared__ unsigned char smem_raw[];
-    const int yt = a.yt;
-    const int nrows = 3 * yt;                  // (component, row) lines
+    const int yt = a.yt;                       // a power of two
+    const int ysh = __ffs(yt) - 1;
+    const int nrows = 3 * yt;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int z = blockIdx.y, y0 = blockIdx.x * yt;
-    const int nx = g.nx, ny = g.ny, nz = g.nz, hx = g.hx;
-    // LDS: region A = spectra staging raw[(k*3 + c)*RS + yy] (RS = yt + 1),
-    // also the rows hs[(c*yt + yy)*HS + x] (HS = nx + 1); region B = FFT
-    // scratch per line (and the forward exchange zx[line*M2 + k]).
-    const int RS = yt + 1, HS = nx + 1;
-    size_t abytes = (size_t)hx * 3 * RS * sizeof(cpx<T>);
-    const size_t hbytes = (size_t)nrows * HS * sizeof(T);
-    if (hbytes > abytes) abytes = hbytes;
-    abytes = (abytes + 15) / 16 * 16;
-    cpx<T> *raw = reinterpret_cast<cpx<T> *>(smem_raw);
+    const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int z = (int)(tile / gridDim.x), y0 = (int)(tile % gridDim.x) * yt;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    // LDS: rows hs[(c*yt + yy)*HS + x] (HS = nx + 2, even, so that (even,
+    // odd) sample pairs are 8-byte aligned), then the FFT scratch per line.
+    const int HS = nx + 2;
+    const size_t hbytes = ((size_t)nrows * HS * sizeof(T) + 15) / 16 * 16;
     T *hs = reinterpret_cast<T *>(smem_raw);
-    cpx<T> *scr = reinterpret_cast<cpx<T> *>(smem_raw + abytes);
-    const long long plane = (long long)ny * nx;
+    cpx<T> *scr = reinterpret_cast<cpx<T> *>(smem_raw + hbytes);
+    const int plane = ny * nx;                 // components hold < 2^31 cells
     const long long comp = (long long)nz * plane;
-    const T *Pin = reinterpret_cast<const T *>(a.P_in);
     const T *coefz = reinterpret_cast<const T *>(a.coef) + (long long)z * NCOEF;
     const KParams<T> *kp = reinterpret_cast<const KParams<T> *>(a.kp);
     const bool material = coefz[8] != T(0);
@@ -88,15 +88,18 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
     const int ny_here = ny - y0 < yt ? ny - y0 : yt;
 
-    // line mapping of the x transforms: line = c*yt + yy
+    // line roles
     const int l = tid / TPL, t = tid - l * TPL;
     const bool lact = l < nrows;
-    const int lc = lact ? l / yt : 0, lyy = lact ? l - lc * yt : 0;
+    const int lc = lact ? l >> ysh : 0, lyy = lact ? l & (yt - 1) : 0;
+    const bool has = lact && lyy < ny_here;
+    const int lane = tid & 63;
+    const int partner = (lane - t) + ((TPL - t) & (TPL - 1));
     cpx<T> *L = scr + (lact ? l : 0) * LEN;
     cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
-    auto s1_index = [&](int kc, int yy) -> long long {
-        return ((long long)kc * nz + z) * ny + y0 + yy;
-    };
+    const long long kst = 3LL * nz * ny;       // S1 stride between kx
+    cpx<T> *s1row = S1 + ((long long)lc * nz + z) * ny + y0 + (has ? lyy : 0);
+
     // ---- prologue: issue the global loads up front
     TwReg<T, M2> tr;
     cpx<T> wk[8];                              // W_M^k, k = t + q*TPL
@@ -105,107 +108,91 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
 #pragma unroll
         for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
     }
-    // spectra of the group: the first RPT*nthr elements are loaded into
-    // registers as one batch of independent loads, stored to LDS only after
-    // the cell loads below have been issued
-    constexpr int RPT = 4;
-    const int nraw = hx * 3 * yt;
-    cpx<T> rv[RPT];
+    // spectrum X[k], k = t + q*TPL, of this thread's row; lane t = 0 also
+    // reads X[M/2]
+    cpx<T> xa[8], xn = {T(0), T(0)};
     if (a.elec_in) {
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int e = tid + j * nthr;
-            const int kc = e / yt, yy = e - kc * yt;
-            rv[j] = (e < nraw && yy < ny_here) ? S1[s1_index(kc, yy)] : cpx<T>{T(0), T(0)};
-        }
+        for (int q = 0; q < PPT; ++q)
+            xa[q] = has ? s1row[(long long)(t + q * TPL) * kst] : cpx<T>{T(0), T(0)};
+        if (has && t == 0) xn = s1row[(long long)M2 * kst];
     }
-    // z neighbours exist if in range (or periodic) and not vacuum
-    const T *coefzm = z > 0 ? coefz - NCOEF : (g.pz ? coefz + (long long)(nz - 1) * NCOEF : nullptr);
-    const T *coefzp = z < nz - 1 ? coefz + NCOEF : (g.pz ? coefz - (long long)(nz - 1) * NCOEF : nullptr);
-    const bool hzm = coefzm && coefzm[8] != T(0);
-    const bool hzp = coefzp && coefzp[8] != T(0);
-    const long long dzm = z > 0 ? -plane : (long long)(nz - 1) * plane;
-    const long long dzp = z < nz - 1 ? plane : -(long long)(nz - 1) * plane;
-    const T *Pold = reinterpret_cast<const T *>(a.P_old);
+    // cells: centre, neighbours (-x +x -y +y -z +z; a missing neighbour is
+    // the centre itself, so its difference vanishes), old state
+    const int zm = z > 0 ? z - 1 : (g.pz ? nz - 1 : -1);
+    const int zp = z < nz - 1 ? z + 1 : (g.pz ? 0 : -1);
+    const T *coef0 = reinterpret_cast<const T *>(a.coef);
+    const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
+    const bool hzp = zp >= 0 && coef0[(long long)zp * NCOEF + 8] != T(0);
     const bool need_nb = material && (terms & T_GRAD);
-    // per cell: centre, neighbours (-x +x -y +y -z +z; a missing neighbour
-    // holds the centre value, so its difference vanishes), old state
+    const bool need_old = MODE == UPD_STEP && a.stage == 1;
+    const T *Pin0 = reinterpret_cast<const T *>(a.P_in);
+    const T *Pold0 = reinterpret_cast<const T *>(a.P_old);
+    const T *Pc[3] = {Pin0, Pin0 + comp, Pin0 + 2 * comp};
+    const unsigned nx_div = 0xffffffffu / (unsigned)nx + 1u;   // e / nx for e < 2^16
     T cp[CPT][3], cn[CPT][6][3], co[CPT][3];
     bool cok[CPT];
-    long long ccell[CPT];
-    int cyy[CPT], cx[CPT];
+    int cyy[CPT], cx[CPT], coff[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
-        const int e = tid + i * nthr;
-        const int yy = e / nx, x = e - yy * nx, y = y0 + yy;
-        cok[i] = e < yt * nx && y < ny;
+        const unsigned e = tid + i * nthr;
+        const int yy = nx == 1 ? (int)e : (int)__umulhi(e, nx_div);
+        const int x = (int)e - yy * nx, y = y0 + yy;
+        cok[i] = yy < ny_here;
+        const int yc = cok[i] ? y : y0, xc = cok[i] ? x : 0;   // a valid cell for the tail
         cyy[i] = yy;
         cx[i] = x;
-        const long long cell = (long long)z * plane + (long long)y * nx + x;
-        ccell[i] = cell;
-        if (!cok[i]) continue;
+        const int off = z * plane + yc * nx + xc;
+        coff[i] = off;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) cp[i][c] = Pin[c * comp + cell];
+        for (int c = 0; c < 3; ++c) cp[i][c] = Pc[c][off];
         if (need_nb) {
-            int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-            bool hxm = true, hxp = true, hym = true, hyp = true;
-            if (xm < 0) { if (g.px) xm += nx; else hxm = false; }
-            if (xp >= nx) { if (g.px) xp -= nx; else hxp = false; }
-            if (ym < 0) { if (g.py) ym += ny; else hym = false; }
-            if (yp >= ny) { if (g.py) yp -= ny; else hyp = false; }
-            const long long rowz = (long long)z * plane;
-            const long long nbc[6] = {rowz + (long long)y * nx + xm, rowz + (long long)y * nx + xp,
-                                      rowz + (long long)ym * nx + x, rowz + (long long)yp * nx + x,
-                                      cell + dzm, cell + dzp};
-            const bool nbh[6] = {hxm, hxp, hym, hyp, hzm, hzp};
+            const int xm = xc > 0 ? off - 1 : (g.px ? off + nx - 1 : off);
+            const int xp = xc < nx - 1 ? off + 1 : (g.px ? off - nx + 1 : off);
+            const int ym = yc > 0 ? off - nx : (g.py ? off + plane - nx : off);
+            const int yp = yc < ny - 1 ? off + nx : (g.py ? off - plane + nx : off);
+            const int zmo = hzm ? off + (zm - z) * plane : off;
+            const int zpo = hzp ? off + (zp - z) * plane : off;
+            const int nb[6] = {xm, xp, ym, yp, zmo, zpo};
 #pragma unroll
             for (int d = 0; d < 6; ++d)
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    cn[i][d][c] = nbh[d] ? Pin[c * comp + nbc[d]] : cp[i][c];
+                for (int c = 0; c < 3; ++c) cn[i][d][c] = Pc[c][nb[d]];
         }
-        if (MODE == UPD_STEP && a.stage == 1) {
+        if (need_old) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) co[i][c] = Pold[c * comp + cell];
+            for (int c = 0; c < 3; ++c) co[i][c] = Pold0[c * comp + off];
         }
     }
 
     // ---- 1. electrostatic field rows (inverse x transform, half length)
     if (a.elec_in) {
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int e = tid + j * nthr;
-            const int kc = e / yt, yy = e - kc * yt;
-            if (e < nraw) raw[kc * RS + yy] = rv[j];
-        }
-        for (int e = tid + RPT * nthr; e < nraw; e += nthr) {     // long rows only
-            const int kc = e / yt, yy = e - kc * yt;
-            raw[kc * RS + yy] = yy < ny_here ? S1[s1_index(kc, yy)] : cpx<T>{T(0), T(0)};
-        }
-        __syncthreads();
         cpx<T> v[8];
-        const bool has = lact && lyy < ny_here;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            const int k = t + q * TPL;                 // 0 .. M2-1
-            const int km = M2 - k;                     // 1 .. M2
-            cpx<T> A = has ? raw[(k * 3 + lc) * RS + lyy] : cpx<T>{T(0), T(0)};
-            cpx<T> B = has ? raw[(km * 3 + lc) * RS + lyy] : cpx<T>{T(0), T(0)};
-            if (k == 0) {                              // X[0], X[M/2] are real
+            // X[M2 - k]: lane TPL - t, point PPT-1-q; for t = 0 it is this
+            // lane's point PPT - q (or X[M2] at q = 0)
+            const int qs = PPT - 1 - q;
+            cpx<T> b = {__shfl(xa[qs].x, partner, 64), __shfl(xa[qs].y, partner, 64)};
+            if (t == 0) b = q == 0 ? xn : xa[(PPT - q) % PPT];
+            cpx<T> A = xa[q];
+            if (t == 0 && q == 0) {                    // X[0], X[M/2] are real
                 A.y = T(0);
-                B.y = T(0);
+                b.y = T(0);
             }
-            v[q] = real_merge(A, B, wk[q]);
+            v[q] = real_merge(A, b, wk[q]);
         }
         half_fft<T, M2, true>(v, L, t, tr, lact);
-        if constexpr (M2 <= 8) __syncthreads();   // no barrier inside: raw is still read
         if (lact) {
-            T *ha = hs + (lc * yt + lyy) * HS;
+            T *ha = hs + l * HS;
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
                 const int n = t + q * TPL;
-                if (2 * n < nx) ha[2 * n] = v[q].x;
-                if (2 * n + 1 < nx) ha[2 * n + 1] = v[q].y;
+                if (2 * n + 1 < nx) {
+                    *reinterpret_cast<cpx<T> *>(ha + 2 * n) = v[q];
+                } else if (2 * n < nx) {
+                    ha[2 * n] = v[q].x;
+                }
             }
         }
         __syncthreads();
@@ -219,7 +206,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     for (int i = 0; i < CPT; ++i) {
         if (!cok[i]) continue;
         const int yy = cyy[i], x = cx[i];
-        const long long cell = ccell[i];
+        const int off = coff[i];
         const T *p = cp[i];
         T E[3] = {T(0), T(0), T(0)};
         T sq[3];
@@ -228,7 +215,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         T hel[3] = {T(0), T(0), T(0)};
         if (a.elec_in) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) hel[c] = hs[(c * yt + yy) * HS + x];
+            for (int c = 0; c < 3; ++c) hel[c] = hs[((c << ysh) + yy) * HS + x];
         }
         T fg = T(0);
         if (material) {
@@ -269,16 +256,18 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                 else if (a.stage == 0) o[c] = p[c] + dtau * E[c];
                 else o[c] = T(0.5) * (co[i][c] + p[c]) + T(0.5) * dtau * E[c];
             }
+            bool bad = false;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Pout[c * comp + cell] = o[c];
-                if (!isfinite(o[c])) atomicOr(a.flag, 1);
-                if (do_fx) hs[(c * yt + yy) * HS + x] = o[c];
+                Pout[c * comp + off] = o[c];
+                bad = bad || !isfinite(o[c]);
+                if (do_fx) hs[((c << ysh) + yy) * HS + x] = o[c];
             }
+            if (bad) atomicOr(a.flag, 1);
         } else if constexpr (MODE == UPD_FIELD) {
             const T sc = kp->out_scale;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Pout[c * comp + cell] = material ? sc * E[c] : T(0);
+            for (int c = 0; c < 3; ++c) Pout[c * comp + off] = material ? sc * E[c] : T(0);
         } else {
             if (material) {
                 if (terms & T_LANDAU) acc[0] += (double)landau_f(sq, coefz);
@@ -300,49 +289,43 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     if (do_fx) {
         __syncthreads();
         cpx<T> v[8];
-        const bool has = lact && lyy < ny_here;
-        const T *ha = hs + (lc * yt + lyy) * HS;
+        const T *ha = hs + (lact ? l : 0) * HS;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int n = t + q * TPL;
-            const T ev = (has && 2 * n < nx) ? ha[2 * n] : T(0);
-            const T od = (has && 2 * n + 1 < nx) ? ha[2 * n + 1] : T(0);
-            v[q] = {ev, od};
-        }
-        half_fft<T, M2, false>(v, L, t, tr, lact);
-        __syncthreads();                       // scratch becomes the exchange buffer
-        cpx<T> *zx = scr + (lact ? l : 0) * M2;
-        if (lact) {
-#pragma unroll
-            for (int q = 0; q < PPT; ++q) zx[t + q * TPL] = v[q];
-        }
-        __syncthreads();
-        if (lact) {
-#pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                const int k = t + q * TPL;
-                cpx<T> xh;
-                raw[(k * 3 + lc) * RS + lyy] = real_split(zx[k], zx[(M2 - k) & (M2 - 1)], wk[q], xh);
-                if (k == 0) raw[(M2 * 3 + lc) * RS + lyy] = xh;
+            if (has && 2 * n + 1 < nx) {
+                v[q] = *reinterpret_cast<const cpx<T> *>(ha + 2 * n);
+            } else {
+                v[q] = {(has && 2 * n < nx) ? ha[2 * n] : T(0), T(0)};
             }
         }
-        __syncthreads();
-        for (int e = tid; e < hx * 3 * yt; e += nthr) {
-            const int kc = e / yt, yy = e - kc * yt;
-            if (yy < ny_here) S1[s1_index(kc, yy)] = raw[kc * RS + yy];
+        half_fft<T, M2, false>(v, L, t, tr, lact);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            // Z[M2 - k]: as for the inverse; for t = 0 this lane's point
+            // (PPT - q) mod PPT
+            const int qs = PPT - 1 - q;
+            cpx<T> zm_ = {__shfl(v[qs].x, partner, 64), __shfl(v[qs].y, partner, 64)};
+            if (t == 0) zm_ = v[(PPT - q) % PPT];
+            cpx<T> xh;
+            const cpx<T> xk = real_split(v[q], zm_, wk[q], xh);
+            if (has) {
+                s1row[(long long)(t + q * TPL) * kst] = xk;
+                if (t == 0 && q == 0) s1row[(long long)M2 * kst] = xh;
+            }
         }
     }
 
     if constexpr (MODE == UPD_ENERGY) {
         __syncthreads();
         double *red = reinterpret_cast<double *>(smem_raw);
-        const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
             double sacc = acc[k];
             for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
             acc[k] = sacc;
         }
+        const int wave = tid >> 6;
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < 7; ++k) red[wave * 8 + k] = acc[k];
@@ -352,22 +335,17 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             double sacc = 0.0;
             const int nw = (nthr + 63) / 64;
             for (int w = 0; w < nw; ++w) sacc += red[w * 8 + tid];
-            a.partials[((long long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = sacc;
+            a.partials[(long long)tile * 8 + tid] = sacc;
         }
     }
 }
 
-// LDS bytes of the update kernel for rows-per-group yt: region A holds the
-// x-spectra staging [hx][3][yt+1] and, at other times, the rows [3][yt][nx+1];
-// region B the half-length FFT scratch [3 yt][M/2 + M/16] and, at other
-// times, the forward-transform exchange [3 yt][M/2].
+// LDS bytes of the update kernel for rows-per-group yt: the rows
+// [3 yt][nx + 2] and the half-length FFT scratch [3 yt][M/2 + M/16].
 template <typename T, int M>
 static size_t update_lds(const Geom &g, int yt)
 {
-    const size_t raw = (size_t)g.hx * 3 * (yt + 1) * sizeof(cpx<T>);
-    const size_t hsb = (size_t)3 * yt * (g.nx + 1) * sizeof(T);
-    size_t a = raw > hsb ? raw : hsb;
-    a = (a + 15) / 16 * 16;
+    const size_t a = ((size_t)3 * yt * (g.nx + 2) * sizeof(T) + 15) / 16 * 16;
     const size_t b = (size_t)3 * yt * LinePad<M / 2>::len * sizeof(cpx<T>);
     size_t tot = a + b;
     if (tot < 16 * 8 * sizeof(double)) tot = 16 * 8 * sizeof(double);
@@ -383,16 +361,18 @@ static int update_threads(const Geom &g, int yt, int tpl)
     return (nthr + 63) / 64 * 64;
 }
 
-// Rows per work-group: even, up to 16 (128-byte segments of the kx-major
-// spectra for FP32), limited by threads (<= 2 cells per thread, <= 1024 FP32
-// / 512 FP64 threads) and 64 KiB of LDS.
+// Rows per work-group: a power of two, limited by threads (<= 2 cells per
+// thread, <= 1024 FP32 / 512 FP64 threads) and 64 KiB of LDS.
 template <typename T, int M>
 static int rows_for(const Geom &g)
 {
     const int maxthr = UpdMaxThreads<T>::v;
     const int ny_even = g.ny + (g.ny & 1);
     int best = 2;
-    for (int yt = 2; yt <= 16 && yt <= (ny_even > 2 ? ny_even : 2); yt += 2) {
+    // FP32: at most 8 rows (measured best on the 128x128x32 film: 64-byte
+    // spectra segments, 512 threads); FP64: up to 16
+    const int ymax = sizeof(T) == 4 ? 8 : 16;
+    for (int yt = 2; yt <= ymax && yt <= (ny_even > 2 ? ny_even : 2); yt *= 2) {
         if (update_threads(g, yt, M >= 16 ? M / 16 : 1) > maxthr) break;
         if (update_lds<T, M>(g, yt) > 65536) break;
         best = yt;
