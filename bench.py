@@ -176,6 +176,110 @@ def traffic_from(fetch_kernels, write_kernels, fetch_copy, write_copy, copy_byte
     return res
 
 
+def relax_floor(cfg):
+    """Energy floor of the relaxation test near F = 0 (paraelectric runs):
+    alpha_ref P0^2 * 1e-3 times the sample volume, in J."""
+    s = cfg["scales"]
+    n = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+    dv = cfg["d"][0] * cfg["d"][1] * cfg["d"][2]
+    return s["alpha_ref"] * s["P0"] ** 2 * 1e-3 * n * dv
+
+
+def run_c3(max_steps, check, tune_steps, seq_every):
+    """Batched relaxation of the 64-instance workload against plain runs.
+
+    Relaxed: |F(n) - F(n - check)| < 1e-6 max(|F(n)|, floor), tested every
+    `check` steps on each instance.  Batched: one context per grid shape
+    (24 / 24 / 16 instances), each on its own stream, autotuned, stepped
+    `check` steps at a time until every instance has relaxed (or max_steps).
+    Plain: one single-instance context per shape runs every seq_every-th
+    instance alone from the same start with the same test; its time is
+    scaled by seq_every.  Set-up (tensor builds, uploads, tuning) is not
+    timed."""
+    import numpy as np
+    import torch
+
+    import paper_2605_28800_amd as T
+    import tdgl_inputs as I
+    groups = I.c3_groups()
+    starts, ctxs, info = [], [], []
+    for c in groups:
+        nb = len(c["T"])
+        st = torch.cuda.Stream()
+        ctx = T.Context(c, T.TDGL_FP32, stream=st, batch=nb)
+        P = np.stack([I.initial_P(c, sd, np.float32) for sd in c["seeds"]])
+        ctx.set_P(P)
+        fused, rows, ms = T.tdgl_autotune(ctx.ctx, tune_steps)
+        info.append({"grid": list(c["n"]), "instances": nb, "fused_plane": fused, "rows": rows,
+                     "ms_per_step_tuned": ms})
+        starts.append(P)
+        ctxs.append(ctx)
+    torch.cuda.synchronize()
+    floors = [relax_floor(c) for c in groups]
+    prev = [ctx.energies_batch()[0][:, 4].copy() for ctx in ctxs]
+    relaxed = [np.full(len(c["T"]), -1) for c in groups]
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < max_steps and any((r < 0).any() for r in relaxed):
+        for ctx in ctxs:
+            ctx.step(check)
+        steps += check
+        for g, ctx in enumerate(ctxs):
+            F = ctx.energies_batch()[0][:, 4]
+            ok = np.abs(F - prev[g]) < 1e-6 * np.maximum(np.abs(F), floors[g])
+            relaxed[g][(relaxed[g] < 0) & ok] = steps
+            prev[g] = F.copy()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    cells = sum(c["n"][0] * c["n"][1] * c["n"][2] * len(c["T"]) for c in groups)
+    for ctx in ctxs:
+        ctx.close()
+    # plain runs, one instance at a time, same start and test
+    t_seq, n_seq, agree = 0.0, 0, 0
+    for g, c in enumerate(groups):
+        one = T.Context(dict(c, T=c["T"][0]), T.TDGL_FP32)
+        try:
+            for i in range(0, len(c["T"]), seq_every):
+                T.tdgl_set_temperature(one.ctx, c["T"][i])
+                one.set_P(starts[g][i])
+                torch.cuda.synchronize()
+                f_prev = one.energies()[0][4]
+                t1 = time.perf_counter()
+                k, done = 0, -1
+                while k < max_steps:
+                    one.step(check)
+                    k += check
+                    f = one.energies()[0][4]
+                    if abs(f - f_prev) < 1e-6 * max(abs(f), floors[g]):
+                        done = k
+                        break
+                    f_prev = f
+                t_seq += (time.perf_counter() - t1) * seq_every
+                n_seq += 1
+                agree += int(done == relaxed[g][i])
+        finally:
+            one.close()
+    return {
+        "workload": "64 open BaTiO3 boxes: 24 of 32x32x32, 24 of 64x64x16, 16 of 96x96x8 "
+                    "(padded 64^3 / 128x128x32 / 256x256x16), T ~ U(200, 450) K, "
+                    "P ~ U(-0.1, 0.1), FP32 Heun dtau=1e-3",
+        "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V)" % check,
+        "groups": info,
+        "max_steps": max_steps,
+        "batched_steps": steps,
+        "relaxed": int(sum((r >= 0).sum() for r in relaxed)),
+        "instances": int(sum(len(r) for r in relaxed)),
+        "relax_steps": [r.tolist() for r in relaxed],
+        "batched_s": t_batch,
+        "batched_cell_steps_per_s": cells * steps / t_batch,
+        "plain_s": t_seq,
+        "plain_runs_timed": n_seq,
+        "plain_scaled_by": seq_every,
+        "plain_same_relax_step": agree,
+        "speedup": t_seq / t_batch if t_batch > 0 else None,
+    }
+
+
 def cpu_baseline(cfg, nsteps):
     """The oracle as it stands, timed on the host on a few Heun steps of the
     same grid.  Its interaction table is built with mimg = 0 (the cost of a
@@ -212,6 +316,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--c4-steps", type=int, default=200,
                     help="FP32 Heun steps of the 256x256x64 open bilayer (0: skip)")
+    ap.add_argument("--c3-max-steps", type=int, default=20000,
+                    help="step cap of the batched 64-instance relaxation (0: skip)")
+    ap.add_argument("--c3-check", type=int, default=100)
+    ap.add_argument("--c3-seq-every", type=int, default=8,
+                    help="plain runs: time every k-th instance alone and scale by k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fft-path", type=int, default=0, help="0 auto (fused if it fits), 1 three passes")
     ap.add_argument("--rows", type=int, default=0, help="update-kernel rows per group (0 auto)")
@@ -323,6 +432,14 @@ def main():
         log("c4: %.4f ms/step, %.3e cell-steps/s, step roofline %.3f"
             % (c4["ms_per_step"], v4, c4["roofline_frac_step"]))
 
+    c3 = None
+    if args.c3_max_steps > 0:
+        log("c3: batched relaxation of 64 instances (cap %d steps)" % args.c3_max_steps)
+        c3 = run_c3(args.c3_max_steps, args.c3_check, 200, args.c3_seq_every)
+        log("c3: %d/%d relaxed in %d steps, batched %.2f s, plain %.2f s (x%.1f)"
+            % (c3["relaxed"], c3["instances"], c3["batched_steps"], c3["batched_s"],
+               c3["plain_s"], c3["speedup"] or 0))
+
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         log("cpu baseline: oracle, %d Heun steps" % args.cpu_steps)
@@ -354,6 +471,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64": fp64,
         "c4_large_grid": c4,
+        "c3_batched_relaxation": c3,
         "kernels": kernels,
         "step_roofline": {"bytes_per_cell_step": round(step_bytes, 1),
                           "frac": round(value * step_bytes / (HBM_PEAK_GBS * 1e9), 4),

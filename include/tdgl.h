@@ -102,6 +102,23 @@ int tdgl_abi_version(void);
 tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream,
                         tdgl_ctx **out);
 
+/* A context holding nbatch independent simulations of the same grid and
+ * model (materials, layer map, gradient, scales, tensor, E_ext, integrator)
+ * that may differ in temperature and state: every kernel of a step covers
+ * all instances in one launch.  The paper runs many simulations in
+ * parallel to cut the total cost (section 3) and relaxes batches of
+ * single-cell runs from random starts (section 4.2).  State arrays gain a
+ * leading instance dimension: P is [nbatch][3][nz][ny][nx].  Instance
+ * results are identical to those of nbatch separate contexts.
+ * tdgl_create is tdgl_create_batch with nbatch = 1.  Errors as tdgl_create;
+ * TDGL_E_ARG for nbatch outside 1..4096, TDGL_E_UNSUPPORTED when
+ * nz * nbatch exceeds 65535. */
+tdgl_status tdgl_create_batch(const tdgl_grid *grid, int nbatch, int precision,
+                              void *hip_stream, tdgl_ctx **out);
+
+/* Number of instances of the context. */
+tdgl_status tdgl_get_batch(const tdgl_ctx *ctx, int *nbatch);
+
 /* Release the context and all device memory it allocated.  NULL is a no-op. */
 void tdgl_destroy(tdgl_ctx *ctx);
 
@@ -157,8 +174,13 @@ tdgl_status tdgl_build_tensor(tdgl_ctx *ctx, int mimg);
  * inspection. */
 tdgl_status tdgl_get_tensor_spectrum(tdgl_ctx *ctx, double *dst, size_t count);
 
-/* Temperature (K) for the Table 1 coefficient forms. */
+/* Temperature (K) for the Table 1 coefficient forms, for every instance. */
 tdgl_status tdgl_set_temperature(tdgl_ctx *ctx, double T_kelvin);
+
+/* Temperature of each instance: T_kelvin[nbatch] (host memory).  The
+ * reduced scales stay shared (one alpha_ref), so only the Landau
+ * coefficients differ between instances. */
+tdgl_status tdgl_set_temperatures(tdgl_ctx *ctx, const double *T_kelvin);
 
 /* Uniform applied field E_ext (V/m), eq 7.  May change between tdgl_step
  * calls (time-dependent excitation, section 3). */
@@ -189,15 +211,16 @@ tdgl_status tdgl_get_fft_path(const tdgl_ctx *ctx, int *fused);
  * fail with TDGL_E_HIP at the next step. */
 tdgl_status tdgl_set_update_rows(tdgl_ctx *ctx, int rows);
 
-/* Load P (C/m^2, [3][nz][ny][nx]) from src: host memory if src_on_device is
- * 0, device memory otherwise; src_precision TDGL_FP32 or TDGL_FP64 (converted
+/* Load P (C/m^2, [nbatch][3][nz][ny][nx]) from src: host memory if
+ * src_on_device is 0, device memory otherwise; src_precision TDGL_FP32 or TDGL_FP64 (converted
  * to the context precision).  Vacuum layers are set to zero and the
  * non-finite flag is cleared.  Needs the model to be complete (scales,
  * every material named by the layer map, gradient coefficients when the
  * gradient term is on).  Host sources are copied before return. */
 tdgl_status tdgl_set_P(tdgl_ctx *ctx, const void *src, int src_on_device, int src_precision);
 
-/* Store the current P to dst (host or device, FP32 or FP64).  Host
+/* Store the current P to dst (layout of tdgl_set_P; host or device, FP32 or
+ * FP64).  Host
  * destinations are synchronising and report TDGL_E_NONFINITE like
  * tdgl_sync (the data is copied either way). */
 tdgl_status tdgl_get_P(tdgl_ctx *ctx, void *dst, int dst_on_device, int dst_precision);
@@ -211,19 +234,24 @@ tdgl_status tdgl_get_P(tdgl_ctx *ctx, void *dst, int dst_on_device, int dst_prec
 tdgl_status tdgl_step(tdgl_ctx *ctx, long long nsteps);
 
 /* Effective field E_eff (V/m) of the current P with the terms in mask (a
- * subset of TDGL_ALL), written to device memory dst_dev ([3][nz][ny][nx],
- * context precision).  Vacuum cells get 0. */
+ * subset of TDGL_ALL), written to device memory dst_dev
+ * ([nbatch][3][nz][ny][nx], context precision).  Vacuum cells get 0. */
 tdgl_status tdgl_eval_field(tdgl_ctx *ctx, unsigned mask, void *dst_dev);
 
 /* Energies of the current P with the context's term mask, in J:
  * F[0] Landau, F[1] gradient, F[2] electrostatic, F[3] external, F[4] total;
  * meanP[3]: mean P over material cells (C/m^2).  FP64 accumulation.
- * Synchronising. */
+ * Synchronising.  For a batch: instance 0. */
 tdgl_status tdgl_energies(tdgl_ctx *ctx, double F[5], double meanP[3]);
 
+/* tdgl_energies for every instance: F[nbatch][5], meanP[nbatch][3] (host
+ * memory). */
+tdgl_status tdgl_energies_batch(tdgl_ctx *ctx, double *F, double *meanP);
+
 /* Reduced per-layer Landau coefficients ([nz][8]: a1x a1y a1z a11 a12 a111
- * a112 a123, zero for vacuum) and scalars out[8]: kappa, hx*, hy*, hz*,
- * dV*, energy scale (J), field scale (V/m), l0 (m).  Host-side; for tests. */
+ * a112 a123, zero for vacuum; instance 0 of a batch) and scalars out[8]:
+ * kappa, hx*, hy*, hz*, dV*, energy scale (J), field scale (V/m), l0 (m).
+ * Host-side; for tests. */
 tdgl_status tdgl_get_reduced(const tdgl_ctx *ctx, double *coef, double scal[8]);
 
 /* Advance nsteps time steps with plain stream launches and time every kernel
@@ -246,6 +274,17 @@ tdgl_status tdgl_profile_step(tdgl_ctx *ctx, int nsteps, double ms_out[5]);
  * simulation state is unchanged; intermediate spectra are not.  Allocates
  * and frees one P-sized device buffer; synchronising.  1 <= nrep <= 100000. */
 tdgl_status tdgl_profile_kernels(tdgl_ctx *ctx, int nrep, double ms_out[5]);
+
+/* Pick the fastest launch configuration for this context by measurement:
+ * each candidate (fused plane pass where it fits or the three passes,
+ * times update tiles of 2, 4, 8, 16 rows) advances the current state by
+ * nsteps steps as one graph, once to warm up and once timed with HIP events,
+ * always from the same saved P.  The fastest stays set (as with
+ * tdgl_set_fft_path and tdgl_set_update_rows); choice[0] = 1 if it uses the
+ * fused pass, choice[1] = rows; *ms_per_step (may be NULL) its time.  P, the
+ * step parity and the non-finite flag are restored.  Allocates and frees
+ * one P-sized device buffer; synchronising.  1 <= nsteps <= 100000. */
+tdgl_status tdgl_autotune(tdgl_ctx *ctx, int nsteps, int choice[2], double *ms_per_step);
 
 /* Wait for all work of the context; returns TDGL_E_NONFINITE if a step
  * produced a non-finite P. */

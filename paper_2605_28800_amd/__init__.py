@@ -55,6 +55,9 @@ _ctx_p = c_void_p
 _SIGS = {
     "tdgl_abi_version": ([], c_int),
     "tdgl_create": ([ctypes.POINTER(tdgl_grid), c_int, c_void_p, ctypes.POINTER(_ctx_p)], c_int),
+    "tdgl_create_batch": ([ctypes.POINTER(tdgl_grid), c_int, c_int, c_void_p,
+                           ctypes.POINTER(_ctx_p)], c_int),
+    "tdgl_get_batch": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_destroy": ([_ctx_p], None),
     "tdgl_last_error": ([_ctx_p], ctypes.c_char_p),
     "tdgl_get_dims": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
@@ -67,6 +70,7 @@ _SIGS = {
     "tdgl_build_tensor": ([_ctx_p, c_int], c_int),
     "tdgl_get_tensor_spectrum": ([_ctx_p, ctypes.POINTER(c_double), c_size_t], c_int),
     "tdgl_set_temperature": ([_ctx_p, c_double], c_int),
+    "tdgl_set_temperatures": ([_ctx_p, ctypes.POINTER(c_double)], c_int),
     "tdgl_set_eext": ([_ctx_p, c_double, c_double, c_double], c_int),
     "tdgl_set_terms": ([_ctx_p, c_uint], c_int),
     "tdgl_set_integrator": ([_ctx_p, c_int, c_double], c_int),
@@ -76,9 +80,11 @@ _SIGS = {
     "tdgl_step": ([_ctx_p, ctypes.c_longlong], c_int),
     "tdgl_eval_field": ([_ctx_p, c_uint, c_void_p], c_int),
     "tdgl_energies": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
+    "tdgl_energies_batch": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_get_reduced": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_profile_step": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_profile_kernels": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
+    "tdgl_autotune": ([_ctx_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)], c_int),
     "tdgl_set_fft_path": ([_ctx_p, c_int], c_int),
     "tdgl_get_fft_path": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_set_update_rows": ([_ctx_p, c_int], c_int),
@@ -121,6 +127,21 @@ def tdgl_create(grid: tdgl_grid, precision: int, hip_stream=None):
     if st != TDGL_OK:
         raise TdglError(st, "tdgl_create")
     return ctx
+
+
+def tdgl_create_batch(grid: tdgl_grid, nbatch: int, precision: int, hip_stream=None):
+    ctx = _ctx_p()
+    st = lib().tdgl_create_batch(ctypes.byref(grid), nbatch, precision, hip_stream,
+                                 ctypes.byref(ctx))
+    if st != TDGL_OK:
+        raise TdglError(st, "tdgl_create_batch")
+    return ctx
+
+
+def tdgl_get_batch(ctx):
+    n = c_int()
+    _check(ctx, lib().tdgl_get_batch(ctx, ctypes.byref(n)))
+    return n.value
 
 
 def tdgl_destroy(ctx):
@@ -196,6 +217,11 @@ def tdgl_set_temperature(ctx, T):
     _check(ctx, lib().tdgl_set_temperature(ctx, T))
 
 
+def tdgl_set_temperatures(ctx, T):
+    arr = (c_double * len(T))(*[float(v) for v in T])
+    _check(ctx, lib().tdgl_set_temperatures(ctx, arr))
+
+
 def tdgl_set_eext(ctx, ex, ey, ez):
     _check(ctx, lib().tdgl_set_eext(ctx, ex, ey, ez))
 
@@ -235,6 +261,15 @@ def tdgl_energies(ctx):
     return tuple(F), tuple(m)
 
 
+def tdgl_energies_batch(ctx):
+    nb = tdgl_get_batch(ctx)
+    F = np.zeros((nb, 5))
+    m = np.zeros((nb, 3))
+    _check(ctx, lib().tdgl_energies_batch(ctx, F.ctypes.data_as(ctypes.POINTER(c_double)),
+                                          m.ctypes.data_as(ctypes.POINTER(c_double))))
+    return F, m
+
+
 def tdgl_get_reduced(ctx, nz: int):
     coef = np.zeros((nz, 8))
     scal = np.zeros(8)
@@ -255,21 +290,32 @@ def tdgl_profile_kernels(ctx, nrep: int):
     return tuple(ms)
 
 
+def tdgl_autotune(ctx, nsteps: int):
+    """Returns (fused, rows, ms_per_step) of the configuration it kept."""
+    ch = (c_int * 2)()
+    ms = c_double()
+    _check(ctx, lib().tdgl_autotune(ctx, nsteps, ch, ctypes.byref(ms)))
+    return ch[0], ch[1], ms.value
+
+
 def tdgl_sync(ctx):
     _check(ctx, lib().tdgl_sync(ctx))
 
 
 # --------------------------------------------------------- convenience class
 class Context:
-    """One simulation on the current torch CUDA (HIP) device and stream.
+    """One simulation, or a batch of `batch` simulations of the same grid, on
+    the current torch CUDA (HIP) device and stream.
 
     cfg: a run recipe dict (grid "n", cell size "d", "periodic", "materials",
     "layers", "gradient", "scales", "T", "eext", "terms", "scheme", "dtau",
-    "mimg").  The workspace is a torch uint8 tensor bound to the context.
+    "mimg").  For a batch, "T" may be a list of per-instance temperatures
+    and P carries a leading instance dimension.  The workspace is a torch
+    uint8 tensor bound to the context.
     """
 
     def __init__(self, cfg: dict, precision: int = TDGL_FP32, stream=None, build_tensor=True,
-                 torch_workspace=True):
+                 torch_workspace=True, batch: int = 0):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -278,7 +324,11 @@ class Context:
         pm = sum(1 << k for k in range(3) if cfg["periodic"][k])
         g = tdgl_grid(nx, ny, nz, cfg["d"][0], cfg["d"][1], cfg["d"][2], pm)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.ctx = tdgl_create(g, precision, c_void_p(self.stream.cuda_stream))
+        self.batch = batch
+        if batch:
+            self.ctx = tdgl_create_batch(g, batch, precision, c_void_p(self.stream.cuda_stream))
+        else:
+            self.ctx = tdgl_create(g, precision, c_void_p(self.stream.cuda_stream))
         self.dims = tdgl_get_dims(self.ctx)
         self.workspace = None
         if torch_workspace:
@@ -294,7 +344,10 @@ class Context:
         tdgl_set_layer_materials(self.ctx, cfg["layers"])
         G = cfg["gradient"]
         tdgl_set_gradient(self.ctx, G["G11"], G["G12"], G["G44"], G["G44p"])
-        tdgl_set_temperature(self.ctx, cfg["T"])
+        if np.ndim(cfg["T"]) == 0:
+            tdgl_set_temperature(self.ctx, cfg["T"])
+        else:
+            tdgl_set_temperatures(self.ctx, cfg["T"])
         tdgl_set_eext(self.ctx, *cfg.get("eext", (0.0, 0.0, 0.0)))
         tdgl_set_terms(self.ctx, cfg.get("terms", TDGL_ALL))
         tdgl_set_integrator(self.ctx, TDGL_HEUN if cfg.get("scheme", "heun") == "heun"
@@ -305,7 +358,7 @@ class Context:
     @property
     def shape(self):
         nx, ny, nz = self.cfg["n"]
-        return (3, nz, ny, nx)
+        return (self.batch, 3, nz, ny, nx) if self.batch else (3, nz, ny, nx)
 
     def _tdtype(self, prec):
         return self.torch.float32 if prec == TDGL_FP32 else self.torch.float64
@@ -348,6 +401,10 @@ class Context:
 
     def energies(self):
         return tdgl_energies(self.ctx)
+
+    def energies_batch(self):
+        """Per instance: F[nb][5] (J), meanP[nb][3] (C/m^2)."""
+        return tdgl_energies_batch(self.ctx)
 
     def sync(self):
         tdgl_sync(self.ctx)

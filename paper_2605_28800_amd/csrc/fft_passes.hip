@@ -191,8 +191,9 @@ __device__ __forceinline__ void tensor_row(const T *__restrict__ Nt, int kx, int
 }
 
 // ------------------------------------------------- z pass with multiply
-// S: [hx][3][nz][my] complex (in place); work-group = (kx, tile of CT ky
-// columns) x 3 components.  Columns per group: 128-byte rows where threads
+// S: [hx][nb][3][nz][my] complex (in place); work-group = (kx, instance,
+// tile of CT ky columns) x 3 components; the tensor is shared by the
+// instances.  Columns per group: 128-byte rows where threads
 // (<= 1024 FP32 / 512 FP64) and LDS (<= 64 KiB) allow.
 template <typename T, int MZ>
 struct ZmulCfg {
@@ -211,7 +212,8 @@ struct ZmulCfg {
 
 template <typename T, int MZ>
 __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
-    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, const cpx<T> *__restrict__ tw)
+    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int nb,
+           const cpx<T> *__restrict__ tw)
 {
     using C = ZmulCfg<T, MZ>;
     constexpr int TPL = C::TPL, CT = C::CT;
@@ -223,12 +225,13 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     const int t = (tid / CT) % TPL;
     const int c = tid / (CT * TPL);
     const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int kx = (int)(tile / gridDim.x);
+    const int kxb = (int)(tile / gridDim.x);        // plane (kx, instance)
+    const int kx = kxb / nb;
     const int ky = (int)(tile % gridDim.x) * CT + cc;
     const bool act = ky < my;
     const int kyc = act ? ky : 0;
     // uniform bases, unsigned 32-bit offsets within one kx plane
-    cpx<T> *plane = S + (long long)kx * 3 * nz * my;
+    cpx<T> *plane = S + (long long)kxb * 3 * nz * my;
     const int hy = my / 2 + 1, hz = MZ / 2 + 1;
     const unsigned qs = (unsigned)hz * hy;
     const T *tplane = Nt + (long long)kx * 6 * qs;
@@ -298,7 +301,8 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
 // One work-group per kx.  The plane [3][nz][MY] (lines padded one slot per 8)
 // sits in LDS: y transforms of all (c, z) lines, then the z pass with the
 // tensor multiply in chunks of CK ky columns (scratch [3][MZ][CK]), then the
-// inverse y transforms.  S1: [hx][3][nz][ny] in/out (in place).
+// inverse y transforms.  S1: [hx][nb][3][nz][ny] in/out (in place); one
+// work-group per (kx, instance).
 template <typename T, int MY, int MZ>
 struct PlaneCfg {
     // FP64 groups use at most 384 threads, leaving 256 VGPRs per wave
@@ -319,8 +323,8 @@ size_t plane_lds_bytes(int nz)
 
 template <typename T, int MY, int MZ>
 __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
-    k_plane(cpx<T> *S1, const T *__restrict__ Nt, int ny, int nz, const cpx<T> *__restrict__ twy,
-            const cpx<T> *__restrict__ twz)
+    k_plane(cpx<T> *S1, const T *__restrict__ Nt, int ny, int nz, int nb,
+            const cpx<T> *__restrict__ twy, const cpx<T> *__restrict__ twz)
 {
     using C = PlaneCfg<T, MY, MZ>;
     constexpr int TPLY = C::TPLY, TPLZ = C::TPLZ, CK = C::CK, LINE = C::LINE;
@@ -331,10 +335,10 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     constexpr int LZ = LinePad<MZ>::len;
     const IdxStridePad ipz{CK};
     const int tid = threadIdx.x;
-    const int kx = blockIdx.x;
+    const int kx = blockIdx.x / nb;          // work-group = plane (kx, instance)
     const IdxPad pad{};
     const int nlines = 3 * nz;
-    cpx<T> *gplane = S1 + (long long)kx * nlines * ny;
+    cpx<T> *gplane = S1 + (long long)blockIdx.x * nlines * ny;
 
     // y-pass roles
     const int ly = tid / TPLY, ty = tid - ly * TPLY;
@@ -557,10 +561,10 @@ static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *
 {
     using C = ZmulCfg<T, MZ>;
     const int gx = (g.my + C::CT - 1) / C::CT;
-    if (g.hx > 65535) return hipErrorInvalidValue;
+    if ((long long)g.hx * g.nb > 65535) return hipErrorInvalidValue;
     const size_t shm = (size_t)3 * C::CT * LinePad<MZ>::len * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx), dim3(C::NTHR), shm, s, (cpx<T> *)S,
-                       (const T *)Nt, g.nz, g.my, (const cpx<T> *)tw + MZ);
+    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm, s,
+                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb, (const cpx<T> *)tw + MZ);
     return hipGetLastError();
 }
 
@@ -588,8 +592,8 @@ static hipError_t plane_impl(const Geom &g, void *S1, const void *Nt, const void
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         return hipSuccess;
     }
-    hipLaunchKernelGGL((k_plane<T, MY, MZ>), dim3(g.hx), dim3(C::NTHR), shm, s, (cpx<T> *)S1,
-                       (const T *)Nt, g.ny, g.nz, (const cpx<T> *)tw + MY,
+    hipLaunchKernelGGL((k_plane<T, MY, MZ>), dim3(g.hx * g.nb), dim3(C::NTHR), shm, s,
+                       (cpx<T> *)S1, (const T *)Nt, g.ny, g.nz, g.nb, (const cpx<T> *)tw + MY,
                        (const cpx<T> *)tw + MZ);
     return hipGetLastError();
 }

@@ -31,6 +31,7 @@ struct Geom {
     int mx, my, mz;      // padded FFT lengths
     int hx;              // mx/2 + 1
     int px, py, pz;      // periodic flags
+    int nb = 1;          // instances of this grid advanced together (batch)
 };
 
 // Update kernel modes.
@@ -69,7 +70,8 @@ hipError_t launch_zmul(int prec, const Geom &g, void *S, const void *Nt, const v
 hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a,
                          const void *tw, hipStream_t s, int *nblocks_out);
 int update_rows_per_block(int prec, const Geom &g);
-hipError_t launch_reduce_partials(const double *partials, int n, double *out, hipStream_t s);
+hipError_t launch_reduce_partials(const double *partials, int n, int nb, double *out,
+                                  hipStream_t s);
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst, size_t n,
                           double scale, hipStream_t s);
 hipError_t launch_zero_layers(int prec, void *P, const void *coef, const Geom &g, hipStream_t s);

@@ -58,7 +58,8 @@ struct tdgl_ctx {
     std::vector<signed char> layer;
     bool grad_set = false;
     double G11 = 0, G12 = 0, G44 = 0, G44p = 0;
-    double T = 300.0;
+    int nb = 1;                           // instances of the grid (batch)
+    std::vector<double> Tb;               // temperature per instance
     double eext[3] = {0, 0, 0};
     unsigned terms = TDGL_ALL;
     int scheme = TDGL_HEUN;
@@ -114,7 +115,7 @@ struct Layout {
 Layout layout_of(const tdgl_ctx *c)
 {
     const Geom &g = c->g;
-    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    const size_t N = (size_t)g.nx * g.ny * g.nz * g.nb;   // cells of all instances
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -123,17 +124,17 @@ Layout layout_of(const tdgl_ctx *c)
         return o;
     };
     L.P = take(2 * 3 * N * c->esz);
-    L.S1 = take((size_t)3 * g.nz * g.ny * g.hx * 2 * c->esz);
-    L.S2 = take((size_t)3 * g.nz * g.my * g.hx * 2 * c->esz);
+    L.S1 = take((size_t)3 * g.nb * g.nz * g.ny * g.hx * 2 * c->esz);
+    L.S2 = take((size_t)3 * g.nb * g.nz * g.my * g.hx * 2 * c->esz);
     L.Nt = take((size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * g.hx * c->esz);
-    L.coef = take((size_t)g.nz * NCOEF * c->esz);
+    L.coef = take((size_t)g.nb * g.nz * NCOEF * c->esz);
     L.kp = take(sizeof(KParams<double>));
     L.twf = take((size_t)2 * MAXLEN * 2 * sizeof(float));
     L.twd = take((size_t)2 * MAXLEN * 2 * sizeof(double));
     L.gl = take((size_t)2 * GL_MAXN * GL_MAXN * sizeof(double));
-    L.partials = take((size_t)c->nblocks * 8 * sizeof(double));
+    L.partials = take((size_t)c->nblocks * g.nb * 8 * sizeof(double));
     L.flag = take(sizeof(int));
-    L.res = take(8 * sizeof(double));
+    L.res = take((size_t)8 * g.nb * sizeof(double));
     L.total = off;
     return L;
 }
@@ -209,7 +210,7 @@ tdgl_status ensure_device(tdgl_ctx *c)
         c->ws_owned = true;
     }
     char *b = static_cast<char *>(c->ws);
-    const size_t N = (size_t)c->g.nx * c->g.ny * c->g.nz;
+    const size_t N = (size_t)c->g.nx * c->g.ny * c->g.nz * c->g.nb;
     c->P[0] = b + L.P;
     c->P[1] = b + L.P + 3 * N * c->esz;
     c->S1 = b + L.S1;
@@ -285,14 +286,15 @@ void reduced(const tdgl_ctx *c, std::vector<double> &coef, double scal[8], doubl
 {
     const double l0 = std::sqrt(c->G110 / c->alpha_ref);
     const double h[3] = {c->d[0] / l0, c->d[1] / l0, c->d[2] / l0};
-    coef.assign((size_t)c->g.nz * NCOEF, 0.0);
-    for (int z = 0; z < c->g.nz; ++z) {
+    coef.assign((size_t)c->g.nb * c->g.nz * NCOEF, 0.0);
+    for (int bz = 0; bz < c->g.nb * c->g.nz; ++bz) {
+        const int z = bz % c->g.nz, b = bz / c->g.nz;
         const int id = c->layer[z];
         if (id < 0 || !c->mat_set[id]) continue;
         double si[8];
-        landau_si(c->mats[id], c->T, si);
+        landau_si(c->mats[id], c->Tb[b], si);
         const double a = c->alpha_ref, p2 = c->P0 * c->P0, p4 = p2 * p2;
-        double *o = &coef[(size_t)z * NCOEF];
+        double *o = &coef[(size_t)bz * NCOEF];
         o[0] = si[0] / a;
         o[1] = si[1] / a;
         o[2] = si[2] / a;
@@ -363,8 +365,8 @@ bool elec_on(const tdgl_ctx *c) { return (c->terms & TDGL_ELEC) != 0; }
 hipError_t enq_fx(tdgl_ctx *c, const void *P, hipStream_t s)
 {
     const Geom &g = c->g;
-    return launch_fx(c->prec, g.mx, P, 3LL * g.nz * g.ny, g.nx, g.nx, c->S1,
-                     3LL * g.nz * g.ny, tw(c), s);
+    const long long rows = 3LL * g.nb * g.nz * g.ny;      // rows of all instances
+    return launch_fx(c->prec, g.mx, P, rows, g.nx, g.nx, c->S1, rows, tw(c), s);
 }
 
 // y pass, z pass with the tensor, inverse y pass: S1 (x spectra, kx-major
@@ -373,7 +375,7 @@ hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
 {
     const Geom &g = c->g;
     if (c->use_plane) return launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, s, false);
-    const long long nl = (long long)g.hx * 3 * g.nz;
+    const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
     hipError_t e = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
                               tw(c), s);
     if (e != hipSuccess) return e;
@@ -481,16 +483,24 @@ int tdgl_abi_version(void) { return TDGL_ABI_VERSION; }
 
 tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream, tdgl_ctx **out)
 {
+    return tdgl_create_batch(grid, 1, precision, hip_stream, out);
+}
+
+tdgl_status tdgl_create_batch(const tdgl_grid *grid, int nbatch, int precision, void *hip_stream,
+                              tdgl_ctx **out)
+{
     if (!out) return TDGL_E_ARG;
     *out = nullptr;
     if (!grid) return TDGL_E_ARG;
     if (precision != TDGL_FP32 && precision != TDGL_FP64) return TDGL_E_ARG;
+    if (nbatch < 1 || nbatch > 4096) return TDGL_E_ARG;
     const int n[3] = {grid->nx, grid->ny, grid->nz};
     const double d[3] = {grid->dx, grid->dy, grid->dz};
     for (int k = 0; k < 3; ++k) {
         if (n[k] < 1 || n[k] > 4096) return TDGL_E_ARG;
     }
     if ((long long)n[0] * n[1] * n[2] >= (1LL << 31)) return TDGL_E_UNSUPPORTED;
+    if ((long long)n[2] * nbatch > 65535) return TDGL_E_UNSUPPORTED;     // launch grid rows
     for (int k = 0; k < 3; ++k) {
         if (!(d[k] > 0.0) || !std::isfinite(d[k])) return TDGL_E_ARG;
     }
@@ -516,6 +526,8 @@ tdgl_status tdgl_create(const tdgl_grid *grid, int precision, void *hip_stream, 
     c->prec = precision;
     c->esz = precision == TDGL_FP32 ? 4 : 8;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    c->g.nb = nbatch;
+    c->Tb.assign(nbatch, 300.0);
     c->layer.assign(n[2], 0);
     c->yt = update_rows_per_block(c->prec, c->g);
     c->nblocks = ((c->g.ny + 1) / 2) * c->g.nz;   // partial sums for any row tile >= 2
@@ -536,6 +548,13 @@ void tdgl_destroy(tdgl_ctx *c)
 }
 
 const char *tdgl_last_error(const tdgl_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+tdgl_status tdgl_get_batch(const tdgl_ctx *c, int *nbatch)
+{
+    if (!c || !nbatch) return TDGL_E_ARG;
+    *nbatch = c->g.nb;
+    return TDGL_OK;
+}
 
 tdgl_status tdgl_get_dims(const tdgl_ctx *c, int out[7])
 {
@@ -699,7 +718,19 @@ tdgl_status tdgl_set_temperature(tdgl_ctx *c, double T)
 {
     if (!c) return TDGL_E_ARG;
     if (!(T > 0) || !std::isfinite(T)) return fail(c, TDGL_E_ARG, "temperature must be > 0");
-    c->T = T;
+    c->Tb.assign(c->g.nb, T);
+    c->params_dirty = true;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_temperatures(tdgl_ctx *c, const double *T)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!T) return fail(c, TDGL_E_ARG, "null temperatures");
+    for (int b = 0; b < c->g.nb; ++b)
+        if (!(T[b] > 0) || !std::isfinite(T[b]))
+            return fail(c, TDGL_E_ARG, "temperature of instance %d must be > 0", b);
+    c->Tb.assign(T, T + c->g.nb);
     c->params_dirty = true;
     return TDGL_OK;
 }
@@ -786,7 +817,7 @@ tdgl_status tdgl_set_P(tdgl_ctx *c, const void *src, int on_dev, int src_prec)
     tdgl_status st = upload_params(c);
     if (st != TDGL_OK) return st;
     const Geom &g = c->g;
-    const size_t n = (size_t)3 * g.nx * g.ny * g.nz;
+    const size_t n = (size_t)3 * g.nx * g.ny * g.nz * g.nb;
     void *dst = c->P[c->cur];
     // stored in units of P0 (Table 2)
     const double inv = 1.0 / c->P0;
@@ -817,7 +848,7 @@ tdgl_status tdgl_get_P(tdgl_ctx *c, void *dst, int on_dev, int dst_prec)
     if (dst_prec != TDGL_FP32 && dst_prec != TDGL_FP64) return fail(c, TDGL_E_ARG, "bad precision");
     if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
     const Geom &g = c->g;
-    const size_t n = (size_t)3 * g.nx * g.ny * g.nz;
+    const size_t n = (size_t)3 * g.nx * g.ny * g.nz * g.nb;
     const void *src = c->P[c->cur];
     if (on_dev) {
         HIP_TRY(c, launch_convert(c->prec, src, dst_prec, dst, n, c->P0, c->stream));
@@ -886,10 +917,11 @@ tdgl_status tdgl_eval_field(tdgl_ctx *c, unsigned mask, void *dst)
     return TDGL_OK;
 }
 
-tdgl_status tdgl_energies(tdgl_ctx *c, double F[5], double meanP[3])
+namespace {
+
+// energies of every instance: F[b*5 + 0..4] (J), meanP[b*3 + 0..2] (C/m^2)
+tdgl_status energies_all(tdgl_ctx *c, double *F, double *meanP)
 {
-    if (!c) return TDGL_E_ARG;
-    if (!F || !meanP) return fail(c, TDGL_E_ARG, "null output");
     if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
     const bool el = elec_on(c);
     if (el && !c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
@@ -899,26 +931,49 @@ tdgl_status tdgl_energies(tdgl_ctx *c, double F[5], double meanP[3])
     HIP_TRY(c, enq_eval(c, UPD_ENERGY, c->P[c->cur], nullptr, nullptr, 0, c->terms, el, false,
                         c->stream));
     if (el) c->spec_valid = false;
-    // one partial per work-group of the launch just made
+    // one partial per work-group of the launch just made, instance-major
     const int ngroups = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
-    HIP_TRY(c, launch_reduce_partials(c->partials, ngroups, c->res, c->stream));
-    double r[8];
-    HIP_TRY(c, hipMemcpyAsync(r, c->res, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, launch_reduce_partials(c->partials, ngroups, c->g.nb, c->res, c->stream));
+    std::vector<double> r((size_t)8 * c->g.nb);
+    HIP_TRY(c, hipMemcpyAsync(r.data(), c->res, r.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
     st = read_flag(c);
     std::vector<double> coef;
     double scal[8], gh2[3][3];
     reduced(c, coef, scal, gh2);
     const double f = scal[4] * scal[5];
-    F[0] = r[0] * f;
-    F[1] = r[1] * f;
-    F[2] = r[2] * f;
-    F[3] = r[3] * f;
-    F[4] = F[0] + F[1] + F[2] + F[3];
     long long nmat = 0;
     for (int z = 0; z < c->g.nz; ++z)
         if (c->layer[z] >= 0) nmat += (long long)c->g.nx * c->g.ny;
-    for (int k = 0; k < 3; ++k) meanP[k] = nmat ? r[4 + k] / (double)nmat * c->P0 : 0.0;
+    for (int b = 0; b < c->g.nb; ++b) {
+        const double *rb = &r[(size_t)8 * b];
+        double *Fb = F + 5 * b;
+        for (int k = 0; k < 4; ++k) Fb[k] = rb[k] * f;
+        Fb[4] = Fb[0] + Fb[1] + Fb[2] + Fb[3];
+        for (int k = 0; k < 3; ++k) meanP[3 * b + k] = nmat ? rb[4 + k] / (double)nmat * c->P0 : 0.0;
+    }
     return st;
+}
+
+}  // namespace
+
+tdgl_status tdgl_energies(tdgl_ctx *c, double F[5], double meanP[3])
+{
+    if (!c) return TDGL_E_ARG;
+    if (!F || !meanP) return fail(c, TDGL_E_ARG, "null output");
+    if (c->g.nb == 1) return energies_all(c, F, meanP);
+    std::vector<double> Fa((size_t)5 * c->g.nb), Ma((size_t)3 * c->g.nb);
+    tdgl_status st = energies_all(c, Fa.data(), Ma.data());
+    for (int k = 0; k < 5; ++k) F[k] = Fa[k];
+    for (int k = 0; k < 3; ++k) meanP[k] = Ma[k];
+    return st;
+}
+
+tdgl_status tdgl_energies_batch(tdgl_ctx *c, double *F, double *meanP)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!F || !meanP) return fail(c, TDGL_E_ARG, "null output");
+    return energies_all(c, F, meanP);
 }
 
 tdgl_status tdgl_get_reduced(const tdgl_ctx *c, double *coef, double scal[8])
@@ -968,7 +1023,7 @@ tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
                 (void)hipEventRecord(E[2], c->stream);
                 (void)hipEventRecord(E[3], c->stream);
             } else if (el) {
-                const long long nl = (long long)g.hx * 3 * g.nz;
+                const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
                 le = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
                                 tw(c), c->stream);
                 (void)hipEventRecord(E[1], c->stream);
@@ -1031,7 +1086,7 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int flag0 = 0;
     HIP_TRY(c, hipMemcpy(&flag0, c->flag, sizeof(int), hipMemcpyDeviceToHost));
-    const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->esz;
+    const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->g.nb * c->esz;
     void *save = nullptr;
     HIP_TRY(c, hipMalloc(&save, pbytes));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1040,7 +1095,7 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
     if (he == hipSuccess) he = hipEventCreate(&e1);
     void *A = c->P[c->cur], *B = c->P[1 - c->cur];
     const Geom &g = c->g;
-    const long long nl = (long long)g.hx * 3 * g.nz;
+    const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
     const unsigned t = c->terms;
     // one kernel, nrep times, as one graph; returns ms per launch
     auto time_kernel = [&](int which, double *out) -> hipError_t {
@@ -1100,6 +1155,94 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
     c->spec_valid = false;
     if (he != hipSuccess) return fail(c, TDGL_E_HIP, "kernel profile: %s", hipGetErrorString(he));
     if (re != hipSuccess) return fail(c, TDGL_E_HIP, "state restore: %s", hipGetErrorString(re));
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_autotune(tdgl_ctx *c, int nsteps, int choice[2], double *ms_per_step)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!choice || nsteps < 1 || nsteps > 100000)
+        return fail(c, TDGL_E_ARG, "need 1 <= nsteps <= 100000 and choice");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    if (elec_on(c) && !c->tensor_built)
+        return fail(c, TDGL_E_STATE, "electrostatic term on but tensor not built");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int flag0 = 0;
+    HIP_TRY(c, hipMemcpy(&flag0, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+    const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->g.nb * c->esz;
+    void *save = nullptr;
+    HIP_TRY(c, hipMalloc(&save, pbytes));
+    const int cur0 = c->cur;
+    const int path0 = c->fft_path, yt0 = c->yt, chunk0 = c->graph_chunk;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipMemcpyAsync(save, c->P[cur0], pbytes, hipMemcpyDeviceToDevice, c->stream);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    const int nb_groups = c->nblocks;               // partials the workspace holds per instance
+    double best = 1e300;
+    int best_path = path0, best_yt = yt0;
+    tdgl_status rs = TDGL_OK;
+    c->graph_chunk = nsteps;                        // one graph of nsteps steps per candidate
+    for (int path = 0; path <= 1 && he == hipSuccess && rs == TDGL_OK; ++path) {
+        c->fft_path = path;
+        choose_path(c);
+        if (path == 0 && !c->use_plane) continue;   // the fused pass does not fit
+        for (int yt = 2; yt <= 16 && he == hipSuccess && rs == TDGL_OK; yt *= 2) {
+            if (((c->g.ny + yt - 1) / yt) * c->g.nz > nb_groups) continue;
+            if (yt > 2 && yt > c->g.ny + (c->g.ny & 1)) break;
+            c->yt = yt;
+            drop_graphs(c);
+            // every candidate starts from the saved state and runs the same steps
+            he = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+            if (he != hipSuccess) break;
+            c->cur = cur0;
+            c->spec_valid = false;
+            rs = tdgl_step(c, nsteps);              // warm-up: captures the graph
+            if (rs != TDGL_OK) {                    // a tile the device rejects: skip it
+                rs = TDGL_OK;
+                (void)hipGetLastError();
+                continue;
+            }
+            he = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+            c->cur = cur0;
+            c->spec_valid = false;
+            if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+            if (he == hipSuccess) rs = tdgl_step(c, nsteps);
+            if (he == hipSuccess && rs == TDGL_OK) he = hipEventRecord(e1, c->stream);
+            if (he == hipSuccess && rs == TDGL_OK) he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (he == hipSuccess && rs == TDGL_OK) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he == hipSuccess && rs == TDGL_OK && ms / nsteps < best) {
+                best = ms / nsteps;
+                best_path = path;
+                best_yt = yt;
+            }
+        }
+    }
+    // the winner stays set; the state goes back to what it was
+    c->fft_path = best_path;
+    c->yt = best_yt;
+    c->graph_chunk = chunk0;
+    drop_graphs(c);
+    if (c->dev_init) choose_path(c);
+    hipError_t re = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+    if (re == hipSuccess)
+        re = hipMemcpyAsync(c->flag, &flag0, sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (re == hipSuccess) re = hipStreamSynchronize(c->stream);
+    c->cur = cur0;
+    c->spec_valid = false;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    if (rs != TDGL_OK) return rs;
+    if (he != hipSuccess) return fail(c, TDGL_E_HIP, "autotune: %s", hipGetErrorString(he));
+    if (re != hipSuccess) return fail(c, TDGL_E_HIP, "state restore: %s", hipGetErrorString(re));
+    if (best == 1e300) return fail(c, TDGL_E_HIP, "autotune: no candidate ran");
+    choice[0] = c->use_plane ? 1 : 0;
+    choice[1] = best_yt;
+    if (ms_per_step) *ms_per_step = best;
     return TDGL_OK;
 }
 

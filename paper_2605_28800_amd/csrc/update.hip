@@ -70,9 +70,11 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const int ysh = __ffs(yt) - 1;
     const int nrows = 3 * yt;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    // tile = (instance b, layer z, row group), instance-major
     const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int z = (int)(tile / gridDim.x), y0 = (int)(tile % gridDim.x) * yt;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int zb = (int)(tile / gridDim.x);
+    const int z = zb % nz, b = zb / nz, y0 = (int)(tile % gridDim.x) * yt;
     // LDS: rows hs[(c*yt + yy)*HS + x] (HS = nx + 2, even, so that (even,
     // odd) sample pairs are 8-byte aligned), then the FFT scratch per line.
     const int HS = nx + 2;
@@ -81,7 +83,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     cpx<T> *scr = reinterpret_cast<cpx<T> *>(smem_raw + hbytes);
     const int plane = ny * nx;                 // components hold < 2^31 cells
     const long long comp = (long long)nz * plane;
-    const T *coefz = reinterpret_cast<const T *>(a.coef) + (long long)z * NCOEF;
+    const T *coef0 = reinterpret_cast<const T *>(a.coef) + (long long)b * nz * NCOEF;
+    const T *coefz = coef0 + (long long)z * NCOEF;
     const KParams<T> *kp = reinterpret_cast<const KParams<T> *>(a.kp);
     const bool material = coefz[8] != T(0);
     const unsigned terms = a.terms;
@@ -97,8 +100,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const int partner = (lane - t) + ((TPL - t) & (TPL - 1));
     cpx<T> *L = scr + (lact ? l : 0) * LEN;
     cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
-    const long long kst = 3LL * nz * ny;       // S1 stride between kx
-    cpx<T> *s1row = S1 + ((long long)lc * nz + z) * ny + y0 + (has ? lyy : 0);
+    const long long kst = 3LL * g.nb * nz * ny;   // S1 stride between kx
+    cpx<T> *s1row = S1 + ((long long)(b * 3 + lc) * nz + z) * ny + y0 + (has ? lyy : 0);
 
     // ---- prologue: issue the global loads up front
     TwReg<T, M2> tr;
@@ -121,13 +124,12 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     // the centre itself, so its difference vanishes), old state
     const int zm = z > 0 ? z - 1 : (g.pz ? nz - 1 : -1);
     const int zp = z < nz - 1 ? z + 1 : (g.pz ? 0 : -1);
-    const T *coef0 = reinterpret_cast<const T *>(a.coef);
     const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
     const bool hzp = zp >= 0 && coef0[(long long)zp * NCOEF + 8] != T(0);
     const bool need_nb = material && (terms & T_GRAD);
     const bool need_old = MODE == UPD_STEP && a.stage == 1;
-    const T *Pin0 = reinterpret_cast<const T *>(a.P_in);
-    const T *Pold0 = reinterpret_cast<const T *>(a.P_old);
+    const T *Pin0 = reinterpret_cast<const T *>(a.P_in) + 3 * b * comp;
+    const T *Pold0 = a.P_old ? reinterpret_cast<const T *>(a.P_old) + 3 * b * comp : nullptr;
     const T *Pc[3] = {Pin0, Pin0 + comp, Pin0 + 2 * comp};
     const unsigned nx_div = 0xffffffffu / (unsigned)nx + 1u;   // e / nx for e < 2^16
     T cp[CPT][3], cn[CPT][6][3], co[CPT][3];
@@ -201,7 +203,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     // ---- 2. local terms and the update
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const T dtau = kp->dtau;
-    T *Pout = reinterpret_cast<T *>(a.P_out);
+    T *Pout = reinterpret_cast<T *>(a.P_out) + 3 * b * comp;
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
         if (!cok[i]) continue;
@@ -409,7 +411,8 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
     const int nthr = update_threads(g, a.yt, M >= 16 ? M / 16 : 1);
     const size_t shm = update_lds<T, M>(g, a.yt);
     if (shm > 65536 || nthr > UpdMaxThreads<T>::v) return hipErrorInvalidConfiguration;
-    dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz);
+    if ((long long)g.nz * g.nb > 65535) return hipErrorInvalidValue;
+    dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz * g.nb);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
     hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, a, g,
                        (const cpx<T> *)tw);
@@ -447,10 +450,13 @@ hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a, co
 }
 
 // ------------------------------------------------------------ small kernels
+// instance b = blockIdx.x sums its n partials part[b*n .. b*n + n) into out[b*8 ..]
 __global__ void k_reduce_partials(const double *__restrict__ part, int n, double *out)
 {
     __shared__ double red[256];
     const int tid = threadIdx.x;
+    part += (long long)blockIdx.x * n * 8;
+    out += blockIdx.x * 8;
     for (int k = 0; k < 8; ++k) {
         double s = 0.0;
         for (int i = tid; i < n; i += 256) s += part[(long long)i * 8 + k];
@@ -465,9 +471,10 @@ __global__ void k_reduce_partials(const double *__restrict__ part, int n, double
     }
 }
 
-hipError_t launch_reduce_partials(const double *partials, int n, double *out, hipStream_t s)
+hipError_t launch_reduce_partials(const double *partials, int n, int nb, double *out,
+                                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, n, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, partials, n, out);
     return hipGetLastError();
 }
 
@@ -504,9 +511,9 @@ template <typename T>
 __global__ void k_zero_layers(T *P, const T *__restrict__ coef, int nz, long long plane)
 {
     const int z = blockIdx.y;
-    const int c = blockIdx.z;
-    if (coef[(long long)z * NCOEF + 8] != T(0)) return;
-    T *row = P + ((long long)c * nz + z) * plane;
+    const int c = blockIdx.z % 3, b = blockIdx.z / 3;     // component, instance
+    if (coef[((long long)b * nz + z) * NCOEF + 8] != T(0)) return;
+    T *row = P + ((long long)(b * 3 + c) * nz + z) * plane;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < plane;
          i += (long long)gridDim.x * blockDim.x)
         row[i] = T(0);
@@ -516,7 +523,7 @@ hipError_t launch_zero_layers(int prec, void *P, const void *coef, const Geom &g
 {
     const long long plane = (long long)g.nx * g.ny;
     const unsigned bx = (unsigned)((plane + 255) / 256 < 1024 ? (plane + 255) / 256 : 1024);
-    dim3 grid(bx, g.nz, 3);
+    dim3 grid(bx, g.nz, 3 * g.nb);
     if (prec == PREC_F32)
         hipLaunchKernelGGL((k_zero_layers<float>), grid, dim3(256), 0, s, (float *)P,
                            (const float *)coef, g.nz, plane);

@@ -113,6 +113,24 @@ def config(name: str) -> dict:
     raise KeyError(name)
 
 
+def c3_groups() -> list:
+    """The batched workload: 64 open BaTiO3 boxes (1 nm cells, the c1 model)
+    in three grid shapes -- 24 of 32x32x32, 24 of 64x64x16, 16 of 96x96x8 --
+    with T ~ U(200, 450) K drawn from PCG64(2024) and P ~ U(-0.1, 0.1) C/m^2
+    from per-instance seeds 100..163; FP32, Heun dtau = 1e-3.  Returns one
+    recipe per grid shape with "T" a list and "seeds" the instance seeds."""
+    rng = np.random.Generator(np.random.PCG64(2024))
+    groups, seed = [], 100
+    for n, count in (((32, 32, 32), 24), ((64, 64, 16), 24), ((96, 96, 8), 16)):
+        c = _bto_film(n[0], n[1], n[2], (0, 0, 0), precision="f32", scheme="heun",
+                      dtau=1e-3, steps=5000, init=dict(kind="uniform", amp=0.1))
+        c["T"] = [float(t) for t in rng.uniform(200.0, 450.0, count)]
+        c["seeds"] = list(range(seed, seed + count))
+        seed += count
+        groups.append(c)
+    return groups
+
+
 # --------------------------------------------------------------------------
 # Seeded initial states.  numpy Generator(PCG64(seed)), C order [3][Nz][Ny][Nx];
 # for single-precision runs the values are rounded to float32 first and both

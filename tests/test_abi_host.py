@@ -10,6 +10,7 @@ import pytest
 
 import paper_2605_28800_amd as T
 import tdgl_inputs as I
+from oracle import tdgl_oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -144,5 +145,47 @@ def test_device_calls_fail_cleanly_without_gpu():
         with pytest.raises(T.TdglError) as e:
             T.tdgl_build_tensor(ctx, 0)
         assert e.value.status == T.TDGL_E_HIP
+    finally:
+        T.tdgl_destroy(ctx)
+
+
+def test_batch_create_limits_and_sizes():
+    g = T.tdgl_grid(16, 16, 8, 1e-9, 1e-9, 1e-9, 0)
+    for bad in (0, 5000):
+        ctx = T._ctx_p()
+        st = T.lib().tdgl_create_batch(ctypes.byref(g), bad, T.TDGL_FP32, None, ctypes.byref(ctx))
+        assert st == T.TDGL_E_ARG
+    g2 = T.tdgl_grid(16, 16, 64, 1e-9, 1e-9, 1e-9, 0)
+    ctx = T._ctx_p()
+    st = T.lib().tdgl_create_batch(ctypes.byref(g2), 2048, T.TDGL_FP32, None, ctypes.byref(ctx))
+    assert st == T.TDGL_E_UNSUPPORTED              # nz * nbatch beyond one launch grid
+    ctxs = [T.tdgl_create(g, T.TDGL_FP32)] + [T.tdgl_create_batch(g, n, T.TDGL_FP32)
+                                              for n in (2, 4)]
+    try:
+        assert [T.tdgl_get_batch(c) for c in ctxs] == [1, 2, 4]
+        s1, s2, s4 = [T.tdgl_workspace_size(c) for c in ctxs]
+        per = s2 - s1                               # state, spectra, coefficients of one instance
+        assert per > 3 * 2 * 16 * 16 * 8 * 4        # at least the two P buffers
+        assert abs((s4 - s2) - 2 * per) <= 8 * 256   # the tensor and tables are shared
+    finally:
+        for c in ctxs:
+            T.tdgl_destroy(c)
+
+
+def test_batch_temperatures_reach_the_coefficients():
+    cfg = I.config("c1")
+    g = T.tdgl_grid(*cfg["n"], *cfg["d"], 0)
+    ctx = T.tdgl_create_batch(g, 3, T.TDGL_FP64)
+    try:
+        s = cfg["scales"]
+        T.tdgl_set_scales(ctx, s["P0"], s["alpha_ref"], s["G110"], s["eps_b"])
+        T.tdgl_set_material(ctx, 0, cfg["materials"][0])
+        T.tdgl_set_layer_materials(ctx, cfg["layers"])
+        with pytest.raises(T.TdglError):
+            T.tdgl_set_temperatures(ctx, [300.0, -1.0, 300.0])
+        T.tdgl_set_temperatures(ctx, [250.0, 300.0, 350.0])
+        coef, _ = T.tdgl_get_reduced(ctx, cfg["n"][2])   # instance 0
+        ref = O.landau_coefficients(cfg["materials"][0], 250.0)
+        assert abs(coef[0, 0] - ref["a1x"] / s["alpha_ref"]) < 1e-12 * abs(coef[0, 0])
     finally:
         T.tdgl_destroy(ctx)
