@@ -316,6 +316,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--c4-steps", type=int, default=200,
                     help="FP32 Heun steps of the 256x256x64 open bilayer (0: skip)")
+    ap.add_argument("--c4-loop-values", type=int, default=0,
+                    help="field values of a +-1e8 V/m triangle-wave sweep of the bilayer (0: skip)")
+    ap.add_argument("--c4-loop-steps", type=int, default=500)
     ap.add_argument("--c3-max-steps", type=int, default=20000,
                     help="step cap of the batched 64-instance relaxation (0: skip)")
     ap.add_argument("--c3-check", type=int, default=100)
@@ -432,6 +435,27 @@ def main():
         log("c4: %.4f ms/step, %.3e cell-steps/s, step roofline %.3f"
             % (c4["ms_per_step"], v4, c4["roofline_frac_step"]))
 
+    loop = None
+    if args.c4_loop_values > 0:
+        import numpy as np
+        import torch
+        cfg4 = I.config("c4")
+        log("c4 loop: %d field values x %d steps" % (args.c4_loop_values, args.c4_loop_steps))
+        ctx = T.Context(cfg4, T.TDGL_FP32)
+        try:
+            ctx.set_P(I.initial_P(cfg4, 0, np.float32))
+            vals = np.zeros((args.c4_loop_values, 3))
+            vals[:, 2] = T.triangle_wave(1e8, args.c4_loop_values)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m, F = T.tdgl_sweep_eext(ctx.ctx, vals, args.c4_loop_steps)
+            dt = time.perf_counter() - t0
+        finally:
+            ctx.close()
+        loop = {"Ez_V_per_m": vals[:, 2].tolist(), "Pz_mean": m[:, 0, 2].tolist(),
+                "steps_per_value": args.c4_loop_steps, "seconds": dt}
+        log("c4 loop: %.1f s, Pz from %.4f to %.4f" % (dt, m[:, 0, 2].min(), m[:, 0, 2].max()))
+
     c3 = None
     if args.c3_max_steps > 0:
         log("c3: batched relaxation of 64 instances (cap %d steps)" % args.c3_max_steps)
@@ -472,6 +496,7 @@ def main():
         "fp64": fp64,
         "c4_large_grid": c4,
         "c3_batched_relaxation": c3,
+        "c4_field_sweep": loop,
         "kernels": kernels,
         "step_roofline": {"bytes_per_cell_step": round(step_bytes, 1),
                           "frac": round(value * step_bytes / (HBM_PEAK_GBS * 1e9), 4),

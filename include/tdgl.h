@@ -248,6 +248,17 @@ tdgl_status tdgl_energies(tdgl_ctx *ctx, double F[5], double meanP[3]);
  * memory). */
 tdgl_status tdgl_energies_batch(tdgl_ctx *ctx, double *F, double *meanP);
 
+/* Quasi-static field sweep (the paper drives samples with a time-dependent
+ * external field, section 3, and traces P against E in section 4.4): for
+ * each of the nvalues applied fields e[i][3] (V/m, host memory) in turn,
+ * set E_ext, advance steps_per_value steps and record the mean P of every
+ * instance in meanP[nvalues][nbatch][3] (C/m^2) and, if F is not NULL, the
+ * energies in F[nvalues][nbatch][5] (J).  A triangle wave in E_z gives the
+ * hysteresis loop P_z(E_z).  Synchronising once per value; E_ext keeps the
+ * last value.  Errors as tdgl_step and tdgl_energies. */
+tdgl_status tdgl_sweep_eext(tdgl_ctx *ctx, const double *e, int nvalues,
+                            long long steps_per_value, double *meanP, double *F);
+
 /* Reduced per-layer Landau coefficients ([nz][8]: a1x a1y a1z a11 a12 a111
  * a112 a123, zero for vacuum; instance 0 of a batch) and scalars out[8]:
  * kappa, hx*, hy*, hz*, dV*, energy scale (J), field scale (V/m), l0 (m).

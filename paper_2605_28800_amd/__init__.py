@@ -85,6 +85,8 @@ _SIGS = {
     "tdgl_profile_step": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_profile_kernels": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_autotune": ([_ctx_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)], c_int),
+    "tdgl_sweep_eext": ([_ctx_p, ctypes.POINTER(c_double), c_int, ctypes.c_longlong,
+                         ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_set_fft_path": ([_ctx_p, c_int], c_int),
     "tdgl_get_fft_path": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_set_update_rows": ([_ctx_p, c_int], c_int),
@@ -288,6 +290,25 @@ def tdgl_profile_kernels(ctx, nrep: int):
     ms = (c_double * 5)()
     _check(ctx, lib().tdgl_profile_kernels(ctx, nrep, ms))
     return tuple(ms)
+
+
+def tdgl_sweep_eext(ctx, e, steps_per_value: int):
+    """e: (n, 3) applied fields in V/m.  Returns meanP (n, nbatch, 3) and
+    F (n, nbatch, 5)."""
+    e = np.ascontiguousarray(e, dtype=np.float64).reshape(-1, 3)
+    nb = tdgl_get_batch(ctx)
+    m = np.zeros((len(e), nb, 3))
+    F = np.zeros((len(e), nb, 5))
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(c_double))
+    _check(ctx, lib().tdgl_sweep_eext(ctx, dp(e), len(e), steps_per_value, dp(m), dp(F)))
+    return m, F
+
+
+def triangle_wave(amp: float, n: int) -> np.ndarray:
+    """n values of a triangle wave 0 -> +amp -> -amp -> 0 (one period, the
+    first value one step above 0)."""
+    ph = np.arange(1, n + 1) / n
+    return amp * np.where(ph < 0.25, 4 * ph, np.where(ph < 0.75, 2 - 4 * ph, 4 * ph - 4))
 
 
 def tdgl_autotune(ctx, nsteps: int):

@@ -1158,6 +1158,30 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
     return TDGL_OK;
 }
 
+tdgl_status tdgl_sweep_eext(tdgl_ctx *c, const double *e, int nvalues, long long steps_per_value,
+                            double *meanP, double *F)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!e || !meanP || nvalues < 1 || steps_per_value < 0)
+        return fail(c, TDGL_E_ARG, "need field values, outputs, nvalues >= 1, steps >= 0");
+    for (int i = 0; i < 3 * nvalues; ++i)
+        if (!std::isfinite(e[i])) return fail(c, TDGL_E_ARG, "field value %d is not finite", i / 3);
+    const int nb = c->g.nb;
+    std::vector<double> Fb((size_t)5 * nb), Mb((size_t)3 * nb);
+    for (int i = 0; i < nvalues; ++i) {
+        tdgl_status st = tdgl_set_eext(c, e[3 * i], e[3 * i + 1], e[3 * i + 2]);
+        if (st == TDGL_OK) st = tdgl_step(c, steps_per_value);
+        if (st == TDGL_OK) st = energies_all(c, Fb.data(), Mb.data());
+        if (st != TDGL_OK) return st;
+        for (int b = 0; b < nb; ++b) {
+            for (int k = 0; k < 3; ++k) meanP[((size_t)i * nb + b) * 3 + k] = Mb[(size_t)3 * b + k];
+            if (F)
+                for (int k = 0; k < 5; ++k) F[((size_t)i * nb + b) * 5 + k] = Fb[(size_t)5 * b + k];
+        }
+    }
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_autotune(tdgl_ctx *c, int nsteps, int choice[2], double *ms_per_step)
 {
     if (!c) return TDGL_E_ARG;

@@ -189,3 +189,9 @@ def test_batch_temperatures_reach_the_coefficients():
         assert abs(coef[0, 0] - ref["a1x"] / s["alpha_ref"]) < 1e-12 * abs(coef[0, 0])
     finally:
         T.tdgl_destroy(ctx)
+
+
+def test_triangle_wave_shape():
+    w = T.triangle_wave(2.0, 8)
+    assert np.allclose(w, [1, 2, 1, 0, -1, -2, -1, 0])
+    assert T.triangle_wave(1.0, 400).max() == 1.0 and T.triangle_wave(1.0, 400).min() == -1.0
