@@ -193,7 +193,7 @@ __device__ __forceinline__ void tensor_row(const T *__restrict__ Nt, int kx, int
 // ------------------------------------------------- z pass with multiply
 // S: [hx][nb][3][nz][my] complex (in place); work-group = (kx, instance,
 // tile of CT ky columns) x 3 components; the tensor is shared by the
-// instances.  Columns per group: 128-byte rows where threads
+// instances.  Columns per group: 64-byte rows where threads
 // (<= 1024 FP32 / 512 FP64) and LDS (<= 64 KiB) allow.
 template <typename T, int MZ>
 struct ZmulCfg {
@@ -206,7 +206,7 @@ struct ZmulCfg {
                    ? fit(ct / 2)
                    : ct;
     }
-    static constexpr int CT = fit(128 / (int)sizeof(cpx<T>));
+    static constexpr int CT = fit(64 / (int)sizeof(cpx<T>));    // 64-byte rows (measured best)
     static constexpr int NTHR = 3 * CT * TPL;
 };
 
@@ -476,7 +476,7 @@ static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines
                            const void *tw, hipStream_t s)
 {
     constexpr int TPL = M / 8;
-    const int lpw = TPL >= 256 ? 1 : 256 / TPL;
+    const int lpw = TPL >= 128 ? 1 : 128 / TPL;     // 128-thread groups (measured best)
     const long long blocks = (nlines + lpw - 1) / lpw;
     if (blocks <= 0) return hipSuccess;
     const size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
