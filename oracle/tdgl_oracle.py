@@ -399,7 +399,35 @@ def step_heun(P, prob: Problem, dtau):
     return prob.mask(0.5 * (P + Pt) + 0.5 * dtau * effective_field(Pt, prob))
 
 
-def run(P, prob: Problem, scheme: str, dtau: float, nsteps: int):
+def step_ab3m2(P, prob: Problem, dtau, hist):
+    """One step of the multistep scheme section 3 names AB3M2, read as a
+    predictor-corrector pair: the three-step Adams-Bashforth predictor
+    P* = P_n + dtau (23 E_n - 16 E_{n-1} + 5 E_{n-2}) / 12 and the two-step
+    Adams-Moulton corrector P_{n+1} = P_n + dtau (5 E(P*) + 8 E_n - E_{n-1}) / 12,
+    both third order.  hist holds the fields of earlier steps at their
+    corrected states, newest last; while it holds fewer than two, the step
+    is a Heun step.  E_n is appended; returns the new state."""
+    En = effective_field(P, prob)
+    if len(hist) < 2:
+        Pt = prob.mask(P + dtau * En)
+        Pn = prob.mask(0.5 * (P + Pt) + 0.5 * dtau * effective_field(Pt, prob))
+    else:
+        E1, E2 = hist[-1], hist[-2]
+        Ps = prob.mask(P + dtau * (23.0 * En - 16.0 * E1 + 5.0 * E2) / 12.0)
+        Pn = prob.mask(P + dtau * (5.0 * effective_field(Ps, prob) + 8.0 * En - E1) / 12.0)
+    hist.append(En)
+    del hist[:-2]
+    return Pn
+
+
+def run(P, prob: Problem, scheme: str, dtau: float, nsteps: int, hist=None):
+    """nsteps steps of "euler", "heun" or "ab3m2" (hist: the multistep
+    history to continue from; a fresh run starts with an empty one)."""
+    if scheme == "ab3m2":
+        hist = [] if hist is None else hist
+        for _ in range(nsteps):
+            P = step_ab3m2(P, prob, dtau, hist)
+        return P
     step = step_euler if scheme == "euler" else step_heun
     for _ in range(nsteps):
         P = step(P, prob, dtau)
