@@ -53,7 +53,7 @@ typedef enum {
 } tdgl_status;
 
 enum { TDGL_FP32 = 0, TDGL_FP64 = 1 };            /* arithmetic of the step     */
-enum { TDGL_EULER = 0, TDGL_HEUN = 1 };           /* integrators                */
+enum { TDGL_EULER = 0, TDGL_HEUN = 1, TDGL_AB3M2 = 2 };   /* integrators        */
 /* energy terms (section 3: each contribution can be switched on or off) */
 enum { TDGL_LANDAU = 1, TDGL_GRAD = 2, TDGL_ELEC = 4, TDGL_EXT = 8, TDGL_ALL = 15 };
 
@@ -189,7 +189,14 @@ tdgl_status tdgl_set_eext(tdgl_ctx *ctx, double ex, double ey, double ez);
 /* Energy terms in the effective field (TDGL_* bits). */
 tdgl_status tdgl_set_terms(tdgl_ctx *ctx, unsigned mask);
 
-/* Integrator (TDGL_EULER or TDGL_HEUN) and reduced time step dtau > 0. */
+/* Integrator and reduced time step dtau > 0 (section 3 lists the
+ * schemes): TDGL_EULER; TDGL_HEUN (predictor P~ = P + dtau E(P), corrector
+ * (P + P~)/2 + dtau/2 E(P~)); TDGL_AB3M2, the multistep scheme read as the
+ * third-order Adams-Bashforth predictor with the two-step Adams-Moulton
+ * corrector, two field evaluations per step, started by two Heun steps.
+ * AB3M2 keeps the fields of the last two steps: it allocates three P-sized
+ * device buffers on first use (outside the workspace), and tdgl_set_P, this
+ * call and tdgl_autotune restart it (the next two steps are Heun steps). */
 tdgl_status tdgl_set_integrator(tdgl_ctx *ctx, int scheme, double dtau);
 
 /* Number of steps captured per HIP graph by tdgl_step (default 64; 0 runs
@@ -271,7 +278,8 @@ tdgl_status tdgl_get_reduced(const tdgl_ctx *ctx, double *coef, double scal[8]);
  * fused y-z-y plane kernel), z pass with tensor multiply, y inverse pass,
  * update (predictor / Euler stage), update (Heun corrector); 0 for kernels
  * that did not run.  Synchronising.
- * For benchmarks and profiling; the state advances like tdgl_step. */
+ * For benchmarks and profiling; the state advances like tdgl_step (AB3M2
+ * contexts advance with Heun steps and restart their multistep history). */
 tdgl_status tdgl_profile_step(tdgl_ctx *ctx, int nsteps, double ms_out[5]);
 
 /* Time every kernel of one field evaluation on its own: for each kernel a

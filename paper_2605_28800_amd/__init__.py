@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtdgl.so")
 TDGL_OK, TDGL_E_ARG, TDGL_E_NOMEM, TDGL_E_HIP = 0, -1, -2, -3
 TDGL_E_NONFINITE, TDGL_E_STATE, TDGL_E_UNSUPPORTED = -4, -5, -6
 TDGL_FP32, TDGL_FP64 = 0, 1
-TDGL_EULER, TDGL_HEUN = 0, 1
+TDGL_EULER, TDGL_HEUN, TDGL_AB3M2 = 0, 1, 2
 TDGL_LANDAU, TDGL_GRAD, TDGL_ELEC, TDGL_EXT, TDGL_ALL = 1, 2, 4, 8, 15
 TDGL_MAX_MATERIALS = 16
 
@@ -371,8 +371,8 @@ class Context:
             tdgl_set_temperatures(self.ctx, cfg["T"])
         tdgl_set_eext(self.ctx, *cfg.get("eext", (0.0, 0.0, 0.0)))
         tdgl_set_terms(self.ctx, cfg.get("terms", TDGL_ALL))
-        tdgl_set_integrator(self.ctx, TDGL_HEUN if cfg.get("scheme", "heun") == "heun"
-                            else TDGL_EULER, cfg.get("dtau", 1e-3))
+        schemes = {"euler": TDGL_EULER, "heun": TDGL_HEUN, "ab3m2": TDGL_AB3M2}
+        tdgl_set_integrator(self.ctx, schemes[cfg.get("scheme", "heun")], cfg.get("dtau", 1e-3))
         if build_tensor and (cfg.get("terms", TDGL_ALL) & TDGL_ELEC):
             tdgl_build_tensor(self.ctx, cfg.get("mimg", 16))
 

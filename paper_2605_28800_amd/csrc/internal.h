@@ -34,8 +34,10 @@ struct Geom {
     int nb = 1;          // instances of this grid advanced together (batch)
 };
 
-// Update kernel modes.
-enum { UPD_STEP = 0, UPD_FIELD = 1, UPD_ENERGY = 2 };
+// Update kernel modes.  UPD_STEP_MS: stages of the multistep scheme
+// (0: Heun predictor that also stores E; 2: Adams-Bashforth predictor that
+// stores E; 3: Adams-Moulton corrector).
+enum { UPD_STEP = 0, UPD_FIELD = 1, UPD_ENERGY = 2, UPD_STEP_MS = 3 };
 
 struct UpdArgs {
     const void *P_in;      // state the field is evaluated at
@@ -50,7 +52,10 @@ struct UpdArgs {
     unsigned terms;        // term mask for this evaluation
     int elec_in;           // read the electrostatic field rows from S1
     int fx_out;            // write the x-spectrum of P_out to S1
-    int yt;                // rows per work-group (even)
+    int yt;                // rows per work-group (a power of two)
+    void *hist_w;          // STEP_MS stages 0, 2: E of P_in is stored here
+    const void *hist_a;    // STEP_MS stage 2: E_{n-1}; stage 3: E_n
+    const void *hist_b;    // STEP_MS stage 2: E_{n-2}; stage 3: E_{n-1}
 };
 
 // spectra are kx-major: x pass output element k of row r at out[k*out_kstride + r]

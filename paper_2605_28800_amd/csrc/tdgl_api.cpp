@@ -29,6 +29,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     int cur = 0, scheme = 0, chunk = 0;
     unsigned elec = 0;
+    int hpos = 0;                 // multistep history phase at the chunk start
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -77,6 +78,9 @@ struct tdgl_ctx {
     int *flag = nullptr;
     int cur = 0;
     int yt = 2;
+    void *hist = nullptr;         // multistep: three E buffers (lazy, own allocation)
+    int hist_count = 0;           // valid history entries (0..2)
+    int hist_pos = 0;             // buffer of the newest entry
     size_t lds_max = 65536;      // dynamic LDS one work-group may use on this device
     int fft_path = 0;            // 0: fused plane pass when it fits, 1: three passes
     bool use_plane = false;
@@ -414,6 +418,63 @@ hipError_t enq_eval(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, vo
     return enq_upd(c, mode, Pin, Pold, Pout, stage, terms, elec, fx_out, s);
 }
 
+// multistep history buffer k (0..2)
+void *hist_buf(const tdgl_ctx *c, int k)
+{
+    const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->g.nb * c->esz;
+    return static_cast<char *>(c->hist) + (size_t)k * pbytes;
+}
+
+// one multistep step; *count, *pos: history entries and newest buffer
+hipError_t enq_step_ms(tdgl_ctx *c, int cur, int *count, int *pos, hipStream_t s)
+{
+    const bool el = elec_on(c);
+    const unsigned t = c->terms;
+    void *A = c->P[cur], *B = c->P[1 - cur];
+    const int nw = (*pos + 1) % 3;                      // buffer for E_n
+    UpdArgs a{};
+    a.S1 = c->S1;
+    a.coef = c->coef;
+    a.kp = c->kp;
+    a.partials = c->partials;
+    a.flag = c->flag;
+    a.terms = t;
+    a.elec_in = el ? 1 : 0;
+    a.fx_out = el ? 1 : 0;
+    a.yt = c->yt;
+    a.hist_w = hist_buf(c, nw);
+    hipError_t e = el ? enq_yz(c, s) : hipSuccess;
+    if (e != hipSuccess) return e;
+    a.P_in = A;
+    a.P_out = B;
+    if (*count < 2) {                                   // start-up: Heun, storing E_n
+        a.stage = 0;
+        e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
+        if (e != hipSuccess) return e;
+        e = enq_eval(c, UPD_STEP, B, A, A, 1, t, el, el, s);
+    } else {
+        a.stage = 2;                                    // AB3 predictor -> B
+        a.hist_a = hist_buf(c, *pos);
+        a.hist_b = hist_buf(c, (*pos + 2) % 3);
+        e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
+        if (e != hipSuccess) return e;
+        if (el) e = enq_yz(c, s);                       // AM2 corrector -> A
+        if (e != hipSuccess) return e;
+        a.stage = 3;
+        a.P_in = B;
+        a.P_old = A;
+        a.P_out = A;
+        a.hist_w = nullptr;
+        a.hist_a = hist_buf(c, nw);
+        a.hist_b = hist_buf(c, *pos);
+        e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
+    }
+    if (e != hipSuccess) return e;
+    *pos = nw;
+    if (*count < 2) ++*count;
+    return hipSuccess;
+}
+
 // one time step starting from buffer *cur (updated for Euler)
 hipError_t enq_step(tdgl_ctx *c, int *cur, hipStream_t s)
 {
@@ -433,16 +494,21 @@ hipError_t enq_step(tdgl_ctx *c, int *cur, hipStream_t s)
 tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
 {
     const unsigned el = elec_on(c) ? 1u : 0u;
+    const int hpos = c->scheme == TDGL_AB3M2 ? c->hist_pos : 0;
     for (auto &e : c->graphs)
-        if (e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk && e.elec == el) {
+        if (e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk && e.elec == el &&
+            e.hpos == hpos) {
             *out = e.exec;
             return TDGL_OK;
         }
     hipGraph_t graph = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int cur = c->cur;
+    int hcount = 2, hp = hpos;      // graphs are captured only with a full history
     hipError_t le = hipSuccess;
-    for (int i = 0; i < chunk && le == hipSuccess; ++i) le = enq_step(c, &cur, c->cap);
+    for (int i = 0; i < chunk && le == hipSuccess; ++i)
+        le = c->scheme == TDGL_AB3M2 ? enq_step_ms(c, cur, &hcount, &hp, c->cap)
+                                     : enq_step(c, &cur, c->cap);
     hipError_t ee = hipStreamEndCapture(c->cap, &graph);
     if (le != hipSuccess || ee != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -460,6 +526,7 @@ tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
     ge.scheme = c->scheme;
     ge.chunk = chunk;
     ge.elec = el;
+    ge.hpos = hpos;
     c->graphs.push_back(ge);
     *out = exec;
     return TDGL_OK;
@@ -542,6 +609,7 @@ void tdgl_destroy(tdgl_ctx *c)
         (void)hipStreamSynchronize(c->stream);
         drop_graphs(c);
         if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+        if (c->hist) (void)hipFree(c->hist);
         if (c->cap) (void)hipStreamDestroy(c->cap);
     }
     delete c;
@@ -760,10 +828,12 @@ tdgl_status tdgl_set_terms(tdgl_ctx *c, unsigned mask)
 tdgl_status tdgl_set_integrator(tdgl_ctx *c, int scheme, double dtau)
 {
     if (!c) return TDGL_E_ARG;
-    if (scheme != TDGL_EULER && scheme != TDGL_HEUN) return fail(c, TDGL_E_ARG, "unknown scheme");
+    if (scheme != TDGL_EULER && scheme != TDGL_HEUN && scheme != TDGL_AB3M2)
+        return fail(c, TDGL_E_ARG, "unknown scheme");
     if (!(dtau > 0) || !std::isfinite(dtau)) return fail(c, TDGL_E_ARG, "dtau must be > 0");
     c->scheme = scheme;
     c->dtau = dtau;
+    c->hist_count = 0;            // the multistep history assumes one dtau
     c->params_dirty = true;
     return TDGL_OK;
 }
@@ -838,6 +908,7 @@ tdgl_status tdgl_set_P(tdgl_ctx *c, const void *src, int on_dev, int src_prec)
     HIP_TRY(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
     c->P_set = true;
     c->spec_valid = false;
+    c->hist_count = 0;
     return TDGL_OK;
 }
 
@@ -878,19 +949,36 @@ tdgl_status tdgl_step(tdgl_ctx *c, long long nsteps)
     if (st != TDGL_OK) return st;
     const bool el = elec_on(c);
     if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    const bool ms = c->scheme == TDGL_AB3M2;
+    long long left = nsteps;
+    if (ms) {
+        if (!c->hist) {
+            const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->g.nb * c->esz;
+            if (hipMalloc(&c->hist, 3 * pbytes) != hipSuccess) {
+                c->hist = nullptr;
+                return fail(c, TDGL_E_NOMEM, "multistep history: hipMalloc failed");
+            }
+        }
+        for (; left > 0 && c->hist_count < 2; --left)      // start-up steps, plain launches
+            HIP_TRY(c, enq_step_ms(c, c->cur, &c->hist_count, &c->hist_pos, c->stream));
+    }
     int chunk = c->graph_chunk;
     if (c->scheme == TDGL_EULER && (chunk & 1)) chunk -= 1;
-    long long left = nsteps;
     if (chunk > 0) {
         while (left >= chunk) {
             hipGraphExec_t exec = nullptr;
             st = get_graph(c, chunk, &exec);
             if (st != TDGL_OK) return st;
             HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+            if (ms) c->hist_pos = (c->hist_pos + chunk) % 3;
             left -= chunk;
         }
     }
     for (; left > 0; --left) {
+        if (ms) {
+            HIP_TRY(c, enq_step_ms(c, c->cur, &c->hist_count, &c->hist_pos, c->stream));
+            continue;
+        }
         int cur = c->cur;
         HIP_TRY(c, enq_step(c, &cur, c->stream));
         c->cur = cur;
@@ -999,7 +1087,8 @@ tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
     tdgl_status st = upload_params(c);
     if (st != TDGL_OK) return st;
     if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
-    const int nev = c->scheme == TDGL_HEUN ? 2 : 1;
+    const int nev = c->scheme == TDGL_EULER ? 1 : 2;    // AB3M2 is timed with Heun stages
+    c->hist_count = 0;
     // events: per evaluation y_fwd, z, y_inv, update -> 5 markers
     std::vector<hipEvent_t> ev((size_t)nsteps * nev * 5);
     for (auto &e : ev) HIP_TRY(c, hipEventCreate(&e));
@@ -1138,7 +1227,7 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
     // the update first (it reads the live spectra), the y passes next (each
     // launch recomputes the same output), the in-place z pass last
     if (he == hipSuccess) he = time_kernel(3, &ms_out[3]);
-    if (he == hipSuccess && c->scheme == TDGL_HEUN) he = time_kernel(4, &ms_out[4]);
+    if (he == hipSuccess && c->scheme != TDGL_EULER) he = time_kernel(4, &ms_out[4]);
     if (el) {
         if (he == hipSuccess) he = time_kernel(0, &ms_out[0]);
         if (he == hipSuccess && !c->use_plane) he = time_kernel(2, &ms_out[2]);
@@ -1257,6 +1346,7 @@ tdgl_status tdgl_autotune(tdgl_ctx *c, int nsteps, int choice[2], double *ms_per
     if (re == hipSuccess) re = hipStreamSynchronize(c->stream);
     c->cur = cur0;
     c->spec_valid = false;
+    c->hist_count = 0;            // the trial runs overwrote the multistep history
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(save);

@@ -88,7 +88,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const KParams<T> *kp = reinterpret_cast<const KParams<T> *>(a.kp);
     const bool material = coefz[8] != T(0);
     const unsigned terms = a.terms;
-    const bool do_fx = (MODE == UPD_STEP) && a.fx_out;
+    constexpr bool STEPPING = MODE == UPD_STEP || MODE == UPD_STEP_MS;
+    const bool do_fx = STEPPING && a.fx_out;
     const int ny_here = ny - y0 < yt ? ny - y0 : yt;
 
     // line roles
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
     const bool hzp = zp >= 0 && coef0[(long long)zp * NCOEF + 8] != T(0);
     const bool need_nb = material && (terms & T_GRAD);
-    const bool need_old = MODE == UPD_STEP && a.stage == 1;
+    const bool need_old = (MODE == UPD_STEP && a.stage == 1) || (MODE == UPD_STEP_MS && a.stage == 3);
     const T *Pin0 = reinterpret_cast<const T *>(a.P_in) + 3 * b * comp;
     const T *Pold0 = a.P_old ? reinterpret_cast<const T *>(a.P_old) + 3 * b * comp : nullptr;
     const T *Pc[3] = {Pin0, Pin0 + comp, Pin0 + 2 * comp};
@@ -250,13 +251,37 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                 for (int c = 0; c < 3; ++c) E[c] += kp->eext[c];
             }
         }
-        if constexpr (MODE == UPD_STEP) {
+        if constexpr (STEPPING) {
             T o[3];
+            if constexpr (MODE == UPD_STEP) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (!material) o[c] = T(0);
-                else if (a.stage == 0) o[c] = p[c] + dtau * E[c];
-                else o[c] = T(0.5) * (co[i][c] + p[c]) + T(0.5) * dtau * E[c];
+                for (int c = 0; c < 3; ++c) {
+                    if (!material) o[c] = T(0);
+                    else if (a.stage == 0) o[c] = p[c] + dtau * E[c];
+                    else o[c] = T(0.5) * (co[i][c] + p[c]) + T(0.5) * dtau * E[c];
+                }
+            } else {
+                // multistep stages; the history holds E at the corrected states
+                const long long ho = 3LL * b * comp + off;
+                const T *ha = reinterpret_cast<const T *>(a.hist_a);
+                const T *hb = reinterpret_cast<const T *>(a.hist_b);
+                T *hw = reinterpret_cast<T *>(a.hist_w);
+                const T k12 = dtau / T(12);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T e = material ? E[c] : T(0);
+                    if (a.stage == 0) {
+                        o[c] = p[c] + dtau * e;                          // Heun predictor
+                    } else if (a.stage == 2) {                           // AB3 predictor
+                        const T e1 = ha[c * comp + ho], e2 = hb[c * comp + ho];
+                        o[c] = p[c] + k12 * (T(23) * e - T(16) * e1 + T(5) * e2);
+                    } else {                                             // AM2 corrector
+                        const T en = ha[c * comp + ho], e1 = hb[c * comp + ho];
+                        o[c] = co[i][c] + k12 * (T(5) * e + T(8) * en - e1);
+                    }
+                    if (!material) o[c] = T(0);
+                    if (a.stage != 3) hw[c * comp + ho] = e;
+                }
             }
             bool bad = false;
 #pragma unroll
@@ -422,6 +447,7 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
 #define TDGL_MODE_SWITCH(T, LEN)                                                          \
     switch (mode) {                                                                       \
     case UPD_STEP: return update_impl<T, LEN, UPD_STEP>(g, a, tw, s, nblocks_out);        \
+    case UPD_STEP_MS: return update_impl<T, LEN, UPD_STEP_MS>(g, a, tw, s, nblocks_out);  \
     case UPD_FIELD: return update_impl<T, LEN, UPD_FIELD>(g, a, tw, s, nblocks_out);      \
     default: return update_impl<T, LEN, UPD_ENERGY>(g, a, tw, s, nblocks_out);            \
     }

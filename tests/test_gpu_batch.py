@@ -35,10 +35,14 @@ def _single(cfg, prec, temp, P, steps, path=0):
         ctx.close()
 
 
-@pytest.mark.parametrize("name,prec,path", [("c2_small", "f32", 0), ("c2_small", "f32", 1),
-                                            ("c1", "f64", 0), ("c1", "f64", 1)])
-def test_batch_equals_separate_runs(name, prec, path):
+@pytest.mark.parametrize("name,prec,path,scheme", [("c2_small", "f32", 0, None),
+                                                   ("c2_small", "f32", 1, None),
+                                                   ("c1", "f64", 0, None), ("c1", "f64", 1, None),
+                                                   ("c2_small", "f32", 1, "ab3m2")])
+def test_batch_equals_separate_runs(name, prec, path, scheme):
     cfg = I.config(name)
+    if scheme:
+        cfg["scheme"] = scheme
     temps = [250.0, 300.0, 350.0]
     dt = np.float32 if prec == "f32" else np.float64
     Ps = [I.initial_P(cfg, s, dt) for s in range(3)]

@@ -159,3 +159,45 @@ def test_energies_parity(case):
     for k in range(5):
         assert abs(F[k] - ref[k]) <= 1e-12 * scale, (k, F[k], ref[k])
     assert np.allclose(meanP, E["meanP"] * prob.P0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_ab3m2_trajectory_fp64(path):
+    """The multistep scheme on the FP64 box, through the two Heun start-up
+    steps and well past them, against the oracle's same scheme."""
+    cfg = I.config("c1")
+    cfg["scheme"] = "ab3m2"
+    announce("AB3M2 trajectory fp64 path %d" % path)
+    P = I.initial_P(cfg, 0)
+    prob = O.Problem(cfg)
+    hist = []
+    ctx = gpu_context(cfg, "f64", path=path)
+    try:
+        ctx.set_P(P)
+        Ps = ps_of(cfg)
+        done = 0
+        for chk in (1, 2, 3, 70, 200):
+            ctx.step(chk - done)
+            P = O.run(P, prob, "ab3m2", cfg["dtau"], chk - done, hist=hist)
+            done = chk
+            err = np.abs(ctx.get_P() - P).max() / Ps
+            assert err <= 1e-12, (chk, err)
+    finally:
+        ctx.close()
+
+
+def test_ab3m2_film_fp32():
+    cfg = I.config("c2_small")
+    cfg["scheme"] = "ab3m2"
+    announce("AB3M2 c2_small fp32")
+    P0 = I.initial_P(cfg, 0, np.float32)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(P0)
+        ctx.step(150)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    ref = O.run(P0.astype(np.float64), prob, "ab3m2", cfg["dtau"], 150)
+    assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-5

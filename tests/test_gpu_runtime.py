@@ -24,7 +24,7 @@ def _run(cfg, prec, steps, chunk=None, path=0, seed=0):
         ctx.close()
 
 
-@pytest.mark.parametrize("scheme", ["heun", "euler"])
+@pytest.mark.parametrize("scheme", ["heun", "euler", "ab3m2"])
 def test_graph_chunks_equal_plain_launches(scheme):
     cfg = I.config("c2_small")
     cfg["scheme"] = scheme
@@ -195,3 +195,20 @@ def test_kernel_profile_keeps_the_state(name, path):
     assert all(ms[i] > 0 for i in used), ms
     assert all(ms[i] == 0 for i in range(5) if i not in used), ms
     assert np.array_equal(ref, got)
+
+
+def test_ab3m2_split_steps_bitwise():
+    """The multistep history survives split step calls and graph chunks."""
+    cfg = I.config("c2_small")
+    cfg["scheme"] = "ab3m2"
+    announce("AB3M2 split steps")
+    whole = _run(cfg, "f32", 131, chunk=16)
+    ctx = gpu_context(cfg, "f32", chunk=16)
+    try:
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        for n in (1, 1, 30, 16, 83):
+            ctx.step(n)
+        split = ctx.get_P(T.TDGL_FP32)
+    finally:
+        ctx.close()
+    assert np.array_equal(whole, split)
