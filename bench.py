@@ -49,7 +49,7 @@ def kernel_bytes(dims, esz):
     }
 
 
-def survey_bytes_per_cell_step(dims, esz):
+def model_bytes_per_cell_step(dims, esz):
     """Bytes per cell-step of a streaming 3-pass design with a separate x
     pass (the yardstick quoted with the target): Heun = 2 evals + 12 B."""
     nx, ny, nz, mx, my, mz, hx = dims
@@ -345,7 +345,7 @@ def main():
         print(json.dumps(res["bytes_per_launch"]))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (each simulation fits one "
+        print("bench.py: runs on one GPU only (each simulation fits one "
               "MI355X; --gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.steps < 1:
@@ -401,7 +401,7 @@ def main():
                    "alg_bytes": kb[k],
                    "GBps": round(kb[k] / (prof[k] * 1e-3) / 1e9, 1) if prof[k] else None}
                for k in names}
-    step_bytes = survey_bytes_per_cell_step(r32["dims"], 4)
+    step_bytes = model_bytes_per_cell_step(r32["dims"], 4)
     log("kernels:", json.dumps(kernels))
 
     fp64 = None
@@ -411,7 +411,7 @@ def main():
         v64 = ncell * args.fp64_steps / (r64["ms"] / 1e3)
         fp64 = {"value": v64, "ms_per_step": r64["ms"] / args.fp64_steps,
                 "steps": args.fp64_steps,
-                "roofline_frac_step": v64 * survey_bytes_per_cell_step(r64["dims"], 8)
+                "roofline_frac_step": v64 * model_bytes_per_cell_step(r64["dims"], 8)
                 / (HBM_PEAK_GBS * 1e9)}
         log("fp64: %.4f ms/step, %.3e cell-steps/s" % (fp64["ms_per_step"], v64))
 
@@ -422,7 +422,7 @@ def main():
         log("c4 fp32 run: %d timed Heun steps" % args.c4_steps)
         r4 = run_gpu(cfg4, T.TDGL_FP32, args.c4_steps, 20, 0, kernel_reps=20)
         v4 = n4 * args.c4_steps / (r4["ms"] / 1e3)
-        b4 = survey_bytes_per_cell_step(r4["dims"], 4)
+        b4 = model_bytes_per_cell_step(r4["dims"], 4)
         kb4 = kernel_bytes(r4["dims"], 4)
         k4 = {k: {"ms": round(ms, 5), "alg_bytes": kb4[k],
                   "GBps": round(kb4[k] / (ms * 1e-3) / 1e9, 1) if ms else None}

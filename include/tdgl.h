@@ -49,7 +49,7 @@ typedef enum {
     TDGL_E_HIP = -3,          /* HIP runtime error (no device, launch failure)*/
     TDGL_E_NONFINITE = -4,    /* a non-finite P appeared during tdgl_step     */
     TDGL_E_STATE = -5,        /* call out of order (e.g. step before set_P)   */
-    TDGL_E_UNSUPPORTED = -6   /* valid input this build does not handle       */
+    TDGL_E_UNSUPPORTED = -6   /* valid input this library does not handle     */
 } tdgl_status;
 
 enum { TDGL_FP32 = 0, TDGL_FP64 = 1 };            /* arithmetic of the step     */
@@ -152,7 +152,7 @@ tdgl_status tdgl_set_material(tdgl_ctx *ctx, int id, const tdgl_material *mat);
  * ids[nz]; -1 marks a vacuum layer, where P is held at zero. */
 tdgl_status tdgl_set_layer_materials(tdgl_ctx *ctx, const signed char *ids);
 
-/* Gradient coefficients of eq 4 (N m^4 C^-2).  This build handles the
+/* Gradient coefficients of eq 4 (N m^4 C^-2).  This library handles the
  * diagonal part exactly: d/dP_i gives G11 d_ii P_i + (G44 + G44') d_jj P_i;
  * a non-zero mixed coefficient G12 + G44 - G44' returns TDGL_E_UNSUPPORTED. */
 tdgl_status tdgl_set_gradient(tdgl_ctx *ctx, double G11, double G12, double G44,
