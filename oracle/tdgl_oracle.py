@@ -420,6 +420,61 @@ def step_ab3m2(P, prob: Problem, dtau, hist):
     return Pn
 
 
+# Dormand-Prince 5(4) tableau (Dormand & Prince 1980), the RK45 of
+# section 3: nodes C, stage weights A (row i for stage i + 1), the fifth-order
+# weights B (used to advance) and the fourth-order weights BS.
+DP_C = [0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0]
+DP_A = [[],
+        [1 / 5],
+        [3 / 40, 9 / 40],
+        [44 / 45, -56 / 15, 32 / 9],
+        [19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729],
+        [9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656],
+        [35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84]]
+DP_B = [35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84, 0.0]
+DP_BS = [5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200, 187 / 2100, 1 / 40]
+
+
+def step_rk45(P, prob: Problem, h, atol, rtol):
+    """One attempt of the adaptive RK45 step (section 3): the seven stages
+    of the tableau, the fifth-order solution P5 and the error estimate
+    err = max over cells and components of |h sum_j (B_j - BS_j) k_j| /
+    (atol + rtol max(|P|, |P5|)).  Accepted if err <= 1.  The next step
+    size is h min(5, max(0.2, 0.9 err^(-1/5))) when accepted and
+    h max(0.2, 0.9 err^(-1/5)) when rejected.  Returns (P5 or P, accepted,
+    h_next, err)."""
+    k = []
+    X = P
+    for i in range(7):
+        if i > 0:
+            X = prob.mask(P + h * sum(a * kj for a, kj in zip(DP_A[i], k)))
+        k.append(effective_field(X, prob))
+    P5 = X                                   # stage 7 is evaluated at the new state
+    e = h * sum((b - bs) * kj for b, bs, kj in zip(DP_B, DP_BS, k))
+    sc = atol + rtol * np.maximum(np.abs(P), np.abs(P5))
+    err = float(np.max(np.abs(e) / sc)) if e.size else 0.0
+    fac = 0.9 * err ** -0.2 if err > 0 else 5.0
+    if err <= 1.0:
+        return P5, True, h * min(5.0, max(0.2, fac)), err
+    return P, False, h * max(0.2, fac), err
+
+
+def run_rk45(P, prob: Problem, h, nsteps: int, atol, rtol):
+    """nsteps accepted RK45 steps from step size h; returns (P, tau, h,
+    rejected attempts)."""
+    tau, rejected, done = 0.0, 0, 0
+    while done < nsteps:
+        Pn, ok, hn, _ = step_rk45(P, prob, h, atol, rtol)
+        if ok:
+            tau += h
+            done += 1
+            P = Pn
+        else:
+            rejected += 1
+        h = hn
+    return P, tau, h, rejected
+
+
 def run(P, prob: Problem, scheme: str, dtau: float, nsteps: int, hist=None):
     """nsteps steps of "euler", "heun" or "ab3m2" (hist: the multistep
     history to continue from; a fresh run starts with an empty one)."""

@@ -158,3 +158,71 @@ def test_integrator_order(scheme, order):
         errs.append(np.abs(O.run(P0, prob, scheme, tau / m, m) - ref).max())
     rate = np.log2(errs[0] / errs[1])
     assert abs(rate - order) < (0.15 if order < 3 else 0.2), (errs, rate)
+
+
+def test_rk45_tableau_order_conditions():
+    """The Dormand-Prince weights satisfy the quadrature order conditions
+    (fifth order for B, fourth for BS), every row sums to its node, and the
+    last stage is taken at the fifth-order solution."""
+    A, B, BS, C = O.DP_A, np.array(O.DP_B), np.array(O.DP_BS), np.array(O.DP_C)
+    for i in range(1, 7):
+        assert abs(sum(A[i]) - C[i]) < 1e-15
+    assert np.allclose(A[6] + [0.0], B, rtol=0, atol=1e-16)
+    for q in range(5):
+        assert abs(np.dot(B, C ** q) - 1 / (q + 1)) < 1e-14, q
+    for q in range(4):
+        assert abs(np.dot(BS, C ** q) - 1 / (q + 1)) < 1e-14, q
+    # third-order tree sum_i b_i sum_j a_ij c_j = 1/6 (both weight sets)
+    ac = np.array([0.0] + [np.dot(A[i], C[:i]) for i in range(1, 7)])
+    assert abs(np.dot(B, ac) - 1 / 6) < 1e-14 and abs(np.dot(BS, ac) - 1 / 6) < 1e-14
+
+
+def _mode_problem():
+    n = (8, 6, 5)
+    prob = O.Problem(_linear_cfg(n, (1, 0, 0)))
+    nx, ny, nz = n
+    mode = (np.cos(np.pi * (np.arange(nz) + 0.5) / nz)[:, None, None]
+            * np.cos(np.pi * 2 * (np.arange(ny) + 0.5) / ny)[None, :, None]
+            * np.cos(2 * np.pi * np.arange(nx) / nx)[None, None, :])
+    P0 = np.array([0.3, -0.2, 0.1])[:, None, None, None] * mode[None]
+    lam = 2 * prob.coef[0, 0] + sum(
+        4 * np.sin(th / 2) ** 2 / prob.h[d] ** 2
+        for d, th in ((0, 2 * np.pi / nx), (1, 2 * np.pi / ny), (2, np.pi / nz)))
+    return prob, P0, lam
+
+
+def test_rk45_fifth_order_on_an_exact_mode():
+    """Fixed steps (tolerances so loose that every step is accepted): the
+    error against P0 exp(-lam tau) falls 32x per halving of h."""
+    prob, P0, lam = _mode_problem()
+    tau = 0.1                                  # h lam from 0.36 down to 0.09
+    errs = []
+    for m in (16, 32, 64):
+        P = P0
+        for _ in range(m):
+            P, ok, _, _ = O.step_rk45(P, prob, tau / m, 1e30, 1e30)
+            assert ok
+        errs.append(np.abs(P - P0 * np.exp(-lam * tau)).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 5) < 0.3), (errs, rates)
+
+
+def test_rk45_error_control_follows_the_tolerance():
+    """Adaptive runs to the same time: the error against the exact mode
+    shrinks with rtol, stays within a small multiple of it, and the tighter
+    run takes more steps."""
+    prob, P0, lam = _mode_problem()
+    results = []
+    for rtol in (1e-5, 1e-8):
+        P, tau, h, tries = P0, 0.0, 1e-3, 0
+        steps = 0
+        while tau < 0.4 - 1e-15:
+            hh = min(h, 0.4 - tau)
+            Pn, ok, h, _ = O.step_rk45(P, prob, hh, 1e-12, rtol)
+            if ok:
+                P, tau, steps = Pn, tau + hh, steps + 1
+        err = np.abs(P - P0 * np.exp(-lam * 0.4)).max() / np.abs(P0).max()
+        results.append((err, steps))
+    (e1, s1), (e2, s2) = results
+    assert e2 < e1 and s2 > s1
+    assert e1 < 10 * 1e-5 and e2 < 10 * 1e-8, results
