@@ -53,7 +53,7 @@ typedef enum {
 } tdgl_status;
 
 enum { TDGL_FP32 = 0, TDGL_FP64 = 1 };            /* arithmetic of the step     */
-enum { TDGL_EULER = 0, TDGL_HEUN = 1, TDGL_AB3M2 = 2 };   /* integrators        */
+enum { TDGL_EULER = 0, TDGL_HEUN = 1, TDGL_AB3M2 = 2, TDGL_RK45 = 3 };   /* integrators */
 /* energy terms (section 3: each contribution can be switched on or off) */
 enum { TDGL_LANDAU = 1, TDGL_GRAD = 2, TDGL_ELEC = 4, TDGL_EXT = 8, TDGL_ALL = 15 };
 
@@ -196,8 +196,24 @@ tdgl_status tdgl_set_terms(tdgl_ctx *ctx, unsigned mask);
  * corrector, two field evaluations per step, started by two Heun steps.
  * AB3M2 keeps the fields of the last two steps: it allocates three P-sized
  * device buffers on first use (outside the workspace), and tdgl_set_P, this
- * call and tdgl_autotune restart it (the next two steps are Heun steps). */
+ * call and tdgl_autotune restart it (the next two steps are Heun steps).
+ * TDGL_RK45: the adaptive Dormand-Prince 5(4) pair, seven field evaluations
+ * per attempt; dtau is the first trial step, tdgl_step(n) makes n accepted
+ * steps (see tdgl_set_rk_tolerances); RK45 steps are launched eagerly and
+ * synchronise once per attempt.  This call resets the RK45 time and step. */
 tdgl_status tdgl_set_integrator(tdgl_ctx *ctx, int scheme, double dtau);
+
+/* RK45 error control: an attempt is accepted when, over every cell and
+ * component of every instance, |h sum_j (b_j - b*_j) k_j| <= atol +
+ * rtol max(|P_n|, |P_n+1|) (reduced units, P/P0); the next step is h times
+ * min(5, max(0.2, 0.9 err^-1/5)) after acceptance, max(0.2, 0.9 err^-1/5)
+ * after rejection (a batch shares one step size).  Defaults 1e-8, 1e-6.
+ * Errors: TDGL_E_ARG for negative, non-finite or both-zero tolerances. */
+tdgl_status tdgl_set_rk_tolerances(tdgl_ctx *ctx, double atol, double rtol);
+
+/* RK45 progress since tdgl_set_integrator: reduced time of the accepted
+ * steps, the current step size and the number of rejected attempts. */
+tdgl_status tdgl_get_rk_state(const tdgl_ctx *ctx, double *tau, double *h, long long *rejected);
 
 /* Number of steps captured per HIP graph by tdgl_step (default 64; 0 runs
  * plain stream launches). */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtdgl.so")
 TDGL_OK, TDGL_E_ARG, TDGL_E_NOMEM, TDGL_E_HIP = 0, -1, -2, -3
 TDGL_E_NONFINITE, TDGL_E_STATE, TDGL_E_UNSUPPORTED = -4, -5, -6
 TDGL_FP32, TDGL_FP64 = 0, 1
-TDGL_EULER, TDGL_HEUN, TDGL_AB3M2 = 0, 1, 2
+TDGL_EULER, TDGL_HEUN, TDGL_AB3M2, TDGL_RK45 = 0, 1, 2, 3
 TDGL_LANDAU, TDGL_GRAD, TDGL_ELEC, TDGL_EXT, TDGL_ALL = 1, 2, 4, 8, 15
 TDGL_MAX_MATERIALS = 16
 
@@ -75,6 +75,9 @@ _SIGS = {
     "tdgl_set_terms": ([_ctx_p, c_uint], c_int),
     "tdgl_set_integrator": ([_ctx_p, c_int, c_double], c_int),
     "tdgl_set_graph_chunk": ([_ctx_p, c_int], c_int),
+    "tdgl_set_rk_tolerances": ([_ctx_p, c_double, c_double], c_int),
+    "tdgl_get_rk_state": ([_ctx_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                           ctypes.POINTER(ctypes.c_longlong)], c_int),
     "tdgl_set_P": ([_ctx_p, c_void_p, c_int, c_int], c_int),
     "tdgl_get_P": ([_ctx_p, c_void_p, c_int, c_int], c_int),
     "tdgl_step": ([_ctx_p, ctypes.c_longlong], c_int),
@@ -319,6 +322,18 @@ def tdgl_autotune(ctx, nsteps: int):
     return ch[0], ch[1], ms.value
 
 
+def tdgl_set_rk_tolerances(ctx, atol: float, rtol: float):
+    _check(ctx, lib().tdgl_set_rk_tolerances(ctx, atol, rtol))
+
+
+def tdgl_get_rk_state(ctx):
+    """(reduced time, current step, rejected attempts) of the RK45 run."""
+    tau, h, rej = c_double(), c_double(), ctypes.c_longlong()
+    _check(ctx, lib().tdgl_get_rk_state(ctx, ctypes.byref(tau), ctypes.byref(h),
+                                        ctypes.byref(rej)))
+    return tau.value, h.value, rej.value
+
+
 def tdgl_sync(ctx):
     _check(ctx, lib().tdgl_sync(ctx))
 
@@ -371,7 +386,8 @@ class Context:
             tdgl_set_temperatures(self.ctx, cfg["T"])
         tdgl_set_eext(self.ctx, *cfg.get("eext", (0.0, 0.0, 0.0)))
         tdgl_set_terms(self.ctx, cfg.get("terms", TDGL_ALL))
-        schemes = {"euler": TDGL_EULER, "heun": TDGL_HEUN, "ab3m2": TDGL_AB3M2}
+        schemes = {"euler": TDGL_EULER, "heun": TDGL_HEUN, "ab3m2": TDGL_AB3M2,
+                   "rk45": TDGL_RK45}
         tdgl_set_integrator(self.ctx, schemes[cfg.get("scheme", "heun")], cfg.get("dtau", 1e-3))
         if build_tensor and (cfg.get("terms", TDGL_ALL) & TDGL_ELEC):
             tdgl_build_tensor(self.ctx, cfg.get("mimg", 16))

@@ -37,7 +37,9 @@ struct Geom {
 // Update kernel modes.  UPD_STEP_MS: stages of the multistep scheme
 // (0: Heun predictor that also stores E; 2: Adams-Bashforth predictor that
 // stores E; 3: Adams-Moulton corrector).
-enum { UPD_STEP = 0, UPD_FIELD = 1, UPD_ENERGY = 2, UPD_STEP_MS = 3 };
+// UPD_STEP_RK: stage s = 1..7 of the RK45 step (stages 1-6 store k_s and
+// form the next stage point; stage 7 stores k_7 and reduces the error).
+enum { UPD_STEP = 0, UPD_FIELD = 1, UPD_ENERGY = 2, UPD_STEP_MS = 3, UPD_STEP_RK = 4 };
 
 struct UpdArgs {
     const void *P_in;      // state the field is evaluated at
@@ -56,6 +58,10 @@ struct UpdArgs {
     void *hist_w;          // STEP_MS stages 0, 2: E of P_in is stored here
     const void *hist_a;    // STEP_MS stage 2: E_{n-1}; stage 3: E_n
     const void *hist_b;    // STEP_MS stage 2: E_{n-2}; stage 3: E_{n-1}
+    const void *rk_base;   // STEP_RK: P_n
+    void *rk_k;            // STEP_RK: k_1..k_7, each [nb][3][nz][ny][nx]
+    double rk_h;           // STEP_RK: step size
+    double rk_atol, rk_rtol;
 };
 
 // spectra are kx-major: x pass output element k of row r at out[k*out_kstride + r]

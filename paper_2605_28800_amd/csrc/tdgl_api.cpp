@@ -79,6 +79,9 @@ struct tdgl_ctx {
     int cur = 0;
     int yt = 2;
     void *hist = nullptr;         // multistep: three E buffers (lazy, own allocation)
+    void *rkbuf = nullptr;        // RK45: stage point Q and k_1..k_7 (lazy, own allocation)
+    double rk_h = 0.0, rk_tau = 0.0, rk_atol = 1e-8, rk_rtol = 1e-6;
+    long long rk_rejected = 0;
     int hist_count = 0;           // valid history entries (0..2)
     int hist_pos = 0;             // buffer of the newest entry
     size_t lds_max = 65536;      // dynamic LDS one work-group may use on this device
@@ -610,6 +613,7 @@ void tdgl_destroy(tdgl_ctx *c)
         drop_graphs(c);
         if (c->ws_owned && c->ws) (void)hipFree(c->ws);
         if (c->hist) (void)hipFree(c->hist);
+        if (c->rkbuf) (void)hipFree(c->rkbuf);
         if (c->cap) (void)hipStreamDestroy(c->cap);
     }
     delete c;
@@ -828,12 +832,16 @@ tdgl_status tdgl_set_terms(tdgl_ctx *c, unsigned mask)
 tdgl_status tdgl_set_integrator(tdgl_ctx *c, int scheme, double dtau)
 {
     if (!c) return TDGL_E_ARG;
-    if (scheme != TDGL_EULER && scheme != TDGL_HEUN && scheme != TDGL_AB3M2)
+    if (scheme != TDGL_EULER && scheme != TDGL_HEUN && scheme != TDGL_AB3M2 &&
+        scheme != TDGL_RK45)
         return fail(c, TDGL_E_ARG, "unknown scheme");
     if (!(dtau > 0) || !std::isfinite(dtau)) return fail(c, TDGL_E_ARG, "dtau must be > 0");
     c->scheme = scheme;
     c->dtau = dtau;
     c->hist_count = 0;            // the multistep history assumes one dtau
+    c->rk_h = dtau;               // RK45: first trial step
+    c->rk_tau = 0.0;
+    c->rk_rejected = 0;
     c->params_dirty = true;
     return TDGL_OK;
 }
@@ -937,6 +945,98 @@ tdgl_status tdgl_get_P(tdgl_ctx *c, void *dst, int on_dev, int dst_prec)
     return read_flag(c);
 }
 
+namespace {
+
+// One accepted RK45 step (attempts repeat until one is accepted).
+tdgl_status rk45_step(tdgl_ctx *c)
+{
+    const Geom &g = c->g;
+    const size_t n3 = (size_t)3 * g.nx * g.ny * g.nz * g.nb;
+    const size_t pbytes = n3 * c->esz;
+    if (!c->rkbuf) {
+        if (hipMalloc(&c->rkbuf, 8 * pbytes) != hipSuccess) {
+            c->rkbuf = nullptr;
+            return fail(c, TDGL_E_NOMEM, "RK45 buffers: hipMalloc failed");
+        }
+    }
+    const bool el = elec_on(c);
+    const int ngroups = ((g.ny + c->yt - 1) / c->yt) * g.nz * g.nb;
+    std::vector<double> part((size_t)ngroups * 8);
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        void *Pn = c->P[c->cur], *W0 = c->P[1 - c->cur];
+        void *Q = c->rkbuf;
+        void *K = static_cast<char *>(c->rkbuf) + pbytes;
+        if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, Pn, c->stream));
+        UpdArgs a{};
+        a.S1 = c->S1;
+        a.coef = c->coef;
+        a.kp = c->kp;
+        a.partials = c->partials;
+        a.flag = c->flag;
+        a.terms = c->terms;
+        a.elec_in = el ? 1 : 0;
+        a.fx_out = el ? 1 : 0;
+        a.yt = c->yt;
+        a.rk_base = Pn;
+        a.rk_k = K;
+        a.rk_h = c->rk_h;
+        a.rk_atol = c->rk_atol;
+        a.rk_rtol = c->rk_rtol;
+        // stage s reads the point written by stage s - 1; the fifth-order
+        // solution (stage 6 output) lands in W0 = P[1 - cur]
+        const void *in = Pn;
+        for (int st = 1; st <= 7; ++st) {
+            if (el) HIP_TRY(c, enq_yz(c, c->stream));
+            void *out = st == 7 ? const_cast<void *>(in) : ((st % 2 == 0) ? W0 : Q);
+            a.stage = st;
+            a.P_in = in;
+            a.P_out = out;
+            HIP_TRY(c, launch_update(c->prec, UPD_STEP_RK, g, a, tw(c), c->stream, nullptr));
+            in = out;
+        }
+        HIP_TRY(c, hipMemcpyAsync(part.data(), c->partials, part.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        double err = 0.0;
+        for (int i = 0; i < ngroups; ++i) err = part[(size_t)i * 8] > err ? part[(size_t)i * 8] : err;
+        if (!std::isfinite(err)) return fail(c, TDGL_E_NONFINITE, "RK45 error estimate not finite");
+        const double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 5.0;
+        if (err <= 1.0) {                        // accept: P5 (and its spectrum) is current
+            c->rk_tau += c->rk_h;
+            c->rk_h *= std::min(5.0, std::max(0.2, fac));
+            c->cur = 1 - c->cur;
+            c->spec_valid = el;
+            return TDGL_OK;
+        }
+        ++c->rk_rejected;                        // reject: retry from P_n
+        c->rk_h *= std::max(0.2, fac);
+        c->spec_valid = false;
+    }
+    return fail(c, TDGL_E_NONFINITE, "RK45: 64 rejected attempts in a row");
+}
+
+}  // namespace
+
+tdgl_status tdgl_set_rk_tolerances(tdgl_ctx *c, double atol, double rtol)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!(atol >= 0) || !(rtol >= 0) || !(atol + rtol > 0) || !std::isfinite(atol) ||
+        !std::isfinite(rtol))
+        return fail(c, TDGL_E_ARG, "tolerances must be >= 0, finite, not both 0");
+    c->rk_atol = atol;
+    c->rk_rtol = rtol;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_rk_state(const tdgl_ctx *c, double *tau, double *h, long long *rejected)
+{
+    if (!c || !tau || !h || !rejected) return TDGL_E_ARG;
+    *tau = c->rk_tau;
+    *h = c->rk_h;
+    *rejected = c->rk_rejected;
+    return TDGL_OK;
+}
+
 tdgl_status tdgl_step(tdgl_ctx *c, long long nsteps)
 {
     if (!c) return TDGL_E_ARG;
@@ -949,6 +1049,13 @@ tdgl_status tdgl_step(tdgl_ctx *c, long long nsteps)
     if (st != TDGL_OK) return st;
     const bool el = elec_on(c);
     if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    if (c->scheme == TDGL_RK45) {
+        for (long long i = 0; i < nsteps; ++i) {
+            st = rk45_step(c);
+            if (st != TDGL_OK) return st;
+        }
+        return TDGL_OK;
+    }
     const bool ms = c->scheme == TDGL_AB3M2;
     long long left = nsteps;
     if (ms) {

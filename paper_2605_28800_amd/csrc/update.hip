@@ -45,6 +45,20 @@ __device__ __forceinline__ T landau_f(const T sq[3], const T *cf)
            cf[6] * (x * x * (y + z) + y * y * (x + z) + z * z * (x + y)) + cf[7] * x * y * z;
 }
 
+// Dormand-Prince 5(4) tableau (Dormand & Prince 1980): row s of RK_A gives
+// the weights of k_1..k_s for the stage point s + 1 (row 6 is the
+// fifth-order solution); RK_E = fifth- minus fourth-order weights.
+__constant__ double RK_A[6][6] = {
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+__constant__ double RK_E[7] = {35.0 / 384 - 5179.0 / 57600, 0, 500.0 / 1113 - 7571.0 / 16695,
+                               125.0 / 192 - 393.0 / 640, -2187.0 / 6784 + 92097.0 / 339200,
+                               11.0 / 84 - 187.0 / 2100, -1.0 / 40};
+
 template <typename T>
 struct UpdMaxThreads {    // FP64 groups stay at 512 threads (room for 256 VGPRs)
     static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
@@ -88,7 +102,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const KParams<T> *kp = reinterpret_cast<const KParams<T> *>(a.kp);
     const bool material = coefz[8] != T(0);
     const unsigned terms = a.terms;
-    constexpr bool STEPPING = MODE == UPD_STEP || MODE == UPD_STEP_MS;
+    constexpr bool STEPPING = MODE == UPD_STEP || MODE == UPD_STEP_MS || MODE == UPD_STEP_RK;
+    T rkerr = T(0);                            // STEP_RK stage 7: max scaled error
     const bool do_fx = STEPPING && a.fx_out;
     const int ny_here = ny - y0 < yt ? ny - y0 : yt;
 
@@ -260,6 +275,36 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                     else if (a.stage == 0) o[c] = p[c] + dtau * E[c];
                     else o[c] = T(0.5) * (co[i][c] + p[c]) + T(0.5) * dtau * E[c];
                 }
+            } else if constexpr (MODE == UPD_STEP_RK) {
+                // k_s = E at this stage point; stages 1-6 form the next point
+                // P_n + h sum_j A[s][j] k_j, stage 7 the error estimate
+                const int st = a.stage;
+                const long long ko = 3LL * g.nb * comp;          // one k buffer
+                const long long ho = 3LL * b * comp + off;
+                T *K = reinterpret_cast<T *>(a.rk_k);
+                const T *Pn = reinterpret_cast<const T *>(a.rk_base);
+                const T h = (T)a.rk_h;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T e = material ? E[c] : T(0);
+                    K[(st - 1) * ko + c * comp + ho] = e;
+                    const T pn = Pn[c * comp + ho];
+                    if (st < 7) {
+                        T acc = T(RK_A[st - 1][st - 1]) * e;
+                        for (int j = 0; j < st - 1; ++j)
+                            acc += T(RK_A[st - 1][j]) * K[j * ko + c * comp + ho];
+                        o[c] = material ? pn + h * acc : T(0);
+                    } else {
+                        T acc = T(RK_E[6]) * e;
+                        for (int j = 0; j < 6; ++j)
+                            acc += T(RK_E[j]) * K[j * ko + c * comp + ho];
+                        const T sc = T(a.rk_atol) +
+                                     T(a.rk_rtol) * (fabs(pn) > fabs(p[c]) ? fabs(pn) : fabs(p[c]));
+                        const T r = fabs(h * acc) / sc;
+                        rkerr = r > rkerr ? r : rkerr;
+                        o[c] = p[c];                             // P5 itself (for the spectrum)
+                    }
+                }
             } else {
                 // multistep stages; the history holds E at the corrected states
                 const long long ho = 3LL * b * comp + off;
@@ -284,9 +329,10 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                 }
             }
             bool bad = false;
+            const bool store = !(MODE == UPD_STEP_RK && a.stage == 7);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Pout[c * comp + off] = o[c];
+                if (store) Pout[c * comp + off] = o[c];
                 bad = bad || !isfinite(o[c]);
                 if (do_fx) hs[((c << ysh) + yy) * HS + x] = o[c];
             }
@@ -339,6 +385,25 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             if (has) {
                 s1row[(long long)(t + q * TPL) * kst] = xk;
                 if (t == 0 && q == 0) s1row[(long long)M2 * kst] = xh;
+            }
+        }
+    }
+
+    if constexpr (MODE == UPD_STEP_RK) {
+        if (a.stage == 7) {                      // block maximum of the scaled error
+            double m = (double)rkerr;
+            for (int o2 = 32; o2 > 0; o2 >>= 1) {
+                const double v = __shfl_xor(m, o2, 64);
+                m = v > m ? v : m;
+            }
+            __syncthreads();
+            double *red = reinterpret_cast<double *>(smem_raw);
+            if (lane == 0) red[tid >> 6] = m;
+            __syncthreads();
+            if (tid == 0) {
+                double mm = 0.0;
+                for (int w = 0; w < (nthr + 63) / 64; ++w) mm = red[w] > mm ? red[w] : mm;
+                a.partials[(long long)tile * 8] = mm;
             }
         }
     }
@@ -448,6 +513,7 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
     switch (mode) {                                                                       \
     case UPD_STEP: return update_impl<T, LEN, UPD_STEP>(g, a, tw, s, nblocks_out);        \
     case UPD_STEP_MS: return update_impl<T, LEN, UPD_STEP_MS>(g, a, tw, s, nblocks_out);  \
+    case UPD_STEP_RK: return update_impl<T, LEN, UPD_STEP_RK>(g, a, tw, s, nblocks_out);  \
     case UPD_FIELD: return update_impl<T, LEN, UPD_FIELD>(g, a, tw, s, nblocks_out);      \
     default: return update_impl<T, LEN, UPD_ENERGY>(g, a, tw, s, nblocks_out);            \
     }

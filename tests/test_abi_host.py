@@ -195,3 +195,17 @@ def test_triangle_wave_shape():
     w = T.triangle_wave(2.0, 8)
     assert np.allclose(w, [1, 2, 1, 0, -1, -2, -1, 0])
     assert T.triangle_wave(1.0, 400).max() == 1.0 and T.triangle_wave(1.0, 400).min() == -1.0
+
+
+def test_rk_tolerance_validation():
+    g = T.tdgl_grid(8, 8, 8, 1e-9, 1e-9, 1e-9, 0)
+    ctx = T.tdgl_create(g, T.TDGL_FP64)
+    try:
+        for bad in ((-1.0, 1e-6), (0.0, 0.0), (float("nan"), 1e-6), (1e-8, float("inf"))):
+            with pytest.raises(T.TdglError):
+                T.tdgl_set_rk_tolerances(ctx, *bad)
+        T.tdgl_set_rk_tolerances(ctx, 0.0, 1e-6)
+        T.tdgl_set_integrator(ctx, T.TDGL_RK45, 2e-3)
+        assert T.tdgl_get_rk_state(ctx) == (0.0, 2e-3, 0)
+    finally:
+        T.tdgl_destroy(ctx)

@@ -201,3 +201,47 @@ def test_ab3m2_film_fp32():
         ctx.close()
     ref = O.run(P0.astype(np.float64), prob, "ab3m2", cfg["dtau"], 150)
     assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-5
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_rk45_adaptive_fp64(path):
+    """Adaptive RK45 on the FP64 box against the oracle's same controller:
+    the same accepted time, next step and number of rejected attempts
+    (the step grows until the stiff modes reject it), and the same state."""
+    cfg = I.config("c1")
+    cfg["scheme"] = "rk45"
+    announce("RK45 adaptive fp64 path %d" % path)
+    P0 = I.initial_P(cfg, 0)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64", path=path)
+    try:
+        T.tdgl_set_rk_tolerances(ctx.ctx, 1e-9, 1e-7)
+        ctx.set_P(P0)
+        ctx.step(25)
+        tau, h, rej = T.tdgl_get_rk_state(ctx.ctx)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    P, tau_o, h_o, rej_o = O.run_rk45(P0, prob, cfg["dtau"], 25, 1e-9, 1e-7)
+    assert rej == rej_o and rej_o > 0, (rej, rej_o)
+    assert abs(tau - tau_o) <= 1e-12 * tau_o and abs(h - h_o) <= 1e-10 * h_o
+    assert np.abs(got - P).max() / ps_of(cfg) <= 1e-11
+
+
+def test_rk45_fp32_film_relaxes():
+    cfg = I.config("c2_small")
+    cfg["scheme"] = "rk45"
+    announce("RK45 fp32 film")
+    ctx = gpu_context(cfg, "f32")
+    try:
+        T.tdgl_set_rk_tolerances(ctx.ctx, 1e-6, 1e-4)
+        ctx.set_P(I.initial_P(cfg, 0, np.float32))
+        F = [ctx.energies()[0][4]]
+        for _ in range(3):
+            ctx.step(10)
+            F.append(ctx.energies()[0][4])
+        tau, h, rej = T.tdgl_get_rk_state(ctx.ctx)
+    finally:
+        ctx.close()
+    assert tau > 30 * cfg["dtau"] and h > 0
+    assert np.all(np.diff(F) < 0), F
