@@ -82,15 +82,16 @@ class Problem:
         assert self.layers.shape == (nz,)
         self.materials = cfg["materials"]
         self.set_temperature(cfg["T"])
-        # gradient: eq 4, diagonal part; g[i, d] multiplies d_dd P_i
+        # gradient (eq 4): g[i, d] multiplies the squared derivative of P_i
+        # along d (G11 along the component, G44 + G44' across); g12 and gm
+        # (= G44 - G44') multiply the cross products P_i,i P_j,j and P_i,j P_j,i
         G = cfg["gradient"]
-        mixed = G["G12"] + G["G44"] - G["G44p"]
-        if abs(mixed) > 1e-12 * abs(G["G11"]):
-            raise NotImplementedError("mixed-derivative gradient terms (G12+G44-G44' != 0)")
         self.g = np.empty((3, 3))
         for i in range(3):
             for d in range(3):
                 self.g[i, d] = (G["G11"] if i == d else G["G44"] + G["G44p"]) / self.G110
+        self.g12 = G["G12"] / self.G110
+        self.gm = (G["G44"] - G["G44p"]) / self.G110
         self.tab = None
         if tensor and (self.terms & ELEC):
             self.tab = offset_table(self.n, self.periodic, self.mimg, self.h)
@@ -184,8 +185,37 @@ def _neighbour_valid_uncached(prob: Problem, axis_arr: int, shift: int):
     return valid & mat & nb_mat
 
 
+def _cdiff(Q, prob: Problem, dim: int):
+    """Central difference of the cell field Q ([nz][ny][nx]) along physical
+    dimension dim, (Q(c+d) - Q(c-d)) / (2 h_d), where a missing neighbour
+    (open surface, vacuum) is replaced by Q(c)."""
+    axis_arr = 2 - dim
+    up = np.where(_neighbour_valid(prob, axis_arr, +1), np.roll(Q, -1, axis=axis_arr), Q)
+    dn = np.where(_neighbour_valid(prob, axis_arr, -1), np.roll(Q, 1, axis=axis_arr), Q)
+    return (up - dn) / (2.0 * prob.h[dim])
+
+
+def _cdiff_adj(F, prob: Problem, dim: int):
+    """Adjoint of _cdiff: (A^T F)(c) = sum_c' F(c') d(_cdiff Q)(c')/dQ(c)."""
+    axis_arr = 2 - dim
+    vup = _neighbour_valid(prob, axis_arr, +1)
+    vdn = _neighbour_valid(prob, axis_arr, -1)
+    out = np.where(vdn, np.roll(F, 1, axis=axis_arr), 0.0)      # c' = c - d sees c as its +d
+    out -= np.where(vup, np.roll(F, -1, axis=axis_arr), 0.0)    # c' = c + d sees c as its -d
+    out += F * ((~vup).astype(float) - (~vdn).astype(float))    # c' = c where c replaced a neighbour
+    return out / (2.0 * prob.h[dim])
+
+
+# the cross terms of eq 4, one per unordered component pair (i, j):
+#   G12: P_i,i P_j,j  and  G44 - G44': P_i,j P_j,i
+_CROSS_PAIRS = ((0, 1), (1, 2), (2, 0))
+
+
 def gradient_field(P, prob: Problem):
-    """H_G,i = sum_d g[i,d] * sum_{existing nb along d} (P_nb - P_c)/h_d^2."""
+    """H_G = -(1/dV) dF_G/dP for the discrete eq 4: the diagonal part
+    sum_d g[i,d] sum_{existing nb along d} (P_nb - P_c)/h_d^2 plus, when
+    G12 or G44 - G44' is non-zero, the derivative of the cross terms
+    (central differences with missing neighbours replaced by the cell)."""
     H = np.zeros_like(P)
     for axis_arr in range(3):
         dim = 2 - axis_arr
@@ -194,11 +224,22 @@ def gradient_field(P, prob: Problem):
             Pnb = np.roll(P, -shift, axis=axis_arr + 1)
             for i in range(3):
                 H[i] += np.where(valid, prob.g[i, dim] * (Pnb[i] - P[i]) / prob.h[dim]**2, 0.0)
+    if prob.g12 != 0.0 or prob.gm != 0.0:
+        D = {(i, d): _cdiff(P[i], prob, d) for i in range(3) for d in range(3)}
+        for i, j in _CROSS_PAIRS:
+            # G12 P_i,i P_j,j
+            H[i] -= prob.g12 * _cdiff_adj(D[(j, j)], prob, i)
+            H[j] -= prob.g12 * _cdiff_adj(D[(i, i)], prob, j)
+            # (G44 - G44') P_i,j P_j,i
+            H[i] -= prob.gm * _cdiff_adj(D[(j, i)], prob, j)
+            H[j] -= prob.gm * _cdiff_adj(D[(i, j)], prob, i)
+        H[:, ~prob.material] = 0.0
     return H
 
 
 def gradient_energy(P, prob: Problem):
-    """F_G* = dV* sum over edges (a,b) along d of (g[i,d]/2)|P_a,i - P_b,i|^2/h_d^2."""
+    """F_G* = dV* [sum over edges (a,b) along d of (g[i,d]/2)|P_a,i - P_b,i|^2/h_d^2
+    + sum over material cells of the cross terms of eq 4]."""
     F = 0.0
     for axis_arr in range(3):
         dim = 2 - axis_arr
@@ -207,6 +248,12 @@ def gradient_energy(P, prob: Problem):
         for i in range(3):
             e = np.where(valid, 0.5 * prob.g[i, dim] * (Pnb[i] - P[i])**2 / prob.h[dim]**2, 0.0)
             F += e.sum()
+    if prob.g12 != 0.0 or prob.gm != 0.0:
+        D = {(i, d): _cdiff(P[i], prob, d) for i in range(3) for d in range(3)}
+        mat = np.broadcast_to(prob.material[:, None, None], P.shape[1:])
+        for i, j in _CROSS_PAIRS:
+            cross = prob.g12 * D[(i, i)] * D[(j, j)] + prob.gm * D[(i, j)] * D[(j, i)]
+            F += np.where(mat, cross, 0.0).sum()
     return prob.dV * F
 
 
