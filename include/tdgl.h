@@ -152,9 +152,14 @@ tdgl_status tdgl_set_material(tdgl_ctx *ctx, int id, const tdgl_material *mat);
  * ids[nz]; -1 marks a vacuum layer, where P is held at zero. */
 tdgl_status tdgl_set_layer_materials(tdgl_ctx *ctx, const signed char *ids);
 
-/* Gradient coefficients of eq 4 (N m^4 C^-2).  This library handles the
- * diagonal part exactly: d/dP_i gives G11 d_ii P_i + (G44 + G44') d_jj P_i;
- * a non-zero mixed coefficient G12 + G44 - G44' returns TDGL_E_UNSUPPORTED. */
+/* Gradient coefficients of eq 4 (N m^4 C^-2), the same for the whole
+ * sample.  Discretised as an energy: squared derivatives on the cell
+ * edges (G11 along the component, G44 + G44' across, the 7-point stencil)
+ * plus, for the cross products G12 P_i,i P_j,j and (G44 - G44') P_i,j P_j,i,
+ * cell-centred central differences in which a missing neighbour (open
+ * surface, vacuum) takes the cell's own value; the field is minus the
+ * exact gradient of that discrete energy, in the interior
+ * G11 d_ii P_i + (G44 + G44') d_jj P_i + (G12 + G44 - G44') d_ij P_j. */
 tdgl_status tdgl_set_gradient(tdgl_ctx *ctx, double G11, double G12, double G44,
                               double G44p);
 

@@ -23,7 +23,9 @@ struct KParams {
     T eext[3];       // reduced applied field
     T gh2[3][3];     // g[i][d] / h_d^2: gradient coefficient of component i along d
     T out_scale;     // V/m per reduced field unit (field output)
-    T pad[2];
+    T g12, gm;       // cross terms of the gradient energy: G12, G44 - G44' (reduced)
+    T inv2h[3];      // 1 / (2 h_d), reduced cell sizes
+    T pad[3];
 };
 
 struct Geom {
@@ -62,7 +64,12 @@ struct UpdArgs {
     void *rk_k;            // STEP_RK: k_1..k_7, each [nb][3][nz][ny][nx]
     double rk_h;           // STEP_RK: step size
     double rk_atol, rk_rtol;
+    const void *cross;     // field of the gradient cross terms (k_cross), or null
 };
+
+// field of the cross terms of the gradient energy (G12, G44 - G44') of P
+hipError_t launch_cross(int prec, const Geom &g, const void *P, void *H, const void *coef,
+                        const void *kp, hipStream_t s);
 
 // spectra are kx-major: x pass output element k of row r at out[k*out_kstride + r]
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,

@@ -80,6 +80,7 @@ struct tdgl_ctx {
     int yt = 2;
     void *hist = nullptr;         // multistep: three E buffers (lazy, own allocation)
     void *rkbuf = nullptr;        // RK45: stage point Q and k_1..k_7 (lazy, own allocation)
+    void *xbuf = nullptr;         // field of the gradient cross terms (lazy, own allocation)
     double rk_h = 0.0, rk_tau = 0.0, rk_atol = 1e-8, rk_rtol = 1e-6;
     long long rk_rejected = 0;
     int hist_count = 0;           // valid history entries (0..2)
@@ -341,6 +342,9 @@ tdgl_status upload_params_t(tdgl_ctx *c)
     for (int i = 0; i < 3; ++i)
         for (int dd = 0; dd < 3; ++dd) kp.gh2[i][dd] = (T)gh2[i][dd];
     kp.out_scale = (T)scal[6];
+    kp.g12 = c->grad_set ? (T)(c->G12 / c->G110) : T(0);
+    kp.gm = c->grad_set ? (T)((c->G44 - c->G44p) / c->G110) : T(0);
+    for (int k = 0; k < 3; ++k) kp.inv2h[k] = (T)(0.5 / scal[1 + k]);
     HIP_TRY(c, hipMemcpyAsync(c->coef, cf.data(), cf.size() * sizeof(T), hipMemcpyHostToDevice,
                               c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->kp, &kp, sizeof kp, hipMemcpyHostToDevice, c->stream));
@@ -349,6 +353,8 @@ tdgl_status upload_params_t(tdgl_ctx *c)
     return TDGL_OK;
 }
 
+bool cross_terms(const tdgl_ctx *c) { return c->grad_set && (c->G12 != 0.0 || c->G44 != c->G44p); }
+
 tdgl_status upload_params(tdgl_ctx *c)
 {
     if (!c->params_dirty) return TDGL_OK;
@@ -356,6 +362,13 @@ tdgl_status upload_params(tdgl_ctx *c)
     if (st != TDGL_OK) return st;
     st = ensure_device(c);
     if (st != TDGL_OK) return st;
+    if (cross_terms(c) && !c->xbuf) {
+        const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->g.nb * c->esz;
+        if (hipMalloc(&c->xbuf, pbytes) != hipSuccess) {
+            c->xbuf = nullptr;
+            return fail(c, TDGL_E_NOMEM, "gradient cross-term buffer: hipMalloc failed");
+        }
+    }
     return c->prec == PREC_F32 ? upload_params_t<float>(c) : upload_params_t<double>(c);
 }
 
@@ -391,10 +404,21 @@ hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
     return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny, tw(c), s);
 }
 
+// field of the gradient cross terms at Pin into xbuf, when the model has them
+hipError_t enq_cross(tdgl_ctx *c, const void *Pin, unsigned terms, UpdArgs &a, hipStream_t s)
+{
+    a.cross = nullptr;
+    if (!(terms & TDGL_GRAD) || !cross_terms(c) || !c->xbuf) return hipSuccess;
+    a.cross = c->xbuf;
+    return launch_cross(c->prec, c->g, Pin, c->xbuf, c->coef, c->kp, s);
+}
+
 hipError_t enq_upd(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
                    int stage, unsigned terms, bool elec_in, bool fx_out, hipStream_t s)
 {
     UpdArgs a{};
+    hipError_t ce = enq_cross(c, Pin, terms, a, s);
+    if (ce != hipSuccess) return ce;
     a.P_in = Pin;
     a.P_old = Pold;
     a.P_out = Pout;
@@ -452,14 +476,16 @@ hipError_t enq_step_ms(tdgl_ctx *c, int cur, int *count, int *pos, hipStream_t s
     a.P_out = B;
     if (*count < 2) {                                   // start-up: Heun, storing E_n
         a.stage = 0;
-        e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
+        e = enq_cross(c, A, t, a, s);
+        if (e == hipSuccess) e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
         if (e != hipSuccess) return e;
         e = enq_eval(c, UPD_STEP, B, A, A, 1, t, el, el, s);
     } else {
         a.stage = 2;                                    // AB3 predictor -> B
         a.hist_a = hist_buf(c, *pos);
         a.hist_b = hist_buf(c, (*pos + 2) % 3);
-        e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
+        e = enq_cross(c, A, t, a, s);
+        if (e == hipSuccess) e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
         if (e != hipSuccess) return e;
         if (el) e = enq_yz(c, s);                       // AM2 corrector -> A
         if (e != hipSuccess) return e;
@@ -470,7 +496,8 @@ hipError_t enq_step_ms(tdgl_ctx *c, int cur, int *count, int *pos, hipStream_t s
         a.hist_w = nullptr;
         a.hist_a = hist_buf(c, nw);
         a.hist_b = hist_buf(c, *pos);
-        e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
+        e = enq_cross(c, B, t, a, s);
+        if (e == hipSuccess) e = launch_update(c->prec, UPD_STEP_MS, c->g, a, tw(c), s, nullptr);
     }
     if (e != hipSuccess) return e;
     *pos = nw;
@@ -614,6 +641,7 @@ void tdgl_destroy(tdgl_ctx *c)
         if (c->ws_owned && c->ws) (void)hipFree(c->ws);
         if (c->hist) (void)hipFree(c->hist);
         if (c->rkbuf) (void)hipFree(c->rkbuf);
+        if (c->xbuf) (void)hipFree(c->xbuf);
         if (c->cap) (void)hipStreamDestroy(c->cap);
     }
     delete c;
@@ -707,10 +735,6 @@ tdgl_status tdgl_set_gradient(tdgl_ctx *c, double G11, double G12, double G44, d
     if (!c) return TDGL_E_ARG;
     if (!std::isfinite(G11) || !std::isfinite(G12) || !std::isfinite(G44) || !std::isfinite(G44p))
         return fail(c, TDGL_E_ARG, "gradient coefficients must be finite");
-    const double mixed = G12 + G44 - G44p;
-    const double scale = std::fabs(G11) + std::fabs(G44) + std::fabs(G44p);
-    if (std::fabs(mixed) > 1e-12 * scale)
-        return fail(c, TDGL_E_UNSUPPORTED, "mixed-derivative gradient term G12+G44-G44' != 0");
     c->G11 = G11;
     c->G12 = G12;
     c->G44 = G44;
@@ -991,6 +1015,7 @@ tdgl_status rk45_step(tdgl_ctx *c)
             a.stage = st;
             a.P_in = in;
             a.P_out = out;
+            HIP_TRY(c, enq_cross(c, in, c->terms, a, c->stream));
             HIP_TRY(c, launch_update(c->prec, UPD_STEP_RK, g, a, tw(c), c->stream, nullptr));
             in = out;
         }

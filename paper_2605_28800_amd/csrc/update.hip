@@ -59,6 +59,55 @@ __constant__ double RK_E[7] = {35.0 / 384 - 5179.0 / 57600, 0, 500.0 / 1113 - 75
                                125.0 / 192 - 393.0 / 640, -2187.0 / 6784 + 92097.0 / 339200,
                                11.0 / 84 - 187.0 / 2100, -1.0 / 40};
 
+// Cross terms of the gradient energy (G12 P_i,i P_j,j and (G44 - G44')
+// P_i,j P_j,i) for one cell, with cell-centred central differences in which
+// a missing neighbour takes the cell's own value.  The field is minus the
+// exact gradient of that discrete energy: with D_d the central difference
+// and D_d^T its adjoint,
+//   H_i -= g12 sum_{j != i} D_i^T(D_j P_j) + gm sum_{j != i} D_j^T(D_i P_j).
+// ex[2d + s]: neighbour of the cell along d on side s (0: -, 1: +) exists;
+// nb[2d + s]: its offset (the cell's own when missing); cn: the edge values
+// (centre when missing); P: component bases.  Corner (a s, b t) exists iff
+// both edges do (the layer map depends on z only).
+template <typename T>
+struct CrossArgs {
+    const T *P[3];
+    int off;
+    int nb[6];
+    bool ex[6];
+    T ih[3];            // 1 / (2 h_d)
+};
+
+// F(q) = D_b Q at q = cell + s a (s = -1, 0, +1)
+template <typename T>
+__device__ __forceinline__ T cross_db(const CrossArgs<T> &x, const T (&cn)[6][3], T pc, int comp,
+                                      int a, int s, int b)
+{
+    if (s == 0) return (cn[2 * b + 1][comp] - cn[2 * b][comp]) * x.ih[b];
+    const int e = 2 * a + (s > 0 ? 1 : 0);
+    if (!x.ex[e]) return T(0);                       // multiplied by 0 below
+    const int qa = x.nb[e];
+    const T qv = cn[e][comp];
+    const T up = x.ex[2 * b + 1] ? x.P[comp][qa + (x.nb[2 * b + 1] - x.off)] : qv;
+    const T dn = x.ex[2 * b] ? x.P[comp][qa + (x.nb[2 * b] - x.off)] : qv;
+    (void)pc;
+    return (up - dn) * x.ih[b];
+}
+
+// (D_a^T (D_b Q))(cell)
+template <typename T>
+__device__ __forceinline__ T cross_t(const CrossArgs<T> &x, const T (&cn)[6][3], T pc, int comp,
+                                     int a, int b)
+{
+    const bool em = x.ex[2 * a], ep = x.ex[2 * a + 1];
+    const T fm = cross_db(x, cn, pc, comp, a, -1, b);
+    const T fp = cross_db(x, cn, pc, comp, a, +1, b);
+    const T f0 = cross_db(x, cn, pc, comp, a, 0, b);
+    T r = (em ? fm : T(0)) - (ep ? fp : T(0));
+    r += f0 * (T(ep ? 0 : 1) - T(em ? 0 : 1));
+    return r * x.ih[a];
+}
+
 template <typename T>
 struct UpdMaxThreads {    // FP64 groups stay at 512 threads (room for 256 VGPRs)
     static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
@@ -255,6 +304,23 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                         fg += T(0.5) * (kp->gh2[c][0] * dx_ * dx_ + kp->gh2[c][1] * dy_ * dy_ +
                                         kp->gh2[c][2] * dz_ * dz_);
                     }
+                }
+                if (MODE == UPD_ENERGY && (kp->g12 != T(0) || kp->gm != T(0))) {
+                    // cross terms of eq 4 at the cell (central differences,
+                    // missing neighbours = the cell itself)
+                    T D[3][3];                               // D[i][d] = D_d P_i
+#pragma unroll
+                    for (int ci = 0; ci < 3; ++ci)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            D[ci][d] = (cn[i][2 * d + 1][ci] - cn[i][2 * d][ci]) * kp->inv2h[d];
+                    fg += kp->g12 * (D[0][0] * D[1][1] + D[1][1] * D[2][2] + D[2][2] * D[0][0]) +
+                          kp->gm * (D[0][1] * D[1][0] + D[1][2] * D[2][1] + D[2][0] * D[0][2]);
+                }
+                if (a.cross) {                               // their field, from k_cross
+                    const T *hx = reinterpret_cast<const T *>(a.cross) + 3LL * b * comp + off;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) E[c] += hx[c * comp];
                 }
             }
             if (a.elec_in) {
@@ -539,6 +605,78 @@ hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a, co
     } else {
         TDGL_UPD_LEN(double)
     }
+}
+
+// ------------------------------------------------------- gradient cross terms
+// Field of the cross terms of eq 4 for every cell of every instance
+// (see cross_t); vacuum cells get 0.  H: [nb][3][nz][ny][nx].
+template <typename T>
+__global__ void k_cross(const T *__restrict__ P, T *__restrict__ H, Geom g,
+                        const T *__restrict__ coef, const KParams<T> *__restrict__ kp)
+{
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int plane = nx * ny;
+    const long long comp = (long long)nz * plane;
+    const long long ncell = comp * g.nb;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(e / comp);
+        const int off = (int)(e - (long long)b * comp);
+        const int z = off / plane, y = (off - z * plane) / nx, x = off - z * plane - y * nx;
+        const T *cf = coef + (long long)b * nz * NCOEF;
+        T *Hb = H + 3LL * b * comp;
+        if (cf[(long long)z * NCOEF + 8] == T(0)) {
+            for (int c = 0; c < 3; ++c) Hb[c * comp + off] = T(0);
+            continue;
+        }
+        const int zm = z > 0 ? z - 1 : (g.pz ? nz - 1 : -1);
+        const int zp = z < nz - 1 ? z + 1 : (g.pz ? 0 : -1);
+        CrossArgs<T> xa;
+        const T *Pb = P + 3LL * b * comp;
+        xa.P[0] = Pb;
+        xa.P[1] = Pb + comp;
+        xa.P[2] = Pb + 2 * comp;
+        xa.off = off;
+        xa.ex[0] = x > 0 || g.px;
+        xa.ex[1] = x < nx - 1 || g.px;
+        xa.ex[2] = y > 0 || g.py;
+        xa.ex[3] = y < ny - 1 || g.py;
+        xa.ex[4] = zm >= 0 && cf[(long long)zm * NCOEF + 8] != T(0);
+        xa.ex[5] = zp >= 0 && cf[(long long)zp * NCOEF + 8] != T(0);
+        xa.nb[0] = x > 0 ? off - 1 : (g.px ? off + nx - 1 : off);
+        xa.nb[1] = x < nx - 1 ? off + 1 : (g.px ? off - nx + 1 : off);
+        xa.nb[2] = y > 0 ? off - nx : (g.py ? off + plane - nx : off);
+        xa.nb[3] = y < ny - 1 ? off + nx : (g.py ? off - plane + nx : off);
+        xa.nb[4] = xa.ex[4] ? off + (zm - z) * plane : off;
+        xa.nb[5] = xa.ex[5] ? off + (zp - z) * plane : off;
+        for (int d = 0; d < 3; ++d) xa.ih[d] = kp->inv2h[d];
+        T cn[6][3];
+        for (int d = 0; d < 6; ++d)
+            for (int c = 0; c < 3; ++c) cn[d][c] = xa.P[c][xa.nb[d]];
+        for (int ci = 0; ci < 3; ++ci) {
+            T hm = T(0);
+            for (int cj = 0; cj < 3; ++cj) {
+                if (cj == ci) continue;
+                hm += kp->g12 * cross_t(xa, cn, T(0), cj, ci, cj);
+                hm += kp->gm * cross_t(xa, cn, T(0), cj, cj, ci);
+            }
+            Hb[ci * comp + off] = -hm;
+        }
+    }
+}
+
+hipError_t launch_cross(int prec, const Geom &g, const void *P, void *H, const void *coef,
+                        const void *kp, hipStream_t s)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz * g.nb;
+    const unsigned blocks = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (prec == PREC_F32)
+        hipLaunchKernelGGL((k_cross<float>), dim3(blocks), dim3(256), 0, s, (const float *)P,
+                           (float *)H, g, (const float *)coef, (const KParams<float> *)kp);
+    else
+        hipLaunchKernelGGL((k_cross<double>), dim3(blocks), dim3(256), 0, s, (const double *)P,
+                           (double *)H, g, (const double *)coef, (const KParams<double> *)kp);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ small kernels

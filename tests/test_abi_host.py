@@ -91,8 +91,9 @@ def test_setter_validation_leaves_context_usable():
                 call()
             assert e.value.status == T.TDGL_E_ARG
         with pytest.raises(T.TdglError) as e:
-            T.tdgl_set_gradient(ctx, 5.1e-10, -2e-11, 2e-11, 2e-11)   # BaTiO3 mixed term
-        assert e.value.status == T.TDGL_E_UNSUPPORTED
+            T.tdgl_set_gradient(ctx, 5.1e-10, float("nan"), 2e-11, 2e-11)
+        assert e.value.status == T.TDGL_E_ARG
+        T.tdgl_set_gradient(ctx, 5.1e-10, -2e-11, 2e-11, 2e-11)       # full eq 4 accepted
         with pytest.raises(T.TdglError) as e:
             T.tdgl_step(ctx, 1)                                        # no P yet
         assert e.value.status == T.TDGL_E_STATE
