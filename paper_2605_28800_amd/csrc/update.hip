@@ -527,9 +527,9 @@ static int rows_for(const Geom &g)
     const int maxthr = UpdMaxThreads<T>::v;
     const int ny_even = g.ny + (g.ny & 1);
     int best = 2;
-    // FP32: at most 8 rows (measured best on the 128x128x32 film: 64-byte
-    // spectra segments, 512 threads); FP64: up to 16
-    const int ymax = sizeof(T) == 4 ? 8 : 16;
+    // at most 8 rows for FP32 and 4 for FP64 (measured best on the
+    // 128x128x32 film; tdgl_autotune picks per grid)
+    const int ymax = sizeof(T) == 4 ? 8 : 4;
     for (int yt = 2; yt <= ymax && yt <= (ny_even > 2 ? ny_even : 2); yt *= 2) {
         if (update_threads(g, yt, M >= 16 ? M / 16 : 1) > maxthr) break;
         if (update_lds<T, M>(g, yt) > 65536) break;
