@@ -165,3 +165,56 @@ def initial_P(cfg: dict, seed: int = 0, dtype=np.float64) -> np.ndarray:
     P[:, lay < 0] = 0.0
     P = np.ascontiguousarray(P.astype(dtype))
     return P
+
+
+# --------------------------------------------------------------------------
+# The learned initial-state proposal: seeded weights and sample conditions.
+# Layer shapes of the encoder-decoder (width w): twelve 3x3x3 convolutions,
+# (cin, cout) as listed; the parameter vector holds, per layer, W as
+# [cout][27][cin] then b [cout].
+# --------------------------------------------------------------------------
+def net_layer_shapes(width: int) -> list:
+    w = width
+    return [(5, w), (w, w), (w, 2 * w), (2 * w, 2 * w), (2 * w, 4 * w), (4 * w, 4 * w),
+            (4 * w, 4 * w), (4 * w, 2 * w), (2 * w, 2 * w), (2 * w, w), (w, w), (w, 3)]
+
+
+def net_params(width: int, seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    """Seeded weights: W ~ U(-a, a) with a = scale * sqrt(6 / (1.01 * 27 cin))
+    (He-uniform for a leaky ReLU of slope 0.1), biases ~ U(-0.05, 0.05) * scale;
+    float32 values."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for ci, co in net_layer_shapes(width):
+        a = scale * np.sqrt(6.0 / (1.01 * 27 * ci))
+        parts.append(rng.uniform(-a, a, size=co * 27 * ci))
+        parts.append(rng.uniform(-0.05 * scale, 0.05 * scale, size=co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def net_conditions(nsamples: int, shape, noise_div: int, seed: int,
+                   T_range=(250.0, 450.0), thickness_range=None, amp: float = 0.1):
+    """Sample conditions of the proposal: T ~ U(T_range) K, film thickness
+    (layers) uniform in thickness_range (inclusive; default the full height),
+    and low-resolution noise ~ U(-amp, amp) C/m^2 of shape
+    [n][3][Z/s][Y/s][X/s].  Returns (T, thickness, noise) as float32 arrays."""
+    Z, Y, X = shape
+    s = noise_div
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = rng.uniform(T_range[0], T_range[1], size=nsamples)
+    lo, hi = thickness_range if thickness_range else (Z, Z)
+    th = rng.integers(lo, hi + 1, size=nsamples)
+    noise = rng.uniform(-amp, amp, size=(nsamples, 3, Z // s, Y // s, X // s))
+    return T.astype(np.float32), th.astype(np.float32), noise.astype(np.float32)
+
+
+def noise_start(noise: np.ndarray, thickness, shape) -> np.ndarray:
+    """The random start that goes with a noise field: the noise repeated to
+    the cell grid, zero in the vacuum layers z >= thickness (C order
+    [n][3][Z][Y][X], float32)."""
+    Z, Y, X = shape
+    s = Z // noise.shape[2]
+    P = np.repeat(np.repeat(np.repeat(noise, s, 2), s, 3), s, 4).astype(np.float32)
+    for i, t in enumerate(thickness):
+        P[i, :, int(t):] = 0.0
+    return np.ascontiguousarray(P)
