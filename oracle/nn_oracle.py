@@ -12,11 +12,11 @@ Definition (all arrays [batch][channel][z][y][x]):
 * Input, 5 channels, every one multiplied by the film mask m (1 in the layers
   z < thickness, 0 in the vacuum above): (T - 350 K)/100 K, m, and the three
   components of a low-resolution noise field (C/m^2, upsampled by repetition
-  to the cell grid) divided by 0.1 C/m^2.
+  to the cell grid) times 10 m^2/C.
 * conv3: 3x3x3 cross-correlation with zero padding and a bias,
   out[o, p] = b[o] + sum_t sum_c W[o, t, c] x[c, p + d_t], where tap
   t = 9 (dz + 1) + 3 (dy + 1) + (dx + 1) and d_t = (dz, dy, dx).
-* act: leaky ReLU with slope 0.1 for negative arguments.
+* act: leaky ReLU with slope 1/8 for negative arguments.
 * pool: mean over 2x2x2 blocks; up: nearest-neighbour repetition by 2.
 * Layers (width w): e0a = act(conv(x; 5->w)), e0 = act(conv(e0a; w->w)),
   e1a = act(conv(pool e0; w->2w)), e1 = act(conv(e1a; 2w->2w)),
@@ -43,9 +43,9 @@ from __future__ import annotations
 
 import numpy as np
 
-SLOPE = 0.1          # leaky ReLU slope for negative arguments
+SLOPE = 0.125        # leaky ReLU slope for negative arguments
 T_CENTER, T_SCALE = 350.0, 100.0
-NOISE_SCALE = 0.1    # C/m^2
+NOISE_GAIN = 10.0    # m^2/C
 
 
 # --------------------------------------------------------------- rounding
@@ -174,7 +174,7 @@ def net_input(T, thickness, noise, shape):
     n = np.repeat(np.repeat(np.repeat(noise, s, 2), s, 3), s, 4)
     m = film_mask(thickness, shape)
     Tn = (np.asarray(T, float)[:, None, None, None, None] - T_CENTER) / T_SCALE
-    return np.concatenate([m * Tn, m, m * n / NOISE_SCALE], axis=1), m
+    return np.concatenate([m * Tn, m, m * n * NOISE_GAIN], axis=1), m
 
 
 def forward(theta, width, T, thickness, noise, shape, bf16=False):

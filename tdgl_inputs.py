@@ -180,13 +180,13 @@ def net_layer_shapes(width: int) -> list:
 
 
 def net_params(width: int, seed: int = 0, scale: float = 1.0) -> np.ndarray:
-    """Seeded weights: W ~ U(-a, a) with a = scale * sqrt(6 / (1.01 * 27 cin))
-    (He-uniform for a leaky ReLU of slope 0.1), biases ~ U(-0.05, 0.05) * scale;
+    """Seeded weights: W ~ U(-a, a) with a = scale * sqrt(6 / (1.015625 * 27 cin))
+    (He-uniform for a leaky ReLU of slope 1/8), biases ~ U(-0.05, 0.05) * scale;
     float32 values."""
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
     for ci, co in net_layer_shapes(width):
-        a = scale * np.sqrt(6.0 / (1.01 * 27 * ci))
+        a = scale * np.sqrt(6.0 / (1.015625 * 27 * ci))
         parts.append(rng.uniform(-a, a, size=co * 27 * ci))
         parts.append(rng.uniform(-0.05 * scale, 0.05 * scale, size=co))
     return np.concatenate(parts).astype(np.float32)

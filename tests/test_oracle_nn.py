@@ -91,8 +91,8 @@ def test_pool_and_up():
 
 def test_act():
     z = np.array([-2.0, -0.5, 0.0, 0.25, 3.0])
-    np.testing.assert_array_equal(N.act(z), [-0.2, -0.05, 0.0, 0.25, 3.0])
-    np.testing.assert_array_equal(N.act_slope(N.act(z)), [0.1, 0.1, 0.1, 1.0, 1.0])
+    np.testing.assert_array_equal(N.act(z), [-0.25, -0.0625, 0.0, 0.25, 3.0])
+    np.testing.assert_array_equal(N.act_slope(N.act(z)), [0.125, 0.125, 0.125, 1.0, 1.0])
 
 
 def test_net_input_channels():
@@ -106,7 +106,7 @@ def test_net_input_channels():
         np.testing.assert_allclose(x[b, 0, 0, 0, 0], (float(T[b]) - 350.0) / 100.0, rtol=1e-12)
         # noise cell (1, 0, 1) of the 2x2x2 noise grid covers z 4..7, y 0..3, x 4..7
         if t > 4:
-            np.testing.assert_allclose(x[b, 2 + 1, 4, 3, 7], noise[b, 1, 1, 0, 1] / 0.1, rtol=1e-7)
+            np.testing.assert_allclose(x[b, 2 + 1, 4, 3, 7], noise[b, 1, 1, 0, 1] * 10.0, rtol=1e-7)
 
 
 def test_param_layout():
@@ -133,9 +133,11 @@ def test_loss_gradient_matches_finite_differences():
     loss, P, g = N.loss_and_grad(theta, width, T, th, noise, target, shape)
     f = lambda t: N.loss_and_grad(t, width, T, th, noise, target, shape)[0]
     rng = _rng(12)
+    # small steps: a larger one can carry a pre-activation across the kink of
+    # the leaky ReLU
     for _ in range(3):                       # random directions
         v = rng.normal(size=theta.shape)
-        h = 1e-5
+        h = 1e-7
         fd = (f(theta + h * v) - f(theta - h * v)) / (2 * h)
         assert abs(fd - g @ v) < 1e-6 * max(abs(fd), 1e-12), (fd, g @ v)
     # single coordinates in every layer: a weight and the bias
@@ -144,7 +146,7 @@ def test_loss_gradient_matches_finite_differences():
         for idx in (k + rng.integers(co * 27 * ci), k + co * 27 * ci + rng.integers(co)):
             e = np.zeros_like(theta)
             e[idx] = 1.0
-            h = 1e-5
+            h = 1e-7
             fd = (f(theta + h * e) - f(theta - h * e)) / (2 * h)
             assert abs(fd - g[idx]) < 1e-6 * max(abs(g).max(), 1e-12), (idx, fd, g[idx])
         k += co * 27 * ci + co
