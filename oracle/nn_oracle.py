@@ -24,8 +24,8 @@ Definition (all arrays [batch][channel][z][y][x]):
   u1 = act(conv(up b3; 4w->2w)) + e1, u1b = act(conv(u1; 2w->2w)),
   u0 = act(conv(up u1b; 2w->w)) + e0, u0b = act(conv(u0; w->w)),
   P = m * conv(u0b; w->3)  (C/m^2, no activation).
-* Loss: sum over samples, components and cells of (P - P_target)^2 divided
-  by 3 x the number of film cells in the batch.
+* Loss: sum over samples, components and film cells of (P - P_target)^2
+  divided by 3 x the number of film cells in the batch.
 * Adam (Kingma and Ba 2015) with bias correction on FP32 master weights.
 
 Parameters are one flat vector: per layer, W as [cout][27][cin] in C order,
@@ -209,7 +209,7 @@ def loss_and_grad(theta, width, T, thickness, noise, target, shape, bf16=False):
     m, L = c["m"], c["L"]
     count = 3.0 * m.sum()
     diff = P - np.asarray(target, dtype=np.float64)
-    loss = float((diff * diff).sum() / count)
+    loss = float((m * diff * diff).sum() / count)
     grads = [None] * 12
     gy = r(m * 2.0 * diff / count)                       # dL/d(conv12 output)
     grads[11] = conv3_weight_grad(gy, c["u0b"])

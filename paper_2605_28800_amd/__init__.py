@@ -94,6 +94,29 @@ _SIGS = {
     "tdgl_get_fft_path": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_set_update_rows": ([_ctx_p, c_int], c_int),
     "tdgl_sync": ([_ctx_p], c_int),
+    # initial-state proposal network (include/tdgl_net.h)
+    "tdgl_net_create": ([ctypes.c_void_p, c_void_p, ctypes.POINTER(c_void_p)], c_int),
+    "tdgl_net_destroy": ([c_void_p], None),
+    "tdgl_net_last_error": ([c_void_p], ctypes.c_char_p),
+    "tdgl_net_num_params": ([c_void_p, ctypes.POINTER(ctypes.c_longlong)], c_int),
+    "tdgl_net_set_params": ([c_void_p, c_void_p, ctypes.c_longlong], c_int),
+    "tdgl_net_get_params": ([c_void_p, c_void_p, ctypes.c_longlong], c_int),
+    "tdgl_net_forward": ([c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+                         c_int),
+    "tdgl_net_loss_grad": ([c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                            ctypes.POINTER(c_double), c_void_p], c_int),
+    "tdgl_net_adam": ([c_void_p, c_double, c_double, c_double, c_double], c_int),
+    "tdgl_net_train": ([c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                        c_double, c_double, c_double, c_double, c_void_p], c_int),
+    "tdgl_net_profile": ([c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                          ctypes.POINTER(c_double)], c_int),
+    "tdgl_nn_conv3": ([c_int, c_void_p, c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                       c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+                      c_int),
+    "tdgl_nn_wgrad_workspace": ([c_int, c_int, c_int, c_int, c_int, c_int,
+                                 ctypes.POINTER(c_size_t)], c_int),
+    "tdgl_nn_conv3_wgrad": ([c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                             c_void_p, c_size_t, c_void_p, c_void_p], c_int),
 }
 EXPORTED = tuple(_SIGS)
 

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtdgl.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["fft_passes.hip", "update.hip", "tensor.hip", "tdgl_api.cpp"]
+SOURCES = ["fft_passes.hip", "update.hip", "tensor.hip", "net.hip", "tdgl_api.cpp",
+           "net_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for every HIP translation unit

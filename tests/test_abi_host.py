@@ -24,8 +24,9 @@ def _built():
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "tdgl.h")).read()
-    return sorted(set(re.findall(r"\b(tdgl_[A-Za-z_]+)\s*\(", src)))
+    src = "".join(open(os.path.join(ROOT, "include", h)).read()
+                  for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h"))
+    return sorted(set(re.findall(r"\b(tdgl_[A-Za-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol():
