@@ -176,15 +176,6 @@ def traffic_from(fetch_kernels, write_kernels, fetch_copy, write_copy, copy_byte
     return res
 
 
-def relax_floor(cfg):
-    """Energy floor of the relaxation test near F = 0 (paraelectric runs):
-    alpha_ref P0^2 * 1e-3 times the sample volume, in J."""
-    s = cfg["scales"]
-    n = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
-    dv = cfg["d"][0] * cfg["d"][1] * cfg["d"][2]
-    return s["alpha_ref"] * s["P0"] ** 2 * 1e-3 * n * dv
-
-
 def run_c3(max_steps, check, tune_steps, seq_every):
     """Batched relaxation of the 64-instance workload against plain runs.
 
@@ -201,6 +192,7 @@ def run_c3(max_steps, check, tune_steps, seq_every):
 
     import paper_2605_28800_amd as T
     import tdgl_inputs as I
+    from paper_2605_28800_amd.relaxation import relax_floor
     groups = I.c3_groups()
     starts, ctxs, info = [], [], []
     for c in groups:
@@ -280,6 +272,107 @@ def run_c3(max_steps, check, tune_steps, seq_every):
     }
 
 
+def net_flops(width, shape):
+    """Algorithmic FLOPs of one sample's forward pass (2 per multiply-add of
+    the convolutions; unpadded channel counts)."""
+    import tdgl_inputs as I
+    nz, ny, nx = shape
+    cells = [nx * ny * nz, nx * ny * nz // 8, nx * ny * nz // 64]
+    level = [0, 0, 1, 1, 2, 2, 2, 1, 1, 0, 0, 0]
+    return sum(2.0 * 27 * ci * co * cells[lv]
+               for (ci, co), lv in zip(I.net_layer_shapes(width), level))
+
+
+def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, check=100,
+           seed=7):
+    """Learned initial-state proposal on 64x64x16 BaTiO3 films (thickness
+    8..16 layers, T ~ U(250, 450) K): relax n_train seeded random starts
+    (batched, one context per thickness) to make the training set, train the
+    network on the GPU, then relax n_test held-out samples from their random
+    starts and from the network's proposals, to the same criterion."""
+    import numpy as np
+    import torch
+
+    import tdgl_inputs as I
+    from paper_2605_28800_amd import relaxation as R
+    from paper_2605_28800_amd.proposal import Net
+    shape, noise_div = (16, 64, 64), 8
+    n = n_train + n_test
+    T, th, noise = I.net_conditions(n, shape, noise_div, seed=seed, T_range=(250.0, 450.0),
+                                    thickness_range=(8, 16))
+    starts = torch.from_numpy(I.noise_start(noise, th, shape)).cuda()
+    recipe = lambda k: I.c5_recipe(int(k), shape)
+    dT, dth, dn = (torch.from_numpy(a).cuda() for a in (T, th, noise))
+    tr = np.arange(n_train)
+    te = np.arange(n_train, n)
+    log("c5: relaxing %d training starts (cap %d steps)" % (n_train, data_steps))
+    P_tr, s_tr, F_tr, t_data = R.relax_grouped(recipe, th[tr], T[tr], starts[:n_train],
+                                               check, data_steps)
+    target = torch.zeros((n, 3) + shape, dtype=torch.float32, device="cuda")
+    target[:n_train] = P_tr
+    log("c5: data %.1f s, %d/%d relaxed" % (t_data, (s_tr > 0).sum(), n_train))
+    net = Net(shape, width=width, noise_div=noise_div, max_batch=batch)
+    try:
+        net.set_params(I.net_params(width, seed=seed))
+        losses, t_train = R.train(net, tr, dT, dth, dn, target, train_steps, batch, 1e-3,
+                                  seed=seed)
+        log("c5: trained %d steps x %d in %.1f s, loss %.3e -> %.3e"
+            % (train_steps, batch, t_train, losses[:20].mean(), losses[-20:].mean()))
+        prof = net.profile(batch, dT, dth, dn, target, reps=5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prop = R.propose(net, te, dT, dth, dn, batch)
+        torch.cuda.synchronize()
+        t_net = time.perf_counter() - t0
+    finally:
+        net.close()
+    log("c5: relaxing %d held-out samples from random starts and from proposals" % n_test)
+    P_pl, s_pl, F_pl, t_pl = R.relax_grouped(recipe, th[te], T[te], starts[n_train:], check,
+                                             eval_steps)
+    P_pr, s_pr, F_pr, t_pr = R.relax_grouped(recipe, th[te], T[te], prop, check, eval_steps)
+    floor = np.array([R.relax_floor(recipe(k)) for k in th[te]])
+    dF = (F_pr - F_pl) / np.maximum(np.abs(F_pl), floor)
+    capped = lambda s: np.where(s > 0, s, eval_steps)
+    fl = net_flops(width, shape) * batch
+    res = {
+        "workload": "64x64x16 open BaTiO3 boxes, film of 8..16 layers under vacuum, "
+                    "T ~ U(250, 450) K, start: U(-0.1, 0.1) C/m^2 noise on 8^3 blocks; "
+                    "FP32 Heun dtau=1e-3; network width %d (%d parameters), BF16" % (
+                        width, sum(co * 27 * ci + co for ci, co in I.net_layer_shapes(width))),
+        "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V)" % check,
+        "train_samples": n_train, "train_relaxed": int((s_tr > 0).sum()),
+        "data_steps_cap": data_steps, "data_seconds": round(t_data, 2),
+        "train_steps": train_steps, "batch": batch, "train_seconds": round(t_train, 2),
+        "loss_first20": float(losses[:20].mean()), "loss_last20": float(losses[-20:].mean()),
+        "test_samples": n_test, "eval_steps_cap": eval_steps,
+        "plain": {"relaxed": int((s_pl > 0).sum()),
+                  "mean_steps": float(capped(s_pl).mean()),
+                  "median_steps": float(np.median(capped(s_pl))),
+                  "seconds": round(t_pl, 3)},
+        "proposal": {"relaxed": int((s_pr > 0).sum()),
+                     "mean_steps": float(capped(s_pr).mean()),
+                     "median_steps": float(np.median(capped(s_pr))),
+                     "seconds": round(t_pr + t_net, 3), "network_seconds": round(t_net, 4)},
+        "steps_ratio": float(capped(s_pl).mean() / capped(s_pr).mean()),
+        "time_ratio": float(t_pl / (t_pr + t_net)),
+        "final_energy_rel_diff": {"median": float(np.median(dF)), "max_abs": float(np.abs(dF).max()),
+                                  "lower_or_equal": int((dF <= 1e-6).sum())},
+        "P_rel_diff_median": float(np.median([
+            (torch.linalg.norm(P_pr[i] - P_pl[i]) / max(torch.linalg.norm(P_pl[i]), 1e-30)).item()
+            for i in range(n_test)])),
+        "train_step_ms": {"forward": prof[0], "backward": prof[1], "adam": prof[2]},
+        "conv_kernels_ms": {"forward": prof[3], "backward_data": prof[4], "weight_grad": prof[5]},
+        "conv_tflops": {"forward": fl / (prof[3] * 1e-3) / 1e12,
+                        "backward_data": fl / (prof[4] * 1e-3) / 1e12,
+                        "weight_grad": fl / (prof[5] * 1e-3) / 1e12,
+                        "peak_bf16_dense": 2500.0},
+    }
+    log("c5: steps plain %.0f vs proposal %.0f (x%.2f), time x%.2f"
+        % (res["plain"]["mean_steps"], res["proposal"]["mean_steps"], res["steps_ratio"],
+           res["time_ratio"]))
+    return res
+
+
 def cpu_baseline(cfg, nsteps):
     """The oracle as it stands, timed on the host on a few Heun steps of the
     same grid.  Its interaction table is built with mimg = 0 (the cost of a
@@ -325,6 +418,15 @@ def main():
     ap.add_argument("--c3-seq-every", type=int, default=8,
                     help="plain runs: time every k-th instance alone and scale by k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c5-train", type=int, default=0,
+                    help="learned-proposal leg: training samples (0 = leg off)")
+    ap.add_argument("--c5-test", type=int, default=64)
+    ap.add_argument("--c5-data-steps", type=int, default=8000)
+    ap.add_argument("--c5-eval-steps", type=int, default=20000)
+    ap.add_argument("--c5-train-steps", type=int, default=1000)
+    ap.add_argument("--c5-batch", type=int, default=8)
+    ap.add_argument("--c5-width", type=int, default=32)
+    ap.add_argument("--c5-only", action="store_true", help="run only the learned-proposal leg")
     ap.add_argument("--fft-path", type=int, default=0, help="0 auto (fused if it fits), 1 three passes")
     ap.add_argument("--rows", type=int, default=0, help="update-kernel rows per group (0 auto)")
     ap.add_argument("--graph-chunk", type=int, default=None,
@@ -359,6 +461,12 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     import tdgl_inputs as I
+
+    if args.c5_only:
+        print(json.dumps({"c5_learned_proposal": run_c5(
+            args.c5_train, args.c5_test, args.c5_data_steps, args.c5_eval_steps,
+            args.c5_train_steps, args.c5_batch, args.c5_width)}), flush=True)
+        return
 
     cfg = I.config("c2")
     ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
@@ -464,6 +572,11 @@ def main():
             % (c3["relaxed"], c3["instances"], c3["batched_steps"], c3["batched_s"],
                c3["plain_s"], c3["speedup"] or 0))
 
+    c5 = None
+    if args.c5_train > 0:
+        c5 = run_c5(args.c5_train, args.c5_test, args.c5_data_steps, args.c5_eval_steps,
+                    args.c5_train_steps, args.c5_batch, args.c5_width)
+
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         log("cpu baseline: oracle, %d Heun steps" % args.cpu_steps)
@@ -497,6 +610,7 @@ def main():
         "c4_large_grid": c4,
         "c3_batched_relaxation": c3,
         "c4_field_sweep": loop,
+        "c5_learned_proposal": c5,
         "kernels": kernels,
         "step_roofline": {"bytes_per_cell_step": round(step_bytes, 1),
                           "frac": round(value * step_bytes / (HBM_PEAK_GBS * 1e9), 4),

@@ -218,3 +218,16 @@ def noise_start(noise: np.ndarray, thickness, shape) -> np.ndarray:
     for i, t in enumerate(thickness):
         P[i, :, int(t):] = 0.0
     return np.ascontiguousarray(P)
+
+
+def c5_recipe(thickness: int, shape=(16, 64, 64)) -> dict:
+    """The learned-proposal workload: an open BaTiO3 box of nz x ny x nx
+    1 nm cells (the c1 model) whose lowest `thickness` layers are the film
+    and the rest vacuum; FP32 Heun dtau = 1e-3.  Conditions (T per sample,
+    low-resolution noise) come from net_conditions; the random start that
+    goes with them from noise_start."""
+    nz, ny, nx = shape
+    c = _bto_film(nx, ny, nz, (0, 0, 0), precision="f32", scheme="heun", dtau=1e-3,
+                  steps=20000, init=dict(kind="uniform", amp=0.1))
+    c["layers"] = [0] * int(thickness) + [-1] * (nz - int(thickness))
+    return c
