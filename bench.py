@@ -295,71 +295,47 @@ def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, c
 
     import tdgl_inputs as I
     from paper_2605_28800_amd import relaxation as R
-    from paper_2605_28800_amd.proposal import Net
     shape, noise_div = (16, 64, 64), 8
-    n = n_train + n_test
-    T, th, noise = I.net_conditions(n, shape, noise_div, seed=seed, T_range=(250.0, 450.0),
-                                    thickness_range=(8, 16))
+    T, th, noise = I.net_conditions(n_train + n_test, shape, noise_div, seed=seed,
+                                    T_range=(250.0, 450.0), thickness_range=(8, 16))
     starts = torch.from_numpy(I.noise_start(noise, th, shape)).cuda()
-    recipe = lambda k: I.c5_recipe(int(k), shape)
-    dT, dth, dn = (torch.from_numpy(a).cuda() for a in (T, th, noise))
-    tr = np.arange(n_train)
-    te = np.arange(n_train, n)
-    log("c5: relaxing %d training starts (cap %d steps)" % (n_train, data_steps))
-    P_tr, s_tr, F_tr, t_data = R.relax_grouped(recipe, th[tr], T[tr], starts[:n_train],
-                                               check, data_steps)
-    target = torch.zeros((n, 3) + shape, dtype=torch.float32, device="cuda")
-    target[:n_train] = P_tr
-    log("c5: data %.1f s, %d/%d relaxed" % (t_data, (s_tr > 0).sum(), n_train))
-    net = Net(shape, width=width, noise_div=noise_div, max_batch=batch)
-    try:
-        net.set_params(I.net_params(width, seed=seed))
-        losses, t_train = R.train(net, tr, dT, dth, dn, target, train_steps, batch, 1e-3,
-                                  seed=seed)
-        log("c5: trained %d steps x %d in %.1f s, loss %.3e -> %.3e"
-            % (train_steps, batch, t_train, losses[:20].mean(), losses[-20:].mean()))
-        prof = net.profile(batch, dT, dth, dn, target, reps=5)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        prop = R.propose(net, te, dT, dth, dn, batch)
-        torch.cuda.synchronize()
-        t_net = time.perf_counter() - t0
-    finally:
-        net.close()
-    log("c5: relaxing %d held-out samples from random starts and from proposals" % n_test)
-    P_pl, s_pl, F_pl, t_pl = R.relax_grouped(recipe, th[te], T[te], starts[n_train:], check,
-                                             eval_steps)
-    P_pr, s_pr, F_pr, t_pr = R.relax_grouped(recipe, th[te], T[te], prop, check, eval_steps)
-    floor = np.array([R.relax_floor(recipe(k)) for k in th[te]])
-    dF = (F_pr - F_pl) / np.maximum(np.abs(F_pl), floor)
+    log("c5: %d training starts (cap %d steps), %d training steps, %d held-out samples"
+        % (n_train, data_steps, train_steps, n_test))
+    r = R.proposal_experiment(lambda k: I.c5_recipe(int(k), shape), shape, noise_div, T, th,
+                              noise, starts, n_train, I.net_params(width, seed=seed), width,
+                              data_steps, eval_steps, train_steps, batch, check, seed=seed,
+                              profile=True, log=lambda m: log("c5: " + m))
     capped = lambda s: np.where(s > 0, s, eval_steps)
+    s_pl, s_pr = r["plain_steps"], r["proposal_steps"]
+    dF = (r["proposal_F"] - r["plain_F"]) / np.maximum(np.abs(r["plain_F"]), r["energy_floor"])
+    prof = r["profile_ms"]
     fl = net_flops(width, shape) * batch
+    losses = r["losses"]
+    t_pr = r["proposal_seconds"] + r["network_seconds"]
     res = {
         "workload": "64x64x16 open BaTiO3 boxes, film of 8..16 layers under vacuum, "
                     "T ~ U(250, 450) K, start: U(-0.1, 0.1) C/m^2 noise on 8^3 blocks; "
                     "FP32 Heun dtau=1e-3; network width %d (%d parameters), BF16" % (
                         width, sum(co * 27 * ci + co for ci, co in I.net_layer_shapes(width))),
         "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V)" % check,
-        "train_samples": n_train, "train_relaxed": int((s_tr > 0).sum()),
-        "data_steps_cap": data_steps, "data_seconds": round(t_data, 2),
-        "train_steps": train_steps, "batch": batch, "train_seconds": round(t_train, 2),
+        "train_samples": n_train, "train_relaxed": int((r["train_steps_relaxed"] > 0).sum()),
+        "trained_on": "relaxed training states only",
+        "data_steps_cap": data_steps, "data_seconds": round(r["data_seconds"], 2),
+        "train_steps": train_steps, "batch": batch, "train_seconds": round(r["train_seconds"], 2),
         "loss_first20": float(losses[:20].mean()), "loss_last20": float(losses[-20:].mean()),
         "test_samples": n_test, "eval_steps_cap": eval_steps,
-        "plain": {"relaxed": int((s_pl > 0).sum()),
-                  "mean_steps": float(capped(s_pl).mean()),
+        "plain": {"relaxed": int((s_pl > 0).sum()), "mean_steps": float(capped(s_pl).mean()),
                   "median_steps": float(np.median(capped(s_pl))),
-                  "seconds": round(t_pl, 3)},
-        "proposal": {"relaxed": int((s_pr > 0).sum()),
-                     "mean_steps": float(capped(s_pr).mean()),
-                     "median_steps": float(np.median(capped(s_pr))),
-                     "seconds": round(t_pr + t_net, 3), "network_seconds": round(t_net, 4)},
+                  "seconds": round(r["plain_seconds"], 3)},
+        "proposal": {"relaxed": int((s_pr > 0).sum()), "mean_steps": float(capped(s_pr).mean()),
+                     "median_steps": float(np.median(capped(s_pr))), "seconds": round(t_pr, 3),
+                     "network_seconds": round(r["network_seconds"], 4)},
         "steps_ratio": float(capped(s_pl).mean() / capped(s_pr).mean()),
-        "time_ratio": float(t_pl / (t_pr + t_net)),
-        "final_energy_rel_diff": {"median": float(np.median(dF)), "max_abs": float(np.abs(dF).max()),
+        "time_ratio": float(r["plain_seconds"] / t_pr),
+        "final_energy_rel_diff": {"median": float(np.median(dF)),
+                                  "max_abs": float(np.abs(dF).max()),
                                   "lower_or_equal": int((dF <= 1e-6).sum())},
-        "P_rel_diff_median": float(np.median([
-            (torch.linalg.norm(P_pr[i] - P_pl[i]) / max(torch.linalg.norm(P_pl[i]), 1e-30)).item()
-            for i in range(n_test)])),
+        "P_rel_diff_median": float(np.median(r["P_rel_diff"])),
         "train_step_ms": {"forward": prof[0], "backward": prof[1], "adam": prof[2]},
         "conv_kernels_ms": {"forward": prof[3], "backward_data": prof[4], "weight_grad": prof[5]},
         "conv_tflops": {"forward": fl / (prof[3] * 1e-3) / 1e12,
@@ -421,9 +397,9 @@ def main():
     ap.add_argument("--c5-train", type=int, default=0,
                     help="learned-proposal leg: training samples (0 = leg off)")
     ap.add_argument("--c5-test", type=int, default=64)
-    ap.add_argument("--c5-data-steps", type=int, default=8000)
+    ap.add_argument("--c5-data-steps", type=int, default=12000)
     ap.add_argument("--c5-eval-steps", type=int, default=20000)
-    ap.add_argument("--c5-train-steps", type=int, default=1000)
+    ap.add_argument("--c5-train-steps", type=int, default=10000)
     ap.add_argument("--c5-batch", type=int, default=8)
     ap.add_argument("--c5-width", type=int, default=32)
     ap.add_argument("--c5-only", action="store_true", help="run only the learned-proposal leg")

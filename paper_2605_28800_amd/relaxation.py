@@ -41,14 +41,15 @@ def relax(ctx, floor, check=100, max_steps=20000):
 
 
 def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=256,
-                  tune_steps=0):
+                  tune_steps=0, log=None):
     """Relax samples that share a recipe per key (e.g. film thickness) in
     batches of at most group_max.
 
     recipe(key) -> run recipe; keys, T: per sample; start: torch float32
     device tensor [n][3][nz][ny][nx] (C/m^2).  Returns the relaxed P (device
     tensor like start), relax steps, final energies F (J) and the seconds
-    spent stepping (set-up excluded)."""
+    spent stepping (set-up excluded).  log(message), if given, hears of each
+    finished group."""
     import torch
     keys = np.asarray(keys)
     n = len(keys)
@@ -78,6 +79,9 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
                 steps[rows] = done
                 F[rows] = ctx.energies_batch()[0][:, 4]
                 out.index_copy_(0, ridx, ctx.get_P_device(TDGL_FP32))
+                if log:
+                    log("relaxed group %s: %d instances, %d relaxed, %.1f s"
+                        % (k, len(rows), (done > 0).sum(), seconds))
             finally:
                 ctx.close()
     return out, steps, F, seconds
@@ -119,3 +123,56 @@ def propose(net, rows, T, thick, noise, batch):
         idx = torch.tensor(np.asarray(rows[a:a + batch], dtype=np.int32), device=T.device)
         out.append(net.forward(T, thick, noise, idx=idx))
     return torch.cat(out, 0)
+
+
+def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_train, theta0,
+                        width, data_steps, eval_steps, train_steps, batch, check=100, lr=1e-3,
+                        seed=0, profile=False, log=None, relaxed_only=True):
+    """The learned proposal end to end.
+
+    Rows 0..n_train-1 of the conditions (T, thick, noise: host arrays;
+    starts: device tensor of the matching random starts) are relaxed from
+    their starts (cap data_steps) into the training set; a network of the
+    given width, initialised with theta0, is trained on it (on the samples
+    that met the criterion only, if relaxed_only and any did); the remaining
+    rows are relaxed from their random starts and from the network's
+    proposals (cap eval_steps).  recipe(thickness) gives the run recipe.
+    Returns a dict of the measurements (relax steps -1 = not relaxed)."""
+    import torch
+
+    from .proposal import Net
+    n = len(T)
+    dT, dth, dn = (torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(starts.device)
+                   for a in (T, thick, noise))
+    tr, te = np.arange(n_train), np.arange(n_train, n)
+    P_tr, s_tr, F_tr, t_data = relax_grouped(recipe, thick[tr], T[tr], starts[:n_train], check,
+                                             data_steps, log=log)
+    target = torch.zeros((n, 3) + tuple(shape), dtype=torch.float32, device=starts.device)
+    target[:n_train] = P_tr
+    net = Net(shape, width=width, noise_div=noise_div, max_batch=batch)
+    try:
+        net.set_params(theta0)
+        rows = tr[s_tr > 0] if relaxed_only and (s_tr > 0).any() else tr
+        losses, t_train = train(net, rows, dT, dth, dn, target, train_steps, batch, lr, seed=seed)
+        if log:
+            log("trained %d steps in %.1f s" % (train_steps, t_train))
+        prof = net.profile(batch, dT, dth, dn, target, reps=5) if profile else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prop = propose(net, te, dT, dth, dn, batch)
+        torch.cuda.synchronize()
+        t_net = time.perf_counter() - t0
+    finally:
+        net.close()
+    P_pl, s_pl, F_pl, t_pl = relax_grouped(recipe, thick[te], T[te], starts[n_train:], check,
+                                           eval_steps, log=log)
+    P_pr, s_pr, F_pr, t_pr = relax_grouped(recipe, thick[te], T[te], prop, check, eval_steps,
+                                           log=log)
+    floor = np.array([relax_floor(recipe(k)) for k in thick[te]])
+    dP = [(torch.linalg.norm(P_pr[i] - P_pl[i]) / max(torch.linalg.norm(P_pl[i]).item(), 1e-30)).item()
+          for i in range(len(te))]
+    return dict(train_steps_relaxed=s_tr, data_seconds=t_data, losses=losses,
+                train_seconds=t_train, profile_ms=prof, network_seconds=t_net,
+                plain_steps=s_pl, proposal_steps=s_pr, plain_F=F_pl, proposal_F=F_pr,
+                plain_seconds=t_pl, proposal_seconds=t_pr, energy_floor=floor,
+                P_rel_diff=np.asarray(dP))

@@ -1,0 +1,43 @@
+"""What the trained proposal network gains over plain random starts.
+
+The learned-proposal workload at a quarter of its size (64x64x16 open
+BaTiO3 boxes, films of 8..16 layers, T ~ U(250, 450) K, starts of
+U(-0.1, 0.1) C/m^2 noise on 8^3 blocks; 256 training starts relaxed for at
+most 8000 steps, 32 held-out samples): relax the training starts into a
+dataset, train the network on the GPU through the library's own kernels on
+the states that relaxed, then relax the held-out samples from their random
+starts and from the network's proposals to the same energy criterion.  The run is seeded and the kernels are
+deterministic, so the numbers repeat on the same build."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import tdgl_inputs as I  # noqa: E402
+from tests.gpu_helpers import announce  # noqa: E402
+
+
+@pytest.mark.timeout(400)
+def test_trained_proposal_relaxes_in_fewer_steps():
+    from paper_2605_28800_amd import relaxation as R
+    shape, noise_div, width = (16, 64, 64), 8, 32
+    n_train, n_test, eval_cap = 256, 32, 20000
+    announce("proposal gain: %d training starts, %d held-out" % (n_train, n_test))
+    T, th, noise = I.net_conditions(n_train + n_test, shape, noise_div, seed=7,
+                                    T_range=(250.0, 450.0), thickness_range=(8, 16))
+    starts = torch.from_numpy(I.noise_start(noise, th, shape)).cuda()
+    r = R.proposal_experiment(lambda k: I.c5_recipe(int(k), shape), shape, noise_div, T, th,
+                              noise, starts, n_train, I.net_params(width, seed=7), width,
+                              data_steps=8000, eval_steps=eval_cap, train_steps=2000, batch=8,
+                              seed=7, log=announce)
+    capped = lambda s: np.where(s > 0, s, eval_cap)
+    plain, prop = capped(r["plain_steps"]), capped(r["proposal_steps"])
+    print("[gain] plain mean %.0f, proposal mean %.0f; relaxed %d / %d of %d; losses %.3e -> %.3e"
+          % (plain.mean(), prop.mean(), (r["plain_steps"] > 0).sum(),
+             (r["proposal_steps"] > 0).sum(), n_test, r["losses"][:20].mean(),
+             r["losses"][-20:].mean()), flush=True)
+    assert np.isfinite(r["losses"]).all() and r["losses"][-20:].mean() < r["losses"][:20].mean()
+    assert (r["proposal_steps"] > 0).sum() >= (r["plain_steps"] > 0).sum()
+    assert prop.mean() < 0.85 * plain.mean()
