@@ -61,11 +61,68 @@ __device__ inline long long gather_index(const Pos &p, int dz, int dy, int dx, i
 }
 
 // ----------------------------------------------------------------- conv
-// One work-group: 4 waves x 32 output positions, 16 * MB output channels
-// (blockIdx.y selects the channel block).  K = 27 * cin_p runs in steps of
-// 32: each lane gathers 8 consecutive input channels of one tap for each of
-// its two position columns, and 8 consecutive weights per 16-row block.
-template <int MB, int EPI>
+// One work-group: 4 waves x 16 * NB output positions, 16 * MB output
+// channels (blockIdx.y selects the channel block).  K = 27 * cin_p runs in
+// steps of 32: each lane gathers 8 consecutive input channels of one tap
+// for each of its NB position columns, and 8 consecutive weights per 16-row
+// block; the operands of step k + 1 are loaded while step k's MFMAs run.
+template <int MB, int NB>
+__device__ __forceinline__ void conv_operands(const ConvArgs &a, const bf16_t *wrow, int kp,
+                                              int lc, int k0, int kq, const Pos *p,
+                                              const bool *inb, bf16x8 *av, bf16x8 *bv) {
+  const int k = k0 + 8 * kq;
+  const bool kv = k < kp;
+  const int t = k >> lc, ci = k & (a.cin_p - 1);
+  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+  for (int mb = 0; mb < MB; ++mb) av[mb] = kv ? load8(wrow + (size_t)mb * 16 * kp + k) : zero8();
+  for (int j = 0; j < NB; ++j) {
+    long long src = -1;
+    if (kv && inb[j]) src = gather_index(p[j], dz, dy, dx, a.lx, a.ly, a.lz, a.in_up2);
+    bv[j] = src >= 0 ? load8(a.in + src * a.cin_p + ci) : zero8();
+  }
+}
+
+// epilogue of one lane: channels co0 .. co0 + 3 of output position n (p its
+// coordinates; ls = log2 of the cells per sample)
+template <int EPI>
+__device__ __forceinline__ void conv_store(const ConvArgs &a, const Pos &p, long long n, int ls,
+                                           int co0, const floatx4 v) {
+  const size_t o = (size_t)n * a.cout_p + co0;
+  if (EPI == EPI_P) {
+    if (co0 != 0) return;
+    const int row = a.idx ? a.idx[p.b] : p.b;
+    const float m = (float)p.z < a.thick[row] ? 1.f : 0.f;
+    const long long r = n & ((1LL << ls) - 1);
+    for (int c = 0; c < 3; ++c) a.P[(((long long)p.b * 3 + c) << ls) + r] = m * (v[c] + a.bias[c]);
+    return;
+  }
+  bf16_t r4[4], s4[4];
+  if (EPI == EPI_ACT || EPI == EPI_ACT_SKIP) {
+    for (int i = 0; i < 4; ++i) r4[i] = f2bf(act(v[i] + a.bias[co0 + i]));
+  } else {
+    for (int i = 0; i < 4; ++i) r4[i] = f2bf(v[i]);
+  }
+  if (EPI == EPI_ACT_SKIP || EPI == EPI_RAW_D || EPI == EPI_RAW_AND_D) {
+    const uint2 ax = *reinterpret_cast<const uint2 *>(a.aux + o);
+    const bf16_t xa[4] = {(bf16_t)(ax.x & 0xFFFF), (bf16_t)(ax.x >> 16), (bf16_t)(ax.y & 0xFFFF),
+                          (bf16_t)(ax.y >> 16)};
+    for (int i = 0; i < 4; ++i)
+      s4[i] = EPI == EPI_ACT_SKIP ? f2bf(bf2f(r4[i]) + bf2f(xa[i])) : f2bf(v[i] * act_slope(xa[i]));
+  }
+  uint2 w0, w1;
+  w0.x = r4[0] | ((uint32_t)r4[1] << 16);
+  w0.y = r4[2] | ((uint32_t)r4[3] << 16);
+  w1.x = s4[0] | ((uint32_t)s4[1] << 16);
+  w1.y = s4[2] | ((uint32_t)s4[3] << 16);
+  if (EPI == EPI_RAW_D) {
+    *reinterpret_cast<uint2 *>(a.out + o) = w1;
+    return;
+  }
+  *reinterpret_cast<uint2 *>(a.out + o) = w0;
+  if (EPI == EPI_ACT_SKIP || EPI == EPI_RAW_AND_D) *reinterpret_cast<uint2 *>(a.out2 + o) = w1;
+}
+
+template <int MB, int NB, int EPI>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, col = lane & 15;
@@ -74,98 +131,154 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int kp = 27 * a.cin_p;
   const int lc = __builtin_ctz(a.cin_p);
   const int co_blk = blockIdx.y * MB * 16;
-  const long long nbase = (long long)blockIdx.x * 128 + wave * 32;
+  const long long nbase = ((long long)blockIdx.x * 4 + wave) * (16 * NB);
 
-  Pos p[2];
-  bool inb[2];
-  for (int j = 0; j < 2; ++j) {
+  Pos p[NB];
+  bool inb[NB];
+  for (int j = 0; j < NB; ++j) {
     const long long n = nbase + 16 * j + col;
     inb[j] = n < npos;
     p[j] = decode(inb[j] ? n : 0, a.lx, a.ly, a.lz);
   }
 
-  floatx4 acc[MB][2];
+  floatx4 acc[MB][NB];
   for (int mb = 0; mb < MB; ++mb)
-    for (int j = 0; j < 2; ++j) acc[mb][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NB; ++j) acc[mb][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const bf16_t *wrow = a.w + (size_t)(co_blk + col) * kp;
+  bf16x8 av[MB], bv[NB];
+  conv_operands<MB, NB>(a, wrow, kp, lc, 0, kq, p, inb, av, bv);
   for (int k0 = 0; k0 < kp; k0 += 32) {
-    const int k = k0 + 8 * kq;
-    const bool kv = k < kp;
-    const int t = k >> lc, ci = k & (a.cin_p - 1);
-    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    bf16x8 av[MB], bv[2];
+    bf16x8 an[MB], bn[NB];
+    if (k0 + 32 < kp) conv_operands<MB, NB>(a, wrow, kp, lc, k0 + 32, kq, p, inb, an, bn);
     for (int mb = 0; mb < MB; ++mb)
-      av[mb] = kv ? load8(wrow + (size_t)mb * 16 * kp + k) : zero8();
-    for (int j = 0; j < 2; ++j) {
-      long long src = -1;
-      if (kv && inb[j]) src = gather_index(p[j], dz, dy, dx, a.lx, a.ly, a.lz, a.in_up2);
-      bv[j] = src >= 0 ? load8(a.in + src * a.cin_p + ci) : zero8();
-    }
-    for (int mb = 0; mb < MB; ++mb)
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NB; ++j)
         acc[mb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mb], bv[j], acc[mb][j], 0, 0, 0);
+    for (int mb = 0; mb < MB; ++mb) av[mb] = an[mb];
+    for (int j = 0; j < NB; ++j) bv[j] = bn[j];
   }
 
   // epilogue: this lane holds channels co0 .. co0 + 3 of position n
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NB; ++j) {
     if (!inb[j]) continue;
     const long long n = nbase + 16 * j + col;
-    for (int mb = 0; mb < MB; ++mb) {
-      const int co0 = co_blk + mb * 16 + 4 * kq;
-      const floatx4 v = acc[mb][j];
-      const size_t o = (size_t)n * a.cout_p + co0;
-      if (EPI == EPI_P) {
-        if (co0 != 0) continue;
-        const int row = a.idx ? a.idx[p[j].b] : p[j].b;
-        const float m = (float)p[j].z < a.thick[row] ? 1.f : 0.f;
-        const long long r = n & ((1LL << ls) - 1);
-        for (int c = 0; c < 3; ++c)
-          a.P[(((long long)p[j].b * 3 + c) << ls) + r] = m * (v[c] + a.bias[c]);
-        continue;
-      }
-      bf16_t r4[4], s4[4];
-      if (EPI == EPI_ACT || EPI == EPI_ACT_SKIP) {
-        for (int i = 0; i < 4; ++i) r4[i] = f2bf(act(v[i] + a.bias[co0 + i]));
-      } else {
-        for (int i = 0; i < 4; ++i) r4[i] = f2bf(v[i]);
-      }
-      if (EPI == EPI_ACT_SKIP || EPI == EPI_RAW_D || EPI == EPI_RAW_AND_D) {
-        const uint2 ax = *reinterpret_cast<const uint2 *>(a.aux + o);
-        const bf16_t xa[4] = {(bf16_t)(ax.x & 0xFFFF), (bf16_t)(ax.x >> 16),
-                              (bf16_t)(ax.y & 0xFFFF), (bf16_t)(ax.y >> 16)};
-        for (int i = 0; i < 4; ++i)
-          s4[i] = EPI == EPI_ACT_SKIP ? f2bf(bf2f(r4[i]) + bf2f(xa[i]))
-                                      : f2bf(v[i] * act_slope(xa[i]));
-      }
-      uint2 w0, w1;
-      w0.x = r4[0] | ((uint32_t)r4[1] << 16);
-      w0.y = r4[2] | ((uint32_t)r4[3] << 16);
-      if (EPI == EPI_RAW_D) {
-        w1.x = s4[0] | ((uint32_t)s4[1] << 16);
-        w1.y = s4[2] | ((uint32_t)s4[3] << 16);
-        *reinterpret_cast<uint2 *>(a.out + o) = w1;
-        continue;
-      }
-      *reinterpret_cast<uint2 *>(a.out + o) = w0;
-      if (EPI == EPI_ACT_SKIP || EPI == EPI_RAW_AND_D) {
-        w1.x = s4[0] | ((uint32_t)s4[1] << 16);
-        w1.y = s4[2] | ((uint32_t)s4[3] << 16);
-        *reinterpret_cast<uint2 *>(a.out2 + o) = w1;
-      }
-    }
+    for (int mb = 0; mb < MB; ++mb)
+      conv_store<EPI>(a, p[j], n, ls, co_blk + mb * 16 + 4 * kq, acc[mb][j]);
   }
 }
 
+// LDS-tiled variant for grids with X >= 16, Y >= NR and Z >= 4: a
+// work-group owns a 4 x NR x 16 (z, y, x) block, wave w the NR rows of
+// plane w; per chunk of CC input channels the 6 x (NR + 2) x 18 input halo
+// of the block is staged in LDS once, and all 27 taps read their operand
+// from there.  MB * NR = 16 accumulator tiles per wave (NR >= 2).
+constexpr int HX = 18;
+
+template <int MB, int NR, int CC, int EPI>
+__global__ __launch_bounds__(256) void k_conv_tile(ConvArgs a) {
+  constexpr int HY = NR + 2, HZ = 6, HPOS = HZ * HY * HX;
+  constexpr int LD = CC + 8;                       // LDS row stride (elements)
+  extern __shared__ bf16_t halo[];                 // [HPOS][LD]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, col = lane & 15;
+  const int X = 1 << a.lx, Y = 1 << a.ly, Z = 1 << a.lz;
+  const int tx_n = X >> 4, ty_n = Y / NR, tz_n = Z >> 2;
+  const int per_b = tx_n * ty_n * tz_n;
+  const int b = blockIdx.x / per_b;
+  int rem = blockIdx.x % per_b;
+  const int z0 = (rem / (tx_n * ty_n)) * 4;
+  rem %= tx_n * ty_n;
+  const int y0 = (rem / tx_n) * NR, x0 = (rem % tx_n) * 16;
+  const int kp = 27 * a.cin_p;
+  const int co_blk = blockIdx.y * MB * 16;
+
+  floatx4 acc[MB][NR];
+  for (int mb = 0; mb < MB; ++mb)
+    for (int j = 0; j < NR; ++j) acc[mb][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bf16_t *wrow = a.w + (size_t)(co_blk + col) * kp;
+
+  for (int ci0 = 0; ci0 < a.cin_p; ci0 += CC) {
+    for (int h = tid; h < HPOS * (CC / 8); h += 256) {
+      const int pos = h / (CC / 8), c8 = h % (CC / 8);
+      Pos hp;
+      hp.b = b;
+      hp.z = z0 - 1 + pos / (HY * HX);
+      hp.y = y0 - 1 + (pos / HX) % HY;
+      hp.x = x0 - 1 + pos % HX;
+      const long long src = gather_index(hp, 0, 0, 0, a.lx, a.ly, a.lz, a.in_up2);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (src >= 0) v = *reinterpret_cast<const uint4 *>(a.in + src * a.cin_p + ci0 + 8 * c8);
+      *reinterpret_cast<uint4 *>(halo + pos * LD + 8 * c8) = v;
+    }
+    __syncthreads();
+    // K within the chunk: kk = tap * CC + c, steps of 32
+    for (int kk0 = 0; kk0 < 27 * CC; kk0 += 32) {
+      const int kk = kk0 + 8 * kq;
+      const bool kv = kk < 27 * CC;
+      const int t = kv ? kk / CC : 0, c = kk % CC;
+      const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // 0..2: halo offsets
+      bf16x8 av[MB];
+      for (int mb = 0; mb < MB; ++mb)
+        av[mb] = kv ? load8(wrow + (size_t)mb * 16 * kp + t * a.cin_p + ci0 + c) : zero8();
+      const bf16_t *hb = halo + (((wave + dz) * HY + dy) * HX + col + dx) * LD + c;
+      for (int j = 0; j < NR; ++j) {
+        const bf16x8 bv = kv ? *reinterpret_cast<const bf16x8 *>(hb + j * HX * LD) : zero8();
+        for (int mb = 0; mb < MB; ++mb)
+          acc[mb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mb], bv, acc[mb][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int ls = a.lx + a.ly + a.lz;
+  for (int j = 0; j < NR; ++j) {
+    Pos pj;
+    pj.b = b;
+    pj.z = z0 + wave;
+    pj.y = y0 + j;
+    pj.x = x0 + col;
+    const long long n = ((((long long)b << a.lz) + pj.z) * Y + pj.y) * (long long)X + pj.x;
+    for (int mb = 0; mb < MB; ++mb)
+      conv_store<EPI>(a, pj, n, ls, co_blk + mb * 16 + 4 * kq, acc[mb][j]);
+  }
+}
+
+template <int MB, int EPI>
+static hipError_t conv_tile(const ConvArgs &a, dim3 grid, hipStream_t s) {
+  // rows per wave NR = 16 / MB (2..8); channel chunk of 16 per halo load:
+  // 6 x (NR + 2) x 18 positions x 24 elements x 2 B (<= 52 KB)
+  constexpr int NR = MB >= 8 ? 2 : 16 / MB > 8 ? 8 : 16 / MB;
+  const size_t shm = (size_t)6 * (NR + 2) * HX * 24 * 2;
+  hipLaunchKernelGGL((k_conv_tile<MB, NR, 16, EPI>), grid, dim3(256), shm, s, a);
+  return hipGetLastError();
+}
+
+// positions per wave: 16 * NB with MB * NB = 16 accumulator tiles (NB >= 2)
 template <int EPI>
-static hipError_t conv_mb(const ConvArgs &a, dim3 grid, hipStream_t s) {
+static hipError_t conv_mb(const ConvArgs &a, long long npos, hipStream_t s) {
   const int mb = a.cout_p / 16 >= 8 ? 8 : a.cout_p / 16;
-  grid.y = a.cout_p / (16 * mb);
+  const int nr = mb >= 8 ? 2 : 16 / mb > 8 ? 8 : 16 / mb;
+  if (a.lx >= 4 && (1 << a.ly) >= nr && a.lz >= 2) {
+    const long long blocks = npos / (64LL * nr);
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks, a.cout_p / (16 * mb), 1);
+    switch (mb) {
+      case 1: return conv_tile<1, EPI>(a, grid, s);
+      case 2: return conv_tile<2, EPI>(a, grid, s);
+      case 4: return conv_tile<4, EPI>(a, grid, s);
+      case 8: return conv_tile<8, EPI>(a, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  const int nbk = mb >= 8 ? 2 : 16 / mb > 8 ? 8 : 16 / mb;
+  const long long blocks = (npos + 64 * nbk - 1) / (64 * nbk);
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  dim3 grid((unsigned)blocks, a.cout_p / (16 * mb), 1);
   switch (mb) {
-    case 1: hipLaunchKernelGGL((k_conv<1, EPI>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_conv<2, EPI>), grid, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_conv<4, EPI>), grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_conv<8, EPI>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_conv<1, 8, EPI>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_conv<2, 8, EPI>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_conv<4, 4, EPI>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_conv<8, 2, EPI>), grid, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -186,16 +299,13 @@ hipError_t launch_conv(int epi, const ConvArgs &a, hipStream_t s) {
   if ((epi == EPI_ACT_SKIP || epi == EPI_RAW_D || epi == EPI_RAW_AND_D) && !a.aux)
     return hipErrorInvalidValue;
   const long long npos = (long long)a.nb << (a.lx + a.ly + a.lz);
-  const long long blocks = (npos + 127) / 128;
-  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  dim3 grid((unsigned)blocks, 1, 1);
   switch (epi) {
-    case EPI_ACT: return conv_mb<EPI_ACT>(a, grid, s);
-    case EPI_ACT_SKIP: return conv_mb<EPI_ACT_SKIP>(a, grid, s);
-    case EPI_P: return conv_mb<EPI_P>(a, grid, s);
-    case EPI_RAW: return conv_mb<EPI_RAW>(a, grid, s);
-    case EPI_RAW_D: return conv_mb<EPI_RAW_D>(a, grid, s);
-    case EPI_RAW_AND_D: return conv_mb<EPI_RAW_AND_D>(a, grid, s);
+    case EPI_ACT: return conv_mb<EPI_ACT>(a, npos, s);
+    case EPI_ACT_SKIP: return conv_mb<EPI_ACT_SKIP>(a, npos, s);
+    case EPI_P: return conv_mb<EPI_P>(a, npos, s);
+    case EPI_RAW: return conv_mb<EPI_RAW>(a, npos, s);
+    case EPI_RAW_D: return conv_mb<EPI_RAW_D>(a, npos, s);
+    case EPI_RAW_AND_D: return conv_mb<EPI_RAW_AND_D>(a, npos, s);
   }
   return hipErrorInvalidValue;
 }

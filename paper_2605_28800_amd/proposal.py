@@ -60,7 +60,10 @@ class Net:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def set_params(self, theta):
         a = np.ascontiguousarray(theta, dtype=np.float32)

@@ -70,6 +70,12 @@ CONV_CASES = [  # cin, cout, cin_p, cout_p, nb, (lz, ly, lx), up2
     (64, 128, 64, 128, 2, (2, 2, 3), 0),
     (128, 64, 128, 64, 1, (2, 3, 3), 1),
     (32, 256, 32, 256, 1, (2, 2, 2), 0),    # two channel blocks
+    # grids of at least 8 x 16 (y, x) take the LDS-tiled kernel
+    (5, 32, 16, 32, 2, (2, 3, 4), 0),
+    (32, 64, 32, 64, 1, (2, 4, 5), 1),
+    (64, 128, 64, 128, 2, (1, 3, 4), 0),
+    (128, 32, 128, 32, 1, (2, 3, 4), 1),
+    (16, 16, 16, 16, 3, (1, 3, 4), 0),
 ]
 
 
