@@ -313,10 +313,12 @@ hipError_t launch_conv(int epi, const ConvArgs &a, hipStream_t s) {
 // ---------------------------------------------------------- weight grad
 // dW[co][k] = sum_n G[n][co] X[n][k] over one split's positions, k = tap * cin_p + ci.
 // Work-group: 16 * MB output channels (blockIdx.z) x 64 k columns
-// (blockIdx.x, 16 per wave), positions in steps of 32.  Both tiles are
-// transposed through LDS so that each lane reads 8 consecutive positions.
-// The blockIdx.x == 0 groups also sum G over the positions (bias gradient).
-constexpr int WG_LD = 40;   // LDS row stride (elements): 32 positions + 8 pad
+// (blockIdx.x, 16 per wave), positions in slabs of 32 * WS.  Both tiles are
+// transposed through LDS so that each lane reads 8 consecutive positions for
+// the matrix core.  The blockIdx.x == 0 groups also sum G over the
+// positions (bias gradient).
+constexpr int WS = 4;                  // 32-position MFMA steps per LDS slab
+constexpr int WG_LD = 32 * WS + 8;     // LDS row stride (elements)
 
 template <int MB>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
@@ -332,22 +334,15 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   const int co_blk = blockIdx.z * MB * 16;
   const long long p0 = (long long)blockIdx.y * a.chunk;
   const long long p1 = p0 + a.chunk < npos ? p0 + a.chunk : npos;
-
-  // this thread's X chunk: position column nl, k = kx .. kx + 7
-  const int nl = tid & 31;
-  const int kx = kt0 + 8 * (tid >> 5);
-  const bool kxv = kx < kp;
-  const int t = kx >> lc, ci = kx & (a.cin_p - 1);
-  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
   const bool bias_thread = blockIdx.x == 0 && tid < MB * 16;
 
   floatx4 acc[MB];
   for (int mb = 0; mb < MB; ++mb) acc[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
 
-  for (long long pb = p0; pb < p1; pb += 32) {
-    for (int c = tid; c < MB * 64; c += 256) {
-      const int gl = c & 31, c8 = c >> 5;
+  for (long long pb = p0; pb < p1; pb += 32 * WS) {
+    for (int c = tid; c < MB * 64 * WS; c += 256) {
+      const int gl = c % (32 * WS), c8 = c / (32 * WS);
       const long long n = pb + gl;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (n < p1) v = *reinterpret_cast<const uint4 *>(a.g + n * a.cout_p + co_blk + 8 * c8);
@@ -357,29 +352,35 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         gs[8 * c8 + 2 * i + 1][gl] = (bf16_t)(w4[i] >> 16);
       }
     }
-    {
+    for (int c = tid; c < 256 * WS; c += 256) {
+      const int nl = c % (32 * WS), k8 = c / (32 * WS);
+      const int kx = kt0 + 8 * k8;
       const long long n = pb + nl;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (kxv && n < p1) {
+      if (kx < kp && n < p1) {
+        const int t = kx >> lc, ci = kx & (a.cin_p - 1);
         const Pos p = decode(n, a.lx, a.ly, a.lz);
-        const long long src = gather_index(p, dz, dy, dx, a.lx, a.ly, a.lz, a.in_up2);
+        const long long src =
+            gather_index(p, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1, a.lx, a.ly, a.lz, a.in_up2);
         if (src >= 0) v = *reinterpret_cast<const uint4 *>(a.in + src * a.cin_p + ci);
       }
       const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-      const int r0 = 8 * (tid >> 5);
       for (int i = 0; i < 4; ++i) {
-        xs[r0 + 2 * i][nl] = (bf16_t)(w4[i] & 0xFFFF);
-        xs[r0 + 2 * i + 1][nl] = (bf16_t)(w4[i] >> 16);
+        xs[8 * k8 + 2 * i][nl] = (bf16_t)(w4[i] & 0xFFFF);
+        xs[8 * k8 + 2 * i + 1][nl] = (bf16_t)(w4[i] >> 16);
       }
     }
     __syncthreads();
-    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xs[wave * 16 + col][8 * kq]);
-    for (int mb = 0; mb < MB; ++mb) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&gs[mb * 16 + col][8 * kq]);
-      acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mb], 0, 0, 0);
+    for (int st = 0; st < WS; ++st) {
+      const int n8 = 32 * st + 8 * kq;
+      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xs[wave * 16 + col][n8]);
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&gs[mb * 16 + col][n8]);
+        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mb], 0, 0, 0);
+      }
     }
     if (bias_thread)
-      for (int i = 0; i < 32; ++i) bsum += bf2f(gs[tid][i]);
+      for (int i = 0; i < 32 * WS; ++i) bsum += bf2f(gs[tid][i]);
     __syncthreads();
   }
   const int k = kt0 + wave * 16 + col;
@@ -400,7 +401,7 @@ void wgrad_split(long long npos, int kp, int *splits, int *chunk) {
   if (s > smax) s = smax;
   if (s < 1) s = 1;
   long long c = (npos + s - 1) / s;
-  c = (c + 31) / 32 * 32;
+  c = (c + 32 * WS - 1) / (32 * WS) * (32 * WS);   // whole LDS slabs
   s = (npos + c - 1) / c;
   *splits = (int)s;
   *chunk = (int)c;
