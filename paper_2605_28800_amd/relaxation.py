@@ -41,12 +41,14 @@ def relax(ctx, floor, check=100, max_steps=20000):
 
 
 def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=256,
-                  tune_steps=0, log=None):
+                  tune_steps=100, log=None):
     """Relax samples that share a recipe per key (e.g. film thickness) in
     batches of at most group_max.
 
     recipe(key) -> run recipe; keys, T: per sample; start: torch float32
-    device tensor [n][3][nz][ny][nx] (C/m^2).  Returns the relaxed P (device
+    device tensor [n][3][nz][ny][nx] (C/m^2).  Each batch context is
+    autotuned (FFT path and update tile, tune_steps steps per candidate)
+    before its relaxation is timed.  Returns the relaxed P (device
     tensor like start), relax steps, final energies F (J) and the seconds
     spent stepping (set-up excluded).  log(message), if given, hears of each
     finished group."""
