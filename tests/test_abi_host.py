@@ -211,3 +211,50 @@ def test_rk_tolerance_validation():
         assert T.tdgl_get_rk_state(ctx) == (0.0, 2e-3, 0)
     finally:
         T.tdgl_destroy(ctx)
+
+
+def test_net_create_rejects_bad_shapes():
+    from paper_2605_28800_amd.proposal import tdgl_net_cfg
+    bad = [
+        (64, 64, 16, 32, 8, 0),        # no batch
+        (64, 64, 16, 32, 8, 5000),     # batch above 4096
+        (48, 64, 16, 32, 8, 8),        # nx not a power of two
+        (64, 64, 2, 32, 8, 8),         # nz below 4
+        (64, 64, 16, 24, 8, 8),        # width not a power of two
+        (64, 64, 16, 4, 8, 8),         # width below 8
+        (64, 64, 16, 256, 8, 8),       # width above 128
+        (64, 64, 16, 32, 32, 8),       # noise block larger than nz
+        (64, 64, 16, 32, 3, 8),        # noise block not a power of two
+    ]
+    for c in bad:
+        cfg = tdgl_net_cfg(*c)
+        h = ctypes.c_void_p()
+        st = T.lib().tdgl_net_create(ctypes.byref(cfg), None, ctypes.byref(h))
+        assert st == T.TDGL_E_ARG, c
+        assert not h.value
+    assert T.lib().tdgl_net_create(None, None, ctypes.byref(ctypes.c_void_p())) == T.TDGL_E_ARG
+
+
+def test_single_layer_entry_points_validate_before_launch():
+    L = T.lib()
+    dummy = ctypes.c_void_p(16)        # never dereferenced: every call below is rejected
+    # cin_p not a power of two >= 16, cout_p below 16, epilogue out of range,
+    # output epilogue with cout_p != 16, missing output pointer
+    cases = [
+        (0, dummy, 0, dummy, dummy, 1, 3, 3, 3, 24, 32, dummy, None, None, None, None),
+        (0, dummy, 0, dummy, dummy, 1, 3, 3, 3, 32, 8, dummy, None, None, None, None),
+        (7, dummy, 0, dummy, dummy, 1, 3, 3, 3, 32, 32, dummy, None, None, None, None),
+        (2, dummy, 0, dummy, dummy, 1, 3, 3, 3, 32, 32, None, None, None, dummy, dummy),
+        (3, dummy, 0, dummy, None, 1, 3, 3, 3, 32, 32, None, None, None, None, None),
+        (1, dummy, 0, dummy, dummy, 1, 3, 3, 3, 32, 32, dummy, None, dummy, None, None),
+        (0, dummy, 1, dummy, dummy, 1, 0, 3, 3, 32, 32, dummy, None, None, None, None),
+    ]
+    for c in cases:
+        assert L.tdgl_nn_conv3(*c, None) == T.TDGL_E_ARG, c
+    nbytes = ctypes.c_size_t()
+    assert L.tdgl_nn_wgrad_workspace(1, 3, 3, 3, 24, 32, ctypes.byref(nbytes)) == T.TDGL_E_ARG
+    assert L.tdgl_nn_wgrad_workspace(2, 4, 4, 3, 32, 64, ctypes.byref(nbytes)) == T.TDGL_OK
+    assert nbytes.value >= 64 * 27 * 32 * 4
+    # too small a workspace
+    assert L.tdgl_nn_conv3_wgrad(dummy, dummy, 0, 2, 4, 4, 3, 32, 64, dummy, 16, dummy,
+                                 None) == T.TDGL_E_ARG
