@@ -332,6 +332,11 @@ def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, c
                      "network_seconds": round(r["network_seconds"], 4)},
         "steps_ratio": float(capped(s_pl).mean() / capped(s_pr).mean()),
         "time_ratio": float(r["plain_seconds"] / t_pr),
+        "instance_time_to_relaxed_s": {
+            "plain": float(r["plain_instance_seconds"].sum()),
+            "proposal": float(r["proposal_instance_seconds"].sum() + r["network_seconds"]),
+            "note": "sum over held-out samples of relax steps x the batch's time per step "
+                    "and instance (the cap where not relaxed), plus network inference"},
         "final_energy_rel_diff": {"median": float(np.median(dF)),
                                   "max_abs": float(np.abs(dF).max()),
                                   "lower_or_equal": int((dF <= 1e-6).sum())},
@@ -394,12 +399,15 @@ def main():
     ap.add_argument("--c3-seq-every", type=int, default=8,
                     help="plain runs: time every k-th instance alone and scale by k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--c5-train", type=int, default=0,
+    # learned-proposal leg; the defaults are its quarter-size version (the
+    # full one: --c5-train 1024 --c5-test 64 --c5-data-steps 12000
+    # --c5-train-steps 10000)
+    ap.add_argument("--c5-train", type=int, default=256,
                     help="learned-proposal leg: training samples (0 = leg off)")
-    ap.add_argument("--c5-test", type=int, default=64)
-    ap.add_argument("--c5-data-steps", type=int, default=12000)
+    ap.add_argument("--c5-test", type=int, default=32)
+    ap.add_argument("--c5-data-steps", type=int, default=8000)
     ap.add_argument("--c5-eval-steps", type=int, default=20000)
-    ap.add_argument("--c5-train-steps", type=int, default=10000)
+    ap.add_argument("--c5-train-steps", type=int, default=2000)
     ap.add_argument("--c5-batch", type=int, default=8)
     ap.add_argument("--c5-width", type=int, default=32)
     ap.add_argument("--c5-only", action="store_true", help="run only the learned-proposal leg")

@@ -49,15 +49,18 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
     device tensor [n][3][nz][ny][nx] (C/m^2).  Each batch context is
     autotuned (FFT path and update tile, tune_steps steps per candidate)
     before its relaxation is timed.  Returns the relaxed P (device
-    tensor like start), relax steps, final energies F (J) and the seconds
-    spent stepping (set-up excluded).  log(message), if given, hears of each
-    finished group."""
+    tensor like start), relax steps, final energies F (J), the seconds spent
+    stepping (set-up excluded) and, per sample, its time to relaxed: its
+    relax step count times its batch's measured time per step and instance
+    (the cap for samples that did not relax).  log(message), if given, hears
+    of each finished group."""
     import torch
     keys = np.asarray(keys)
     n = len(keys)
     out = torch.empty_like(start)
     steps = np.full(n, -1)
     F = np.zeros(n)
+    t_inst = np.zeros(n)
     seconds = 0.0
     for k in np.unique(keys):
         rows_all = np.flatnonzero(keys == k)
@@ -75,10 +78,12 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
                     ctx.set_P(start.index_select(0, ridx).contiguous())
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                done, _ = relax(ctx, relax_floor(cfg), check, max_steps)
+                done, taken = relax(ctx, relax_floor(cfg), check, max_steps)
                 torch.cuda.synchronize()
-                seconds += time.perf_counter() - t0
+                dt = time.perf_counter() - t0
+                seconds += dt
                 steps[rows] = done
+                t_inst[rows] = np.where(done > 0, done, max_steps) * dt / (taken * len(rows))
                 F[rows] = ctx.energies_batch()[0][:, 4]
                 out.index_copy_(0, ridx, ctx.get_P_device(TDGL_FP32))
                 if log:
@@ -86,7 +91,7 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
                         % (k, len(rows), (done > 0).sum(), seconds))
             finally:
                 ctx.close()
-    return out, steps, F, seconds
+    return out, steps, F, seconds, t_inst
 
 
 def train(net, rows, T, thick, noise, target, steps, batch, lr, seed=0, lr_final=None):
@@ -147,8 +152,8 @@ def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_tra
     dT, dth, dn = (torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(starts.device)
                    for a in (T, thick, noise))
     tr, te = np.arange(n_train), np.arange(n_train, n)
-    P_tr, s_tr, F_tr, t_data = relax_grouped(recipe, thick[tr], T[tr], starts[:n_train], check,
-                                             data_steps, log=log)
+    P_tr, s_tr, F_tr, t_data, _ = relax_grouped(recipe, thick[tr], T[tr], starts[:n_train],
+                                                check, data_steps, log=log)
     target = torch.zeros((n, 3) + tuple(shape), dtype=torch.float32, device=starts.device)
     target[:n_train] = P_tr
     net = Net(shape, width=width, noise_div=noise_div, max_batch=batch)
@@ -166,15 +171,16 @@ def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_tra
         t_net = time.perf_counter() - t0
     finally:
         net.close()
-    P_pl, s_pl, F_pl, t_pl = relax_grouped(recipe, thick[te], T[te], starts[n_train:], check,
-                                           eval_steps, log=log)
-    P_pr, s_pr, F_pr, t_pr = relax_grouped(recipe, thick[te], T[te], prop, check, eval_steps,
-                                           log=log)
+    P_pl, s_pl, F_pl, t_pl, i_pl = relax_grouped(recipe, thick[te], T[te], starts[n_train:],
+                                                 check, eval_steps, log=log)
+    P_pr, s_pr, F_pr, t_pr, i_pr = relax_grouped(recipe, thick[te], T[te], prop, check,
+                                                 eval_steps, log=log)
     floor = np.array([relax_floor(recipe(k)) for k in thick[te]])
     dP = [(torch.linalg.norm(P_pr[i] - P_pl[i]) / max(torch.linalg.norm(P_pl[i]).item(), 1e-30)).item()
           for i in range(len(te))]
     return dict(train_steps_relaxed=s_tr, data_seconds=t_data, losses=losses,
                 train_seconds=t_train, profile_ms=prof, network_seconds=t_net,
                 plain_steps=s_pl, proposal_steps=s_pr, plain_F=F_pl, proposal_F=F_pr,
-                plain_seconds=t_pl, proposal_seconds=t_pr, energy_floor=floor,
+                plain_seconds=t_pl, proposal_seconds=t_pr, plain_instance_seconds=i_pl,
+                proposal_instance_seconds=i_pr, energy_floor=floor,
                 P_rel_diff=np.asarray(dP))
