@@ -62,10 +62,13 @@ def model_bytes_per_cell_step(dims, esz):
 
 
 def source_hash():
+    """Hash of the TDGL step's sources (the proposal network's net* files
+    do not change the step's kernels)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_28800_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        if not f.startswith("net"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
