@@ -357,6 +357,36 @@ def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, c
     return res
 
 
+def run_c4(args, names=("y_forward", "z_tensor", "y_inverse", "update_predictor",
+                         "update_corrector")):
+    """The 256x256x64 bilayer: timed Heun steps (graph chunks unless
+    --graph-chunk says otherwise) and, with --kernel-reps, each step kernel
+    timed over graph replays."""
+    import paper_2605_28800_amd as T
+    import tdgl_inputs as I
+    cfg4 = I.config("c4")
+    n4 = cfg4["n"][0] * cfg4["n"][1] * cfg4["n"][2]
+    log("c4 fp32 run: %d timed Heun steps" % args.c4_steps)
+    r4 = run_gpu(cfg4, T.TDGL_FP32, args.c4_steps, 20, 0, chunk=args.graph_chunk,
+                 kernel_reps=20 if args.kernel_reps else 0)
+    v4 = n4 * args.c4_steps / (r4["ms"] / 1e3)
+    b4 = model_bytes_per_cell_step(r4["dims"], 4)
+    kb4 = kernel_bytes(r4["dims"], 4)
+    k4 = None
+    if r4["kprof"] is not None:
+        k4 = {k: {"ms": round(ms, 5), "alg_bytes": kb4[k],
+                  "GBps": round(kb4[k] / (ms * 1e-3) / 1e9, 1) if ms else None}
+              for k, ms in zip(names, r4["kprof"])}
+    c4 = {"workload": "PbTiO3/SrTiO3 bilayer 256x256x64 (48+16 layers), open, padded "
+                      "512x512x128, uniform random start, all terms, Heun dtau=1e-3",
+          "value": v4, "unit": "cell-steps/s", "steps": args.c4_steps,
+          "ms_per_step": r4["ms"] / args.c4_steps, "bytes_per_cell_step": round(b4, 1),
+          "roofline_frac_step": round(v4 * b4 / (HBM_PEAK_GBS * 1e9), 4), "kernels": k4}
+    log("c4: %.4f ms/step, %.3e cell-steps/s, step roofline %.3f"
+        % (c4["ms_per_step"], v4, c4["roofline_frac_step"]))
+    return c4
+
+
 def cpu_baseline(cfg, nsteps):
     """The oracle as it stands, timed on the host on a few Heun steps of the
     same grid.  Its interaction table is built with mimg = 0 (the cost of a
@@ -414,6 +444,7 @@ def main():
     ap.add_argument("--c5-batch", type=int, default=8)
     ap.add_argument("--c5-width", type=int, default=32)
     ap.add_argument("--c5-only", action="store_true", help="run only the learned-proposal leg")
+    ap.add_argument("--c4-only", action="store_true", help="run only the bilayer leg")
     ap.add_argument("--fft-path", type=int, default=0, help="0 auto (fused if it fits), 1 three passes")
     ap.add_argument("--rows", type=int, default=0, help="update-kernel rows per group (0 auto)")
     ap.add_argument("--graph-chunk", type=int, default=None,
@@ -449,6 +480,9 @@ def main():
         __graft_entry__.build()
     import tdgl_inputs as I
 
+    if args.c4_only:
+        print(json.dumps({"c4_large_grid": run_c4(args)}), flush=True)
+        return
     if args.c5_only:
         print(json.dumps({"c5_learned_proposal": run_c5(
             args.c5_train, args.c5_test, args.c5_data_steps, args.c5_eval_steps,
@@ -510,25 +544,7 @@ def main():
                 / (HBM_PEAK_GBS * 1e9)}
         log("fp64: %.4f ms/step, %.3e cell-steps/s" % (fp64["ms_per_step"], v64))
 
-    c4 = None
-    if args.c4_steps > 0:
-        cfg4 = I.config("c4")
-        n4 = cfg4["n"][0] * cfg4["n"][1] * cfg4["n"][2]
-        log("c4 fp32 run: %d timed Heun steps" % args.c4_steps)
-        r4 = run_gpu(cfg4, T.TDGL_FP32, args.c4_steps, 20, 0, kernel_reps=20)
-        v4 = n4 * args.c4_steps / (r4["ms"] / 1e3)
-        b4 = model_bytes_per_cell_step(r4["dims"], 4)
-        kb4 = kernel_bytes(r4["dims"], 4)
-        k4 = {k: {"ms": round(ms, 5), "alg_bytes": kb4[k],
-                  "GBps": round(kb4[k] / (ms * 1e-3) / 1e9, 1) if ms else None}
-              for k, ms in zip(names, r4["kprof"])}
-        c4 = {"workload": "PbTiO3/SrTiO3 bilayer 256x256x64 (48+16 layers), open, padded "
-                          "512x512x128, uniform random start, all terms, Heun dtau=1e-3",
-              "value": v4, "unit": "cell-steps/s", "steps": args.c4_steps,
-              "ms_per_step": r4["ms"] / args.c4_steps, "bytes_per_cell_step": round(b4, 1),
-              "roofline_frac_step": round(v4 * b4 / (HBM_PEAK_GBS * 1e9), 4), "kernels": k4}
-        log("c4: %.4f ms/step, %.3e cell-steps/s, step roofline %.3f"
-            % (c4["ms_per_step"], v4, c4["roofline_frac_step"]))
+    c4 = run_c4(args) if args.c4_steps > 0 else None
 
     loop = None
     if args.c4_loop_values > 0:

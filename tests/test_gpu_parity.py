@@ -36,6 +36,8 @@ CASES = {
     "bulk_8x16x8": dict(n=(8, 16, 8), periodic=(1, 1, 1)),
     "bilayer_vacuum_10x12x6": dict(n=(10, 12, 6), periodic=(0, 0, 0),
                                    layers=[0, 0, 0, 1, 1, -1], two_materials=True),
+    # 512-point x transforms: the update tile needs more than 64 KiB of LDS
+    "open_long_rows_256x8x4": dict(n=(256, 8, 4), periodic=(0, 0, 0)),
 }
 
 
