@@ -73,7 +73,9 @@ tdgl_status tdgl_net_get_params(tdgl_net *net, float *host, long long n);
 
 /* Forward pass of nb samples (1..max_batch).  Sample i uses dataset row
  * idx[i] (device int array) or row i if idx is NULL; T, thick, noise are
- * device arrays over the dataset rows.  P_out (device, may be NULL to keep
+ * device arrays over the dataset rows.  The library cannot see the length
+ * of these device arrays: every idx entry (or, without idx, every row
+ * below nb) must be a row they hold.  P_out (device, may be NULL to keep
  * the result internal) receives [nb][3][nz][ny][nx] FP32 in C/m^2, zero in
  * the vacuum layers.  Asynchronous. */
 tdgl_status tdgl_net_forward(tdgl_net *net, int nb, const int *idx, const float *T,
