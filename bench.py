@@ -287,7 +287,7 @@ def net_flops(width, shape):
 
 
 def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, check=100,
-           seed=7):
+           seed=7, augment=-1):
     """Learned initial-state proposal on 64x64x16 BaTiO3 films (thickness
     8..16 layers, T ~ U(250, 450) K): relax n_train seeded random starts
     (batched, one context per thickness) to make the training set, train the
@@ -304,10 +304,11 @@ def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, c
     starts = torch.from_numpy(I.noise_start(noise, th, shape)).cuda()
     log("c5: %d training starts (cap %d steps), %d training steps, %d held-out samples"
         % (n_train, data_steps, train_steps, n_test))
+    aug = (n_train >= 512) if augment < 0 else bool(augment)
     r = R.proposal_experiment(lambda k: I.c5_recipe(int(k), shape), shape, noise_div, T, th,
                               noise, starts, n_train, I.net_params(width, seed=seed), width,
                               data_steps, eval_steps, train_steps, batch, check, seed=seed,
-                              profile=True, log=lambda m: log("c5: " + m))
+                              profile=True, log=lambda m: log("c5: " + m), augment=aug)
     capped = lambda s: np.where(s > 0, s, eval_steps)
     s_pl, s_pr = r["plain_steps"], r["proposal_steps"]
     dF = (r["proposal_F"] - r["plain_F"]) / np.maximum(np.abs(r["plain_F"]), r["energy_floor"])
@@ -322,7 +323,8 @@ def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, c
                         width, sum(co * 27 * ci + co for ci, co in I.net_layer_shapes(width))),
         "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V)" % check,
         "train_samples": n_train, "train_relaxed": int((r["train_steps_relaxed"] > 0).sum()),
-        "trained_on": "relaxed training states only",
+        "trained_on": "relaxed training states only" + (
+            ", each minibatch sample under a random in-plane symmetry op" if aug else ""),
         "data_steps_cap": data_steps, "data_seconds": round(r["data_seconds"], 2),
         "train_steps": train_steps, "batch": batch, "train_seconds": round(r["train_seconds"], 2),
         "loss_first20": float(losses[:20].mean()), "loss_last20": float(losses[-20:].mean()),
@@ -443,6 +445,10 @@ def main():
     ap.add_argument("--c5-train-steps", type=int, default=2000)
     ap.add_argument("--c5-batch", type=int, default=8)
     ap.add_argument("--c5-width", type=int, default=32)
+    ap.add_argument("--c5-augment", type=int, default=-1,
+                    help="train under random in-plane symmetry ops: 1 on, 0 off, -1 on from "
+                         "512 training samples (measured: helps with 503 relaxed states, "
+                         "hurts with 90)")
     ap.add_argument("--c5-only", action="store_true", help="run only the learned-proposal leg")
     ap.add_argument("--c4-only", action="store_true", help="run only the bilayer leg")
     ap.add_argument("--fft-path", type=int, default=0, help="0 auto (fused if it fits), 1 three passes")
@@ -486,7 +492,8 @@ def main():
     if args.c5_only:
         print(json.dumps({"c5_learned_proposal": run_c5(
             args.c5_train, args.c5_test, args.c5_data_steps, args.c5_eval_steps,
-            args.c5_train_steps, args.c5_batch, args.c5_width)}), flush=True)
+            args.c5_train_steps, args.c5_batch, args.c5_width, augment=args.c5_augment)}),
+            flush=True)
         return
 
     cfg = I.config("c2")
@@ -578,7 +585,7 @@ def main():
     c5 = None
     if args.c5_train > 0:
         c5 = run_c5(args.c5_train, args.c5_test, args.c5_data_steps, args.c5_eval_steps,
-                    args.c5_train_steps, args.c5_batch, args.c5_width)
+                    args.c5_train_steps, args.c5_batch, args.c5_width, augment=args.c5_augment)
 
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:

@@ -81,26 +81,37 @@ tdgl_status tdgl_net_get_params(tdgl_net *net, float *host, long long n);
 tdgl_status tdgl_net_forward(tdgl_net *net, int nb, const int *idx, const float *T,
                              const float *thick, const float *noise, float *P_out);
 
+/* In-plane symmetry ops (training augmentation).  ops[i] (device int,
+ * bits: 1 mirror x, 2 mirror y, 4 swap x and y -- ignored unless nx == ny)
+ * replaces sample i's noise field and target by their images under the op:
+ * F'(x, y) = D F(src(x, y)) with src = swap(mirror_x(mirror_y(x, y))),
+ * F'_x = (-1)^mirror_x F_(swap ? y : x), F'_y = (-1)^mirror_y F_(swap ? x : y),
+ * F'_z = F_z.  The open film is invariant under these ops, so the relaxed
+ * state of the image of a start is the image of its relaxed state.  NULL:
+ * no op. */
+
 /* Forward and backward pass against target rows (device
- * [row][3][nz][ny][nx]).  Returns the loss and, if grad_host is not NULL,
- * the gradient in the parameter layout; the gradient stays on the device
- * for tdgl_net_adam.  Synchronising. */
-tdgl_status tdgl_net_loss_grad(tdgl_net *net, int nb, const int *idx, const float *T,
-                               const float *thick, const float *noise, const float *target,
-                               double *loss, float *grad_host);
+ * [row][3][nz][ny][nx]), each sample under its symmetry op (ops may be
+ * NULL).  Returns the loss and, if grad_host is not NULL, the gradient in
+ * the parameter layout; the gradient stays on the device for
+ * tdgl_net_adam.  Synchronising. */
+tdgl_status tdgl_net_loss_grad(tdgl_net *net, int nb, const int *idx, const int *ops,
+                               const float *T, const float *thick, const float *noise,
+                               const float *target, double *loss, float *grad_host);
 
 /* One Adam step (Kingma and Ba 2015, bias-corrected) with the gradient of
  * the last tdgl_net_loss_grad.  TDGL_E_STATE if there is none.  Async. */
 tdgl_status tdgl_net_adam(tdgl_net *net, double lr, double beta1, double beta2, double eps);
 
 /* nsteps training steps of nb samples each: step s uses rows
- * idx[s * nb .. s * nb + nb - 1] (device), forward, backward, Adam with the
- * given rate.  losses_host (nsteps doubles, may be NULL) receives each
- * step's loss before its update.  Synchronising. */
-tdgl_status tdgl_net_train(tdgl_net *net, int nsteps, int nb, const int *idx, const float *T,
-                           const float *thick, const float *noise, const float *target,
-                           double lr, double beta1, double beta2, double eps,
-                           double *losses_host);
+ * idx[s * nb .. s * nb + nb - 1] (device) under the symmetry ops
+ * ops[s * nb ..] (device, or NULL), forward, backward, Adam with the given
+ * rate.  losses_host (nsteps doubles, may be NULL) receives each step's
+ * loss before its update.  Synchronising. */
+tdgl_status tdgl_net_train(tdgl_net *net, int nsteps, int nb, const int *idx, const int *ops,
+                           const float *T, const float *thick, const float *noise,
+                           const float *target, double lr, double beta1, double beta2,
+                           double eps, double *losses_host);
 
 /* Time the parts of one training step of nb samples (rows 0..nb-1):
  * ms[0] forward, ms[1] loss + backward + gradient reduction, ms[2] Adam,

@@ -27,6 +27,9 @@ Definition (all arrays [batch][channel][z][y][x]):
 * Loss: sum over samples, components and film cells of (P - P_target)^2
   divided by 3 x the number of film cells in the batch.
 * Adam (Kingma and Ba 2015) with bias correction on FP32 master weights.
+* Training augmentation: a sample may be taken under an in-plane symmetry op
+  (apply_op on its noise field and target); the open film is invariant
+  under these ops.
 
 Parameters are one flat vector: per layer, W as [cout][27][cin] in C order,
 then b [cout].
@@ -244,6 +247,23 @@ def loss_and_grad(theta, width, T, thickness, noise, target, shape, bf16=False):
     g = r(conv3_input_grad(g, L[1][0]) * act_slope(c["e0a"]))
     grads[0] = conv3_weight_grad(g, c["x"])
     return loss, P, pack(grads)
+
+
+def apply_op(F, op):
+    """Image of vector fields F [..][3][Z][Y][X] under an in-plane symmetry
+    op (bits: 1 mirror x, 2 mirror y, 4 swap x and y): the swap first, then
+    the x mirror, then the y mirror, each moving positions and components
+    (a mirror negates the normal component)."""
+    G = np.array(F, dtype=np.float64, copy=True)
+    if op & 4:
+        G = np.swapaxes(G, -1, -2)[..., [1, 0, 2], :, :, :].copy()
+    if op & 1:
+        G = G[..., ::-1].copy()
+        G[..., 0, :, :, :] *= -1
+    if op & 2:
+        G = G[..., ::-1, :].copy()
+        G[..., 1, :, :, :] *= -1
+    return G
 
 
 def adam(theta, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

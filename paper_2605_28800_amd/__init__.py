@@ -104,10 +104,10 @@ _SIGS = {
     "tdgl_net_forward": ([c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
                          c_int),
     "tdgl_net_loss_grad": ([c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                            ctypes.POINTER(c_double), c_void_p], c_int),
+                            c_void_p, ctypes.POINTER(c_double), c_void_p], c_int),
     "tdgl_net_adam": ([c_void_p, c_double, c_double, c_double, c_double], c_int),
     "tdgl_net_train": ([c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                        c_double, c_double, c_double, c_double, c_void_p], c_int),
+                        c_void_p, c_double, c_double, c_double, c_double, c_void_p], c_int),
     "tdgl_net_profile": ([c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                           ctypes.POINTER(c_double)], c_int),
     "tdgl_nn_conv3": ([c_int, c_void_p, c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_int,

@@ -426,8 +426,30 @@ hipError_t launch_wgrad(const WgradArgs &a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ elementwise
+// In-plane symmetry op of a sample (bits: 1 mirror x, 2 mirror y, 4 swap x
+// and y; swap only on square grids): the sample's vector fields F become
+// F'(x, y) = D F(src(x, y)) with src = swap(mirror_x(mirror_y(x, y))) and
+// F'_x = (-1)^mx F_(swap ? y : x), F'_y = (-1)^my F_(swap ? x : y), F'_z = F_z.
+struct SymOp {
+  int mx, my, sw;
+  __device__ explicit SymOp(int op) : mx(op & 1), my((op >> 1) & 1), sw((op >> 2) & 1) {}
+  // source (x, y) of destination (x, y) on an X x Y grid
+  __device__ void src(int &x, int &y, int X, int Y) const {
+    if (my) y = Y - 1 - y;
+    if (mx) x = X - 1 - x;
+    if (sw) {
+      const int t = x;
+      x = y;
+      y = t;
+    }
+  }
+  // source component and sign of destination component c
+  __device__ int comp(int c) const { return (sw && c < 2) ? 1 - c : c; }
+  __device__ float sign(int c) const { return (c == 0 && mx) || (c == 1 && my) ? -1.f : 1.f; }
+};
+
 __global__ void k_input(const float *T, const float *thick, const float *noise, const int *idx,
-                        int lx, int ly, int lz, int nb, int ld, bf16_t *x0) {
+                        const int *ops, int lx, int ly, int lz, int nb, int ld, bf16_t *x0) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int ls = lx + ly + lz;
   if (n >= ((long long)nb << ls)) return;
@@ -435,13 +457,17 @@ __global__ void k_input(const float *T, const float *thick, const float *noise, 
   const int row = idx ? idx[p.b] : p.b;
   const float m = (float)p.z < thick[row] ? 1.f : 0.f;
   const int cx = lx - ld, cy = ly - ld, cz = lz - ld;
-  const long long cell = (((long long)(p.z >> ld) << cy) + (p.y >> ld)) * (1LL << cx) + (p.x >> ld);
+  const SymOp g(ops ? ops[p.b] & (lx == ly ? 7 : 3) : 0);
+  int qx = p.x >> ld, qy = p.y >> ld;
+  g.src(qx, qy, 1 << cx, 1 << cy);
+  const long long cell = (((long long)(p.z >> ld) << cy) + qy) * (1LL << cx) + qx;
   const long long nc = 1LL << (cx + cy + cz);
   float v[16];
   for (int c = 0; c < 16; ++c) v[c] = 0.f;
   v[0] = m * ((T[row] - 350.f) / 100.f);
   v[1] = m;
-  for (int c = 0; c < 3; ++c) v[2 + c] = m * (noise[((long long)row * 3 + c) * nc + cell] * 10.f);
+  for (int c = 0; c < 3; ++c)
+    v[2 + c] = m * (g.sign(c) * noise[((long long)row * 3 + g.comp(c)) * nc + cell] * 10.f);
   uint32_t w[8];
   for (int i = 0; i < 8; ++i) w[i] = f2bf(v[2 * i]) | ((uint32_t)f2bf(v[2 * i + 1]) << 16);
   uint4 *o = reinterpret_cast<uint4 *>(x0 + n * 16);
@@ -450,14 +476,14 @@ __global__ void k_input(const float *T, const float *thick, const float *noise, 
 }
 
 hipError_t launch_input(const float *T, const float *thick, const float *noise, const int *idx,
-                        int lx, int ly, int lz, int nb, int noise_div, bf16_t *x0,
+                        const int *ops, int lx, int ly, int lz, int nb, int noise_div, bf16_t *x0,
                         hipStream_t s) {
   if (!pow2(noise_div)) return hipErrorInvalidValue;
   const int ld = __builtin_ctz(noise_div);
   if (ld > lx || ld > ly || ld > lz) return hipErrorInvalidValue;
   const long long n = (long long)nb << (lx + ly + lz);
   hipLaunchKernelGGL(k_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, thick, noise,
-                     idx, lx, ly, lz, nb, ld, x0);
+                     idx, ops, lx, ly, lz, nb, ld, x0);
   return hipGetLastError();
 }
 
@@ -586,8 +612,9 @@ hipError_t launch_up_bwd(const bf16_t *g, const bf16_t *a, int lx, int ly, int l
 // 3 x the film cells of the batch (FP64 partial per block), and the BF16
 // gradient 2 m (P - target) / count in channels 0..2 of 16
 __global__ __launch_bounds__(256) void k_loss(const float *P, const float *target,
-                                              const float *thick, const int *idx, int lx, int ly,
-                                              int lz, int nb, bf16_t *gy, double *partials) {
+                                              const float *thick, const int *idx, const int *ops,
+                                              int lx, int ly, int lz, int nb, bf16_t *gy,
+                                              double *partials) {
   __shared__ double red[4];
   const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
   const int ls = lx + ly + lz;
@@ -605,11 +632,17 @@ __global__ __launch_bounds__(256) void k_loss(const float *P, const float *targe
     const int row = idx ? idx[p.b] : p.b;
     const float m = (float)p.z < thick[row] ? 1.f : 0.f;
     const long long r = n & ((1LL << ls) - 1);
+    // the target is read through the sample's symmetry op
+    const SymOp op(ops ? ops[p.b] & (lx == ly ? 7 : 3) : 0);
+    int sx = p.x, sy = p.y;
+    op.src(sx, sy, 1 << lx, 1 << ly);
+    const long long rs = ((long long)p.z << (lx + ly)) + ((long long)sy << lx) + sx;
     float g[16];
     for (int c = 0; c < 16; ++c) g[c] = 0.f;
     for (int c = 0; c < 3; ++c) {
       const double d = (double)P[(((long long)p.b * 3 + c) << ls) + r] -
-                       (double)target[(((long long)row * 3 + c) << ls) + r];
+                       (double)op.sign(c) *
+                           (double)target[(((long long)row * 3 + op.comp(c)) << ls) + rs];
       e += m * d * d;
       g[c] = (float)(m * 2.0 * d * inv_count);
     }
@@ -626,14 +659,14 @@ __global__ __launch_bounds__(256) void k_loss(const float *P, const float *targe
 }
 
 hipError_t launch_loss(const float *P, const float *target, const float *thick, const int *idx,
-                       int lx, int ly, int lz, int nb, bf16_t *gy, double *partials,
-                       int *nblocks, hipStream_t s) {
+                       const int *ops, int lx, int ly, int lz, int nb, bf16_t *gy,
+                       double *partials, int *nblocks, hipStream_t s) {
   const long long n = (long long)nb << (lx + ly + lz);
   const long long nbk = (n + 255) / 256;
   if (nb < 1 || nbk > 0x7FFFFFFF) return hipErrorInvalidValue;
   *nblocks = (int)nbk;
-  hipLaunchKernelGGL(k_loss, dim3((unsigned)nbk), dim3(256), 0, s, P, target, thick, idx, lx, ly,
-                     lz, nb, gy, partials);
+  hipLaunchKernelGGL(k_loss, dim3((unsigned)nbk), dim3(256), 0, s, P, target, thick, idx, ops, lx,
+                     ly, lz, nb, gy, partials);
   return hipGetLastError();
 }
 

@@ -170,12 +170,13 @@ hipError_t cast_all(tdgl_net *n) {
   return hipSuccess;
 }
 
-hipError_t forward(tdgl_net *n, int nb, const int *idx, const float *T, const float *thick,
-                   const float *noise) {
+hipError_t forward(tdgl_net *n, int nb, const int *idx, const int *ops, const float *T,
+                   const float *thick, const float *noise) {
   hipError_t e;
 #define RUN(x) \
   if ((e = (x)) != hipSuccess) return e
-  RUN(launch_input(T, thick, noise, idx, n->lx, n->ly, n->lz, nb, n->cfg.noise_div, n->x0, n->s));
+  RUN(launch_input(T, thick, noise, idx, ops, n->lx, n->ly, n->lz, nb, n->cfg.noise_div, n->x0,
+                   n->s));
   RUN(conv_fwd(n, 0, nb, n->x0, EPI_ACT, n->e0a, nullptr, nullptr, idx, thick));
   RUN(conv_fwd(n, 1, nb, n->e0a, EPI_ACT, n->e0, nullptr, nullptr, idx, thick));
   RUN(launch_pool(n->e0, n->lx, n->ly, n->lz, nb, n->L[1].cout_p, n->p1, n->s));
@@ -194,12 +195,12 @@ hipError_t forward(tdgl_net *n, int nb, const int *idx, const float *T, const fl
 }
 
 // loss into *loss_dev, gradient into n->grad
-hipError_t backward(tdgl_net *n, int nb, const int *idx, const float *thick, const float *target,
-                    double *loss_dev) {
+hipError_t backward(tdgl_net *n, int nb, const int *idx, const int *ops, const float *thick,
+                    const float *target, double *loss_dev) {
   hipError_t e;
   int nblk = 0;
-  RUN(launch_loss(n->P, target, thick, idx, n->lx, n->ly, n->lz, nb, n->gy, n->loss_part, &nblk,
-                  n->s));
+  RUN(launch_loss(n->P, target, thick, idx, ops, n->lx, n->ly, n->lz, nb, n->gy, n->loss_part,
+                  &nblk, n->s));
   RUN(launch_sum_partials(n->loss_part, nblk, loss_dev, n->s));
   const int l0x = n->lx, l0y = n->ly, l0z = n->lz;
   RUN(wgrad(n, 11, nb, n->gy, n->u0b));
@@ -380,21 +381,21 @@ tdgl_status tdgl_net_forward(tdgl_net *n, int nb, const int *idx, const float *T
                              const float *thick, const float *noise, float *P_out) {
   tdgl_status st = check_batch(n, nb, T, thick, noise);
   if (st != TDGL_OK) return st;
-  CK(forward(n, nb, idx, T, thick, noise));
+  CK(forward(n, nb, idx, nullptr, T, thick, noise));
   if (P_out)
     CK(hipMemcpyAsync(P_out, n->P, (size_t)nb * 3 * n->cells(0) * sizeof(float),
                       hipMemcpyDeviceToDevice, n->s));
   return TDGL_OK;
 }
 
-tdgl_status tdgl_net_loss_grad(tdgl_net *n, int nb, const int *idx, const float *T,
+tdgl_status tdgl_net_loss_grad(tdgl_net *n, int nb, const int *idx, const int *ops, const float *T,
                                const float *thick, const float *noise, const float *target,
                                double *loss, float *grad_host) {
   tdgl_status st = check_batch(n, nb, T, thick, noise);
   if (st != TDGL_OK) return st;
   if (!target || !loss) return fail(n, TDGL_E_ARG, "null target or loss");
-  CK(forward(n, nb, idx, T, thick, noise));
-  CK(backward(n, nb, idx, thick, target, n->loss_dev));
+  CK(forward(n, nb, idx, ops, T, thick, noise));
+  CK(backward(n, nb, idx, ops, thick, target, n->loss_dev));
   CK(hipMemcpyAsync(loss, n->loss_dev, sizeof(double), hipMemcpyDeviceToHost, n->s));
   if (grad_host)
     CK(hipMemcpyAsync(grad_host, n->grad, n->nparam * sizeof(float), hipMemcpyDeviceToHost, n->s));
@@ -413,9 +414,10 @@ tdgl_status tdgl_net_adam(tdgl_net *n, double lr, double b1, double b2, double e
   return TDGL_OK;
 }
 
-tdgl_status tdgl_net_train(tdgl_net *n, int nsteps, int nb, const int *idx, const float *T,
-                           const float *thick, const float *noise, const float *target,
-                           double lr, double b1, double b2, double eps, double *losses_host) {
+tdgl_status tdgl_net_train(tdgl_net *n, int nsteps, int nb, const int *idx, const int *ops,
+                           const float *T, const float *thick, const float *noise,
+                           const float *target, double lr, double b1, double b2, double eps,
+                           double *losses_host) {
   tdgl_status st = check_batch(n, nb, T, thick, noise);
   if (st != TDGL_OK) return st;
   if (!idx || !target || nsteps < 1 || nsteps > 4096)
@@ -424,8 +426,9 @@ tdgl_status tdgl_net_train(tdgl_net *n, int nsteps, int nb, const int *idx, cons
     return fail(n, TDGL_E_ARG, "Adam hyper-parameters out of range");
   for (int k = 0; k < nsteps; ++k) {
     const int *ik = idx + (size_t)k * nb;
-    CK(forward(n, nb, ik, T, thick, noise));
-    CK(backward(n, nb, ik, thick, target, n->loss_dev + k));
+    const int *ok = ops ? ops + (size_t)k * nb : nullptr;
+    CK(forward(n, nb, ik, ok, T, thick, noise));
+    CK(backward(n, nb, ik, ok, thick, target, n->loss_dev + k));
     CK(adam_step(n, lr, b1, b2, eps));
   }
   std::vector<double> l(nsteps);
@@ -455,13 +458,13 @@ tdgl_status tdgl_net_profile(tdgl_net *n, int nb, const float *T, const float *t
   for (auto &e : ev) CK(hipEventCreate(&e));
   double acc[3] = {0, 0, 0};
   // warm-up
-  CK(forward(n, nb, nullptr, T, thick, noise));
-  CK(backward(n, nb, nullptr, thick, target, n->loss_dev));
+  CK(forward(n, nb, nullptr, nullptr, T, thick, noise));
+  CK(backward(n, nb, nullptr, nullptr, thick, target, n->loss_dev));
   for (int r = 0; r < reps; ++r) {
     CK(hipEventRecord(ev[0], n->s));
-    CK(forward(n, nb, nullptr, T, thick, noise));
+    CK(forward(n, nb, nullptr, nullptr, T, thick, noise));
     CK(hipEventRecord(ev[1], n->s));
-    CK(backward(n, nb, nullptr, thick, target, n->loss_dev));
+    CK(backward(n, nb, nullptr, nullptr, thick, target, n->loss_dev));
     CK(hipEventRecord(ev[2], n->s));
     CK(adam_step(n, 1e-3, 0.9, 0.999, 1e-8));
     CK(hipEventRecord(ev[3], n->s));

@@ -58,8 +58,10 @@ hipError_t launch_wgrad(const WgradArgs &a, hipStream_t s);
 void wgrad_split(long long npos, int kp, int *splits, int *chunk);
 
 // elementwise parts
+// ops: per-sample in-plane symmetry op (bits: 1 mirror x, 2 mirror y, 4 swap
+// x and y on square grids), or null for none
 hipError_t launch_input(const float *T, const float *thick, const float *noise, const int *idx,
-                        int lx, int ly, int lz, int nb, int noise_div, bf16_t *x0,
+                        const int *ops, int lx, int ly, int lz, int nb, int noise_div, bf16_t *x0,
                         hipStream_t s);
 hipError_t launch_pool(const bf16_t *in, int lx, int ly, int lz, int nb, int c_p, bf16_t *out,
                        hipStream_t s);
@@ -68,8 +70,8 @@ hipError_t launch_pool_bwd(const bf16_t *g, const bf16_t *add, const bf16_t *a, 
 hipError_t launch_up_bwd(const bf16_t *g, const bf16_t *a, int lx, int ly, int lz, int nb,
                          int c_p, bf16_t *out, hipStream_t s);
 hipError_t launch_loss(const float *P, const float *target, const float *thick, const int *idx,
-                       int lx, int ly, int lz, int nb, bf16_t *gy, double *partials,
-                       int *nblocks, hipStream_t s);
+                       const int *ops, int lx, int ly, int lz, int nb, bf16_t *gy,
+                       double *partials, int *nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t s);
 hipError_t launch_reduce_grad(const float *part, const float *bpart, int splits, int cin,
                               int cout, int cin_p, int cout_p, float *grad, hipStream_t s);

@@ -83,24 +83,26 @@ class Net:
                                            _ptr(noise), _ptr(P)))
         return P
 
-    def loss_grad(self, T, thick, noise, target, idx=None, nb=None, want_grad=True):
+    def loss_grad(self, T, thick, noise, target, idx=None, nb=None, want_grad=True, ops=None):
+        """ops: int32 device tensor of per-sample in-plane symmetry ops, or None."""
         nb = nb if nb is not None else (len(idx) if idx is not None else T.shape[0])
         loss = c_double()
         g = np.empty(self.num_params, dtype=np.float32) if want_grad else None
         self._check(lib().tdgl_net_loss_grad(
-            self.h, nb, _ptr(idx), _ptr(T), _ptr(thick), _ptr(noise), _ptr(target),
+            self.h, nb, _ptr(idx), _ptr(ops), _ptr(T), _ptr(thick), _ptr(noise), _ptr(target),
             ctypes.byref(loss), g.ctypes.data_as(c_void_p) if want_grad else None))
         return loss.value, g
 
     def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
         self._check(lib().tdgl_net_adam(self.h, lr, b1, b2, eps))
 
-    def train(self, idx, nb, T, thick, noise, target, lr, b1=0.9, b2=0.999, eps=1e-8):
-        """len(idx) / nb steps; idx: int32 device tensor of dataset rows."""
+    def train(self, idx, nb, T, thick, noise, target, lr, b1=0.9, b2=0.999, eps=1e-8, ops=None):
+        """len(idx) / nb steps; idx: int32 device tensor of dataset rows; ops:
+        int32 device tensor of the samples' symmetry ops (same length) or None."""
         nsteps = idx.numel() // nb
         losses = np.empty(nsteps, dtype=np.float64)
-        self._check(lib().tdgl_net_train(self.h, nsteps, nb, _ptr(idx), _ptr(T), _ptr(thick),
-                                         _ptr(noise), _ptr(target), lr, b1, b2, eps,
+        self._check(lib().tdgl_net_train(self.h, nsteps, nb, _ptr(idx), _ptr(ops), _ptr(T),
+                                         _ptr(thick), _ptr(noise), _ptr(target), lr, b1, b2, eps,
                                          losses.ctypes.data_as(c_void_p)))
         return losses
 

@@ -94,11 +94,15 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
     return out, steps, F, seconds, t_inst
 
 
-def train(net, rows, T, thick, noise, target, steps, batch, lr, seed=0, lr_final=None):
+def train(net, rows, T, thick, noise, target, steps, batch, lr, seed=0, lr_final=None,
+          augment=True):
     """Adam on minibatches drawn from `rows` (dataset row indices) with a
     seeded shuffle, `steps` steps of `batch` samples; the learning rate
     decays geometrically from lr to lr_final (default lr / 10) in 8 stages.
-    Returns the per-step losses and the seconds spent (GPU-synchronised)."""
+    With augment, every sample is drawn under a seeded random in-plane
+    symmetry op (the 8 mirrors and transposes of a square film; mirrors only
+    otherwise).  Returns the per-step losses and the seconds spent
+    (GPU-synchronised)."""
     import torch
     rng = np.random.Generator(np.random.PCG64(seed))
     rows = np.asarray(rows, dtype=np.int32)
@@ -106,6 +110,10 @@ def train(net, rows, T, thick, noise, target, steps, batch, lr, seed=0, lr_final
     while len(order) < steps * batch:
         order.extend(rng.permutation(rows).tolist())
     idx = torch.tensor(order[:steps * batch], dtype=torch.int32, device=T.device)
+    ops = None
+    if augment:
+        ops = torch.tensor(rng.integers(0, 8, size=steps * batch), dtype=torch.int32,
+                           device=T.device)
     lr_final = lr / 10 if lr_final is None else lr_final
     stages = 8
     per = (steps + stages - 1) // stages
@@ -117,7 +125,8 @@ def train(net, rows, T, thick, noise, target, steps, batch, lr, seed=0, lr_final
         if a >= b:
             break
         rate = lr * (lr_final / lr) ** (s / max(stages - 1, 1))
-        losses.extend(net.train(idx[a * batch:b * batch], batch, T, thick, noise, target, rate))
+        losses.extend(net.train(idx[a * batch:b * batch], batch, T, thick, noise, target, rate,
+                                ops=None if ops is None else ops[a * batch:b * batch]))
     torch.cuda.synchronize()
     return np.asarray(losses), time.perf_counter() - t0
 
@@ -134,7 +143,7 @@ def propose(net, rows, T, thick, noise, batch):
 
 def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_train, theta0,
                         width, data_steps, eval_steps, train_steps, batch, check=100, lr=1e-3,
-                        seed=0, profile=False, log=None, relaxed_only=True):
+                        seed=0, profile=False, log=None, relaxed_only=True, augment=True):
     """The learned proposal end to end.
 
     Rows 0..n_train-1 of the conditions (T, thick, noise: host arrays;
@@ -160,7 +169,8 @@ def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_tra
     try:
         net.set_params(theta0)
         rows = tr[s_tr > 0] if relaxed_only and (s_tr > 0).any() else tr
-        losses, t_train = train(net, rows, dT, dth, dn, target, train_steps, batch, lr, seed=seed)
+        losses, t_train = train(net, rows, dT, dth, dn, target, train_steps, batch, lr, seed=seed,
+                                augment=augment)
         if log:
             log("trained %d steps in %.1f s" % (train_steps, t_train))
         prof = net.profile(batch, dT, dth, dn, target, reps=5) if profile else None

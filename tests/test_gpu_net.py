@@ -266,3 +266,28 @@ def test_training_lowers_the_loss():
         net.close()
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.5 * losses[0], (losses[0], losses[-1])
+
+
+def test_symmetry_ops_in_the_loss_against_oracle():
+    """Samples under in-plane symmetry ops: the kernels read the noise field
+    and the target through the op; the oracle applies the op to the arrays."""
+    announce("net loss under symmetry ops")
+    from paper_2605_28800_amd.proposal import Net
+    width, shape, nd = 8, (8, 16, 16), 4
+    theta, T, th, noise, target = _net_problem(width, shape, nd, B=4, seed=17)
+    ops = np.array([0, 3, 5, 6], dtype=np.int32)
+    noise_op = np.stack([N.apply_op(noise[i], int(o)) for i, o in enumerate(ops)])
+    target_op = np.stack([N.apply_op(target[i], int(o)) for i, o in enumerate(ops)])
+    ol, oP, og = N.loss_and_grad(theta.astype(np.float64), width, T, th, noise_op, target_op,
+                                 shape, bf16=True)
+    net = Net(shape, width=width, noise_div=nd, max_batch=4)
+    try:
+        net.set_params(theta)
+        loss, g = net.loss_grad(_dev(T), _dev(th), _dev(noise), _dev(target),
+                                ops=_dev(ops, torch.int32))
+        loss0, _ = net.loss_grad(_dev(T), _dev(th), _dev(noise), _dev(target))
+    finally:
+        net.close()
+    assert abs(loss - ol) < 5e-3 * ol, (loss, ol)
+    assert _rel(g, og) < 1e-2, _rel(g, og)
+    assert abs(loss - loss0) > 1e-3 * loss0        # the ops do change the samples

@@ -176,3 +176,35 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(new, th - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_symmetry_ops_are_symmetries_of_the_film_model():
+    """The TDGL effective field of the open BaTiO3 box commutes with every
+    in-plane op (all terms, a film under vacuum), which pins the op's
+    position and component conventions."""
+    from oracle import tdgl_oracle as O
+    cfg = I.c5_recipe(3, (4, 6, 6))
+    cfg["T"] = 280.0
+    cfg["mimg"] = 0
+    prob = O.Problem(cfg)
+    P = _rng(21).uniform(-0.2, 0.2, size=(3, 4, 6, 6))
+    P[:, 3:] = 0.0
+    E = O.effective_field(P, prob)
+    scale = np.abs(E).max()
+    for op in range(8):
+        got = O.effective_field(N.apply_op(P, op), prob)
+        np.testing.assert_allclose(got, N.apply_op(E, op), rtol=0, atol=1e-12 * scale)
+
+
+def test_symmetry_op_group_structure():
+    F = _rng(22).normal(size=(2, 3, 2, 4, 4))
+    for op in range(8):
+        if op & 4 == 0:        # mirrors are involutions
+            np.testing.assert_array_equal(N.apply_op(N.apply_op(F, op), op), F)
+    np.testing.assert_array_equal(N.apply_op(N.apply_op(F, 4), 4), F)
+    # swap then both mirrors is a rotation by pi/2: four times is the identity
+    G = F
+    for _ in range(4):
+        G = N.apply_op(G, 5)
+    np.testing.assert_array_equal(G, F)
+    assert not np.array_equal(N.apply_op(F, 5), F)
