@@ -3,7 +3,7 @@
  *
  * A small 3-D convolutional encoder-decoder proposes the polarisation a TDGL
  * relaxation starts from; the TDGL step (tdgl.h) then relaxes from it and
- * remains the judge of the result.  The paper motivates this use of the
+ * decides the final state.  The paper motivates this use of the
  * solver (section 5: relaxed states it generates serve as datasets for
  * data-driven methods); the network itself is this library's addition.
  * It is trained on the GPU by this library's own forward and backward
