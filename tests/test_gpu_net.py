@@ -291,3 +291,39 @@ def test_symmetry_ops_in_the_loss_against_oracle():
     assert abs(loss - ol) < 5e-3 * ol, (loss, ol)
     assert _rel(g, og) < 1e-2, _rel(g, og)
     assert abs(loss - loss0) > 1e-3 * loss0        # the ops do change the samples
+
+
+def test_network_error_paths_leave_it_usable():
+    announce("net error paths")
+    import ctypes
+    import paper_2605_28800_amd as T
+    from paper_2605_28800_amd.proposal import Net
+    width, shape = 8, (4, 8, 8)
+    theta, Tk, th, noise, target = _net_problem(width, shape, 2, B=2, seed=23)
+    net = Net(shape, width=width, noise_div=2, max_batch=2)
+    try:
+        L = T.lib()
+        dT, dth, dn, dt = _dev(Tk), _dev(th), _dev(noise), _dev(target)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+        # Adam before any gradient
+        assert L.tdgl_net_adam(net.h, 1e-3, 0.9, 0.999, 1e-8) == T.TDGL_E_STATE
+        # batch above max_batch, zero steps, bad hyper-parameters, wrong count
+        assert L.tdgl_net_forward(net.h, 3, None, ptr(dT), ptr(dth), ptr(dn), None) == T.TDGL_E_ARG
+        idx = _dev(np.zeros(2, dtype=np.int32), torch.int32)
+        assert L.tdgl_net_train(net.h, 0, 2, ptr(idx), None, ptr(dT), ptr(dth), ptr(dn), ptr(dt),
+                                1e-3, 0.9, 0.999, 1e-8, None) == T.TDGL_E_ARG
+        assert L.tdgl_net_train(net.h, 1, 2, ptr(idx), None, ptr(dT), ptr(dth), ptr(dn), ptr(dt),
+                                -1.0, 0.9, 0.999, 1e-8, None) == T.TDGL_E_ARG
+        short = np.zeros(10, dtype=np.float32)
+        assert L.tdgl_net_set_params(net.h, short.ctypes.data_as(ctypes.c_void_p), 10) == T.TDGL_E_ARG
+        # still usable, and the profile leaves the parameters as they were
+        net.set_params(theta)
+        P = net.forward(dT, dth, dn)
+        assert torch.isfinite(P).all()
+        ms = net.profile(2, dT, dth, dn, dt, reps=2)
+        assert all(v > 0 for v in ms)
+        np.testing.assert_array_equal(net.get_params(), theta)
+        P2 = net.forward(dT, dth, dn)
+        assert torch.equal(P, P2)
+    finally:
+        net.close()
