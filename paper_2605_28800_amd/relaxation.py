@@ -125,8 +125,10 @@ def train(net, rows, T, thick, noise, target, steps, batch, lr, seed=0, lr_final
         if a >= b:
             break
         rate = lr * (lr_final / lr) ** (s / max(stages - 1, 1))
-        losses.extend(net.train(idx[a * batch:b * batch], batch, T, thick, noise, target, rate,
-                                ops=None if ops is None else ops[a * batch:b * batch]))
+        for c0 in range(a, b, 4096):          # tdgl_net_train takes at most 4096 steps a call
+            c1 = min(b, c0 + 4096)
+            losses.extend(net.train(idx[c0 * batch:c1 * batch], batch, T, thick, noise, target,
+                                    rate, ops=None if ops is None else ops[c0 * batch:c1 * batch]))
     torch.cuda.synchronize()
     return np.asarray(losses), time.perf_counter() - t0
 
