@@ -327,3 +327,37 @@ def test_network_error_paths_leave_it_usable():
         assert torch.equal(P, P2)
     finally:
         net.close()
+
+
+@pytest.mark.timeout(600)
+def test_network_forward_at_the_workload_size():
+    """One 64x64x16 sample through the width-32 network (the shapes, tiles
+    and kernels the learned-proposal workload runs) against the oracle.
+
+    At this size BF16 storage alone moves the output by ~9e-3 (relative L2)
+    from the exact FP64 function, and two BF16 computations whose FP32 sums
+    run in different orders flip different roundings, so they differ by
+    about half of that (measured 5.1e-3, uniform over tiles, rows, layers
+    and components).  The test therefore asks (1) the GPU to be within 1e-2
+    of the oracle's BF16 mode and (2) to be as far from the exact function
+    as the oracle's BF16 mode is, to 10 % -- an indexing or epilogue error
+    would add to (2).  The oracle's two forward passes take about two
+    minutes on the host."""
+    announce("net forward 64x64x16 width 32")
+    from paper_2605_28800_amd.proposal import Net
+    shape, width = (16, 64, 64), 32
+    T, th, noise = I.net_conditions(2, shape, 8, seed=31, thickness_range=(8, 16))
+    theta = I.net_params(width, seed=31)
+    net = Net(shape, width=width, noise_div=8, max_batch=2)
+    try:
+        net.set_params(theta)
+        P = net.forward(_dev(T), _dev(th), _dev(noise)).cpu().numpy()
+    finally:
+        net.close()
+    th64 = theta.astype(np.float64)
+    ref, _ = N.forward(th64, width, T[:1], th[:1], noise[:1], shape, bf16=True)
+    exact, _ = N.forward(th64, width, T[:1], th[:1], noise[:1], shape, bf16=False)
+    e_bf16 = _rel(ref, exact)
+    assert _rel(P[:1], ref) < 1e-2, _rel(P[:1], ref)
+    assert abs(_rel(P[:1], exact) - e_bf16) < 0.1 * e_bf16, (_rel(P[:1], exact), e_bf16)
+    assert not P[1, :, int(th[1]):].any()
