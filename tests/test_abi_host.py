@@ -258,3 +258,12 @@ def test_single_layer_entry_points_validate_before_launch():
     # too small a workspace
     assert L.tdgl_nn_conv3_wgrad(dummy, dummy, 0, 2, 4, 4, 3, 32, 64, dummy, 16, dummy,
                                  None) == T.TDGL_E_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
