@@ -93,8 +93,10 @@ class Problem:
         self.g12 = G["G12"] / self.G110
         self.gm = (G["G44"] - G["G44p"]) / self.G110
         self.tab = None
+        self.tensor_source = None
         if tensor and (self.terms & ELEC):
-            self.tab = offset_table(self.n, self.periodic, self.mimg, self.h)
+            self.tab, self.tensor_source = tensor_table(self.n, self.periodic, self.mimg, self.h,
+                                                        cfg.get("tensor_source", "auto"))
 
     def set_temperature(self, T: float):
         self._nb_cache = {}
@@ -312,15 +314,8 @@ def quad_tensor(R, h, n):
 
 
 def offset_table(n, periodic, mimg, h, k0_correction=True):
-    """N for every cell offset of the grid (see tensor_oracle.c for indexing),
-    then the k_parallel = 0 correction for in-plane periodic films.
-
-    Reading for periodic dimensions (the paper treats open samples only):
-    lattice images in a symmetric window; afterwards, per z-offset and
-    component, a constant is added so the in-plane sum takes its exact
-    infinite-lattice value: zz -> 1 at dz = 0 (an infinite uniformly polarised
-    sheet has E = -P_z/(eps0 epsB) inside and 0 outside), all others -> 0.
-    Fully periodic grids use the short-circuit value 0 for every sum."""
+    """N for every cell offset of the grid by the C quadrature (see
+    tensor_oracle.c for indexing), then the k_parallel = 0 correction."""
     pm = sum((1 << k) for k in range(3) if periodic[k])
     if pm not in (0, 3, 7):
         raise NotImplementedError("periodic mask %d" % pm)
@@ -332,7 +327,20 @@ def offset_table(n, periodic, mimg, h, k0_correction=True):
     out = np.zeros((6, K[2], K[1], K[0]))
     hh = np.asarray(h, float)
     _tensor_lib().orc_offset_table(N, pm, int(mimg), _dp(hh), _dp(t), _dp(w), _dp(out))
-    if k0_correction and pm == 3:
+    return k0_correct(out, n, periodic) if k0_correction else out
+
+
+def k0_correct(tab, n, periodic):
+    """Reading for periodic dimensions (the paper treats open samples only):
+    lattice images in a symmetric window; afterwards, per z-offset and
+    component, a constant is added so the in-plane sum takes its exact
+    infinite-lattice value: zz -> 1 at dz = 0 (an infinite uniformly polarised
+    sheet has E = -P_z/(eps0 epsB) inside and 0 outside), all others -> 0.
+    Fully periodic grids use the short-circuit value 0 for every sum."""
+    pm = sum((1 << k) for k in range(3) if periodic[k])
+    out = np.array(tab, dtype=np.float64)
+    K = out.shape[1:][::-1]
+    if pm == 3:
         nz = n[2]
         for q in range(6):
             for iz in range(K[2]):
@@ -340,10 +348,31 @@ def offset_table(n, periodic, mimg, h, k0_correction=True):
                 target = 1.0 if (q == 2 and dz == 0) else 0.0
                 S = out[q, iz].sum()
                 out[q, iz] += (target - S) / (n[0] * n[1])
-    elif k0_correction and pm == 7:
+    elif pm == 7:
         for q in range(6):
             out[q] -= out[q].sum() / (n[0] * n[1] * n[2])
     return out
+
+
+def tensor_table(n, periodic, mimg, h, source="auto"):
+    """The oracle's interaction-tensor table with the k_parallel = 0
+    correction, and where it came from.
+
+    "newell_mp": the Newell closed form in 40-digit arithmetic
+    (oracle/tensor_mp.py), stored for the parity-test grids under
+    tests/golden/tensor_mp/ by a script that calls only the oracle;
+    "quadrature": the C evaluation (tensor_oracle.c), pinned against the
+    40-digit tables.  "auto" takes the stored table when one matches the
+    geometry exactly and the quadrature otherwise (large image windows)."""
+    from . import tensor_tables
+    if source in ("auto", "newell_mp"):
+        tab = tensor_tables.lookup(n, periodic, mimg, h)
+        if tab is not None:
+            return k0_correct(tab, n, periodic), "newell_mp"
+        if source == "newell_mp":
+            raise KeyError("no stored 40-digit table for n=%s periodic=%s mimg=%d"
+                           % (tuple(n), tuple(periodic), mimg))
+    return offset_table(n, periodic, mimg, h), "quadrature"
 
 
 _PAIRS = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (1, 0): 3,
@@ -558,3 +587,25 @@ def energies(P, prob: Problem, terms=None):
     ncell = mat.sum() * prob.n[0] * prob.n[1]
     F["meanP"] = P[:, mat].reshape(3, -1).sum(axis=1) / max(ncell, 1)
     return F
+
+
+# --------------------------------------------------------------------------
+# SI entry points (Table 2 in reverse): P in C/m^2, fields in V/m, energies
+# in J.  The reduced functions above work in units of P0, alpha_ref and l0.
+# --------------------------------------------------------------------------
+def run_si(P_si, prob: Problem, scheme: str, dtau: float, nsteps: int):
+    """run() on an SI state; returns the SI state."""
+    return prob.P0 * run(prob.to_reduced_P(P_si), prob, scheme, dtau, nsteps)
+
+
+def field_si(P_si, prob: Problem, terms=None):
+    """E_eff of an SI state in V/m."""
+    return effective_field(prob.to_reduced_P(P_si), prob, terms) * prob.field_scale
+
+
+def energies_si(P_si, prob: Problem, terms=None):
+    """energies() of an SI state: F terms in J, meanP in C/m^2."""
+    F = energies(prob.to_reduced_P(P_si), prob, terms)
+    out = {k: v * prob.energy_scale for k, v in F.items() if k != "meanP"}
+    out["meanP"] = F["meanP"] * prob.P0
+    return out

@@ -25,10 +25,15 @@ namespace {
 
 constexpr double EPS0 = 8.8541878128e-12;   // F/m (CODATA 2018)
 
+// A captured chunk of steps bakes in everything its launches take by value:
+// the buffer parity, scheme, term mask and whether the cross-term kernel
+// runs (device-side scalars such as dtau, E_ext and the coefficients are
+// read at run time and need no new capture).
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     int cur = 0, scheme = 0, chunk = 0;
-    unsigned elec = 0;
+    unsigned terms = 0;
+    bool cross = false;
     int hpos = 0;                 // multistep history phase at the chunk start
 };
 
@@ -523,11 +528,11 @@ hipError_t enq_step(tdgl_ctx *c, int *cur, hipStream_t s)
 
 tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
 {
-    const unsigned el = elec_on(c) ? 1u : 0u;
+    const bool cross = cross_terms(c) && (c->terms & TDGL_GRAD) && c->xbuf;
     const int hpos = c->scheme == TDGL_AB3M2 ? c->hist_pos : 0;
     for (auto &e : c->graphs)
-        if (e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk && e.elec == el &&
-            e.hpos == hpos) {
+        if (e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk &&
+            e.terms == c->terms && e.cross == cross && e.hpos == hpos) {
             *out = e.exec;
             return TDGL_OK;
         }
@@ -555,7 +560,8 @@ tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
     ge.cur = c->cur;
     ge.scheme = c->scheme;
     ge.chunk = chunk;
-    ge.elec = el;
+    ge.terms = c->terms;
+    ge.cross = cross;
     ge.hpos = hpos;
     c->graphs.push_back(ge);
     *out = exec;

@@ -66,11 +66,13 @@ def test_field_parity(case, prec, path):
 @pytest.mark.parametrize("case", ["open_16x16x8", "open_ragged_12x10x5", "film_16x16x4",
                                   "bulk_8x16x8"])
 def test_tensor_spectrum_parity(case):
-    """The device-built FP64 tensor spectrum equals the oracle's table,
-    transformed with numpy, on the stored octant."""
+    """The device-built FP64 tensor spectrum equals the oracle's table (the
+    Newell closed form in 40-digit arithmetic, a method the library does not
+    use), transformed with numpy, on the stored octant."""
     cfg = _cfg(**CASES[case])
     announce("tensor spectrum %s" % case)
     prob = O.Problem(cfg)
+    assert prob.tensor_source == "newell_mp"      # 40-digit closed form, stored
     ctx = gpu_context(cfg, "f64")
     try:
         got = T.tdgl_get_tensor_spectrum(ctx.ctx)
@@ -247,3 +249,48 @@ def test_rk45_fp32_film_relaxes():
         ctx.close()
     assert tau > 30 * cfg["dtau"] and h > 0
     assert np.all(np.diff(F) < 0), F
+
+
+@pytest.mark.parametrize("case", ["open_10x12x6", "film_16x16x4"])
+def test_parity_at_P0_other_than_one(case):
+    """P0 = 0.3016 C/m^2: the SI fields, energies (J) and trajectory of the
+    library against the oracle's SI entry points (FP64), plus the joule value
+    of a uniform tetragonal box (Landau term only), f(P_s) V with
+    f(P_s) = -2.313340e6 J/m^3 from Table 1 at 300 K."""
+    spec = dict(open_10x12x6=dict(n=(10, 12, 6), periodic=(0, 0, 0)),
+                film_16x16x4=dict(n=(16, 16, 4), periodic=(1, 1, 0)))[case]
+    cfg = _cfg(**spec)
+    cfg["scales"] = dict(cfg["scales"], P0=0.3016)
+    announce("P0 = 0.3016 parity %s" % case)
+    P = I.initial_P(cfg, 4)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64")
+    try:
+        ctx.set_P(P)
+        for mask in MASKS:
+            got = ctx.eval_field(mask).cpu().numpy()
+            assert rel_inf(got, O.field_si(P, prob, mask)) <= 1e-13, mask
+        F, m = ctx.energies()
+        ref = O.energies_si(P, prob)
+        for k, key in enumerate(("F_land", "F_grad", "F_elec", "F_ext")):
+            assert abs(F[k] - ref[key]) <= 1e-12 * abs(ref["F_land"]), (key, F[k], ref[key])
+        assert np.abs(np.array(m) - ref["meanP"]).max() <= 1e-14
+        ctx.step(50)
+        got = ctx.get_P(T.TDGL_FP64)
+    finally:
+        ctx.close()
+    want = O.run_si(P, prob, "heun", cfg["dtau"], 50)
+    assert np.abs(got - want).max() / ps_of(cfg) <= 1e-12
+    # joules of a uniform tetragonal box, Landau only
+    cfg["terms"] = T.TDGL_LANDAU
+    Pu = np.zeros_like(P)
+    Pu[2] = 0.2649101
+    ctx = gpu_context(cfg, "f64")
+    try:
+        ctx.set_P(Pu)
+        F, _ = ctx.energies()
+    finally:
+        ctx.close()
+    V = np.prod(spec["n"]) * 1e-27
+    assert abs(F[0] / (-2.313340e6 * V) - 1) < 2e-6
+    assert abs(F[0] / O.energies_si(Pu, O.Problem(cfg))["F_land"] - 1) < 1e-12

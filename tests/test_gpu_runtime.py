@@ -212,3 +212,42 @@ def test_ab3m2_split_steps_bitwise():
     finally:
         ctx.close()
     assert np.array_equal(whole, split)
+
+
+def test_graph_cache_follows_term_and_gradient_changes():
+    """Captured step chunks take the term mask and the cross-term kernel by
+    value: turning the Landau term off, then switching on the gradient cross
+    terms of eq 4 (G12 != 0, G44 != G44') between tdgl_step calls must change
+    the physics of the graphed chunks as well (FP64 against the oracle)."""
+    cfg = I.config("c2_small")
+    cfg["n"] = (16, 16, 4)
+    cfg["layers"] = [0] * 4
+    announce("graph cache vs set_terms / set_gradient, FP64 16x16x4 film")
+    P0 = I.initial_P(cfg, 3)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64", chunk=64)
+    try:
+        ctx.set_P(P0)
+        ctx.step(128)
+        T.tdgl_set_terms(ctx.ctx, T.TDGL_ALL & ~T.TDGL_LANDAU)
+        ctx.step(128)
+        T.tdgl_set_terms(ctx.ctx, T.TDGL_ALL)
+        G = cfg["gradient"]
+        T.tdgl_set_gradient(ctx.ctx, G["G11"], -0.3 * G["G11"], G["G44"], 0.2 * G["G44"])
+        ctx.step(128)
+        got = ctx.get_P(T.TDGL_FP64)
+    finally:
+        ctx.close()
+    ref = O.run(P0, prob, "heun", cfg["dtau"], 128)
+    prob.terms = T.TDGL_ALL & ~T.TDGL_LANDAU
+    ref = O.run(ref, prob, "heun", cfg["dtau"], 128)
+    prob.terms = T.TDGL_ALL
+    prob.g12 = -0.3 * G["G11"] / prob.G110
+    prob.gm = (G["G44"] - 0.2 * G["G44"]) / prob.G110
+    for i in range(3):
+        for d in range(3):
+            prob.g[i, d] = (G["G11"] if i == d else 1.2 * G["G44"]) / prob.G110
+    ref = O.run(ref, prob, "heun", cfg["dtau"], 128)
+    err = np.abs(got - ref).max() / ps_of(cfg)
+    print("max |dP|/Ps = %.3e" % err)
+    assert err < 1e-12, err
