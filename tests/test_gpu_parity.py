@@ -261,6 +261,7 @@ def test_parity_at_P0_other_than_one(case):
                 film_16x16x4=dict(n=(16, 16, 4), periodic=(1, 1, 0)))[case]
     cfg = _cfg(**spec)
     cfg["scales"] = dict(cfg["scales"], P0=0.3016)
+    cfg["scheme"] = "heun"
     announce("P0 = 0.3016 parity %s" % case)
     P = I.initial_P(cfg, 4)
     prob = O.Problem(cfg)
@@ -279,7 +280,7 @@ def test_parity_at_P0_other_than_one(case):
         got = ctx.get_P(T.TDGL_FP64)
     finally:
         ctx.close()
-    want = O.run_si(P, prob, "heun", cfg["dtau"], 50)
+    want = O.run_si(P, prob, cfg["scheme"], cfg["dtau"], 50)
     assert np.abs(got - want).max() / ps_of(cfg) <= 1e-12
     # joules of a uniform tetragonal box, Landau only
     cfg["terms"] = T.TDGL_LANDAU
