@@ -276,6 +276,31 @@ tdgl_status tdgl_energies(tdgl_ctx *ctx, double F[5], double meanP[3]);
  * memory). */
 tdgl_status tdgl_energies_batch(tdgl_ctx *ctx, double *F, double *meanP);
 
+/* Allocation-free variant of tdgl_energies_batch, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Enqueues the energy evaluation
+ * of every instance on the context's stream and writes out_dev[nbatch][8]
+ * in device memory (caller-owned, 8-byte aligned): F_Land, F_Grad, F_Elec,
+ * F_Ext, F total (J), mean P x, y, z over material cells (C/m^2) -- the
+ * same values, bit for bit, as tdgl_energies_batch.  Asynchronous: nothing
+ * waits for the stream and the non-finite flag is not read.
+ * Scratch: the per-work-group partial sums go to a fixed device array of
+ * TDGL_NOALLOC_SCRATCH_BYTES per device, which the library holds from the
+ * first call on that device until the process ends; the call needs
+ * 64 * nbatch * nz * ceil(ny / rows) bytes of it (rows: the update tile,
+ * tdgl_set_update_rows) and fails with TDGL_E_UNSUPPORTED, before enqueuing
+ * anything, when that exceeds the limit.  Every call on a device shares that
+ * device's array: calls that overlap on one device (different streams, or
+ * concurrent threads) race and give wrong results; calls on one stream are
+ * ordered and safe.  Nothing of a previous call is reused.
+ * Needs P to be set (the context's own buffers exist then: this call never
+ * allocates them).  Model changes since the last step are uploaded first,
+ * which waits for the stream; under capture, make them before capturing.
+ * TDGL_E_STATE if the gradient cross terms were switched on since the last
+ * step (their buffer would have to be allocated). */
+#define TDGL_NOALLOC_SCRATCH_BYTES (1u << 20)
+tdgl_status tdgl_energies_noalloc(tdgl_ctx *ctx, double *out_dev);
+
 /* Quasi-static field sweep (the paper drives samples with a time-dependent
  * external field, section 3, and traces P against E in section 4.4): for
  * each of the nvalues applied fields e[i][3] (V/m, host memory) in turn,

@@ -63,6 +63,7 @@ _SIGS = {
     "tdgl_get_dims": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_workspace_size": ([_ctx_p, ctypes.POINTER(c_size_t)], c_int),
     "tdgl_bind_workspace": ([_ctx_p, c_void_p, c_size_t], c_int),
+    "tdgl_energies_noalloc": ([_ctx_p, c_void_p], c_int),
     "tdgl_set_scales": ([_ctx_p, c_double, c_double, c_double, c_double], c_int),
     "tdgl_set_material": ([_ctx_p, c_int, ctypes.POINTER(tdgl_material)], c_int),
     "tdgl_set_layer_materials": ([_ctx_p, ctypes.POINTER(ctypes.c_byte)], c_int),
@@ -287,6 +288,13 @@ def tdgl_energies(ctx):
     m = (c_double * 3)()
     _check(ctx, lib().tdgl_energies(ctx, F, m))
     return tuple(F), tuple(m)
+
+
+def tdgl_energies_noalloc(ctx, out_dev_ptr: int):
+    """Enqueue the energies of every instance into device memory
+    out_dev_ptr ([nbatch][8] float64: F_Land, F_Grad, F_Elec, F_Ext, F in J,
+    mean P in C/m^2) without allocating; asynchronous."""
+    _check(ctx, lib().tdgl_energies_noalloc(ctx, out_dev_ptr))
 
 
 def tdgl_energies_batch(ctx):

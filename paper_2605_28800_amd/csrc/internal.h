@@ -90,6 +90,13 @@ hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a,
 int update_rows_per_block(int prec, const Geom &g);
 hipError_t launch_reduce_partials(const double *partials, int n, int nb, double *out,
                                   hipStream_t s);
+// final energies [nb][8] (J and C/m^2, as tdgl_energies_batch) from the partials
+hipError_t launch_reduce_energies(const double *partials, int n, int nb, double joule,
+                                  double ncell, double P0, double *out, hipStream_t s);
+// fixed device scratch of the allocation-free entry point: SCRATCH_DOUBLES
+// doubles per device; *out = this device's address (current device)
+constexpr size_t SCRATCH_DOUBLES = 131072;        // 1 MiB
+hipError_t scratch_address(double **out);
 hipError_t launch_convert(int src_prec, const void *src, int dst_prec, void *dst, size_t n,
                           double scale, hipStream_t s);
 hipError_t launch_zero_layers(int prec, void *P, const void *coef, const Geom &g, hipStream_t s);

@@ -419,7 +419,8 @@ hipError_t enq_cross(tdgl_ctx *c, const void *Pin, unsigned terms, UpdArgs &a, h
 }
 
 hipError_t enq_upd(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
-                   int stage, unsigned terms, bool elec_in, bool fx_out, hipStream_t s)
+                   int stage, unsigned terms, bool elec_in, bool fx_out, hipStream_t s,
+                   double *partials = nullptr)
 {
     UpdArgs a{};
     hipError_t ce = enq_cross(c, Pin, terms, a, s);
@@ -430,7 +431,7 @@ hipError_t enq_upd(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, voi
     a.S1 = c->S1;
     a.coef = c->coef;
     a.kp = c->kp;
-    a.partials = c->partials;
+    a.partials = partials ? partials : c->partials;
     a.flag = c->flag;
     a.stage = stage;
     a.terms = terms;
@@ -441,13 +442,14 @@ hipError_t enq_upd(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, voi
 }
 
 hipError_t enq_eval(tdgl_ctx *c, int mode, const void *Pin, const void *Pold, void *Pout,
-                    int stage, unsigned terms, bool elec, bool fx_out, hipStream_t s)
+                    int stage, unsigned terms, bool elec, bool fx_out, hipStream_t s,
+                    double *partials = nullptr)
 {
     if (elec) {
         hipError_t e = enq_yz(c, s);
         if (e != hipSuccess) return e;
     }
-    return enq_upd(c, mode, Pin, Pold, Pout, stage, terms, elec, fx_out, s);
+    return enq_upd(c, mode, Pin, Pold, Pout, stage, terms, elec, fx_out, s, partials);
 }
 
 // multistep history buffer k (0..2)
@@ -1200,6 +1202,47 @@ tdgl_status tdgl_energies_batch(tdgl_ctx *c, double *F, double *meanP)
     if (!c) return TDGL_E_ARG;
     if (!F || !meanP) return fail(c, TDGL_E_ARG, "null output");
     return energies_all(c, F, meanP);
+}
+
+tdgl_status tdgl_energies_noalloc(tdgl_ctx *c, double *out_dev)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!out_dev) return fail(c, TDGL_E_ARG, "null output");
+    // every buffer but the scratch must already exist: no call below allocates
+    if (!c->P_set || !c->dev_init) return fail(c, TDGL_E_STATE, "P has not been set");
+    const bool el = elec_on(c);
+    if (el && !c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
+    if (c->params_dirty) {
+        tdgl_status st = check_model(c);
+        if (st != TDGL_OK) return st;
+        if (cross_terms(c) && !c->xbuf)
+            return fail(c, TDGL_E_STATE,
+                        "gradient cross terms were switched on: their field buffer is made by "
+                        "the next tdgl_step or tdgl_energies, not here");
+    }
+    const int ngroups = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
+    const size_t need = (size_t)ngroups * c->g.nb * 8;
+    if (need > SCRATCH_DOUBLES)
+        return fail(c, TDGL_E_UNSUPPORTED,
+                    "energy partials need %zu doubles; the fixed scratch holds %zu "
+                    "(use tdgl_energies_batch)", need, (size_t)SCRATCH_DOUBLES);
+    double *scr = nullptr;
+    HIP_TRY(c, scratch_address(&scr));
+    tdgl_status st = upload_params(c);      // no allocation: device state and xbuf exist
+    if (st != TDGL_OK) return st;
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    HIP_TRY(c, enq_eval(c, UPD_ENERGY, c->P[c->cur], nullptr, nullptr, 0, c->terms, el, false,
+                        c->stream, scr));
+    if (el) c->spec_valid = false;
+    std::vector<double> coef;
+    double scal[8], gh2[3][3];
+    reduced(c, coef, scal, gh2);
+    long long nmat = 0;
+    for (int z = 0; z < c->g.nz; ++z)
+        if (c->layer[z] >= 0) nmat += (long long)c->g.nx * c->g.ny;
+    HIP_TRY(c, launch_reduce_energies(scr, ngroups, c->g.nb, scal[4] * scal[5], (double)nmat,
+                                      c->P0, out_dev, c->stream));
+    return TDGL_OK;
 }
 
 tdgl_status tdgl_get_reduced(const tdgl_ctx *c, double *coef, double scal[8])

@@ -18,6 +18,8 @@
 //      complex points per row, split into the half spectrum), written over
 //      the spectra rows read in step 1, so the next field evaluation starts
 //      at the y pass.
+#include <mutex>
+
 #include "fft_core.h"
 #include "internal.h"
 
@@ -706,6 +708,82 @@ hipError_t launch_reduce_partials(const double *partials, int n, int nb, double 
 {
     hipLaunchKernelGGL(k_reduce_partials, dim3(nb), dim3(256), 0, s, partials, n, out);
     return hipGetLastError();
+}
+
+// Energies in their final units on the device: instance b = blockIdx.x sums
+// its n partials (as k_reduce_partials) and writes out[b*8 ..]: the four
+// terms times joule (J per reduced unit), their total, and the three
+// polarisation sums / ncell * P0.  The products and the sum are evaluated
+// exactly as the host does it for tdgl_energies (no contraction), so both
+// give the same bits.
+__global__ void k_reduce_energies(const double *__restrict__ part, int n, double joule,
+                                  double ncell, double P0, double *out)
+{
+#pragma clang fp contract(off)
+    __shared__ double red[256];
+    __shared__ double tot[8];
+    const int tid = threadIdx.x;
+    part += (long long)blockIdx.x * n * 8;
+    out += blockIdx.x * 8;
+    for (int k = 0; k < 8; ++k) {
+        double s = 0.0;
+        for (int i = tid; i < n; i += 256) s += part[(long long)i * 8 + k];
+        red[tid] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) tot[k] = red[0];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double F[4];
+        for (int k = 0; k < 4; ++k) F[k] = tot[k] * joule;
+        for (int k = 0; k < 4; ++k) out[k] = F[k];
+        out[4] = F[0] + F[1] + F[2] + F[3];
+        for (int k = 0; k < 3; ++k) out[5 + k] = ncell > 0.0 ? tot[4 + k] / ncell * P0 : 0.0;
+    }
+}
+
+hipError_t launch_reduce_energies(const double *partials, int n, int nb, double joule,
+                                  double ncell, double P0, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_energies, dim3(nb), dim3(256), 0, s, partials, n, joule, ncell,
+                       P0, out);
+    return hipGetLastError();
+}
+
+// Fixed device scratch of the allocation-free energy entry point (energy
+// partials of every work-group and instance).  Each device holds its own
+// copy for the life of the process.  In host code the name below is not a
+// device address: the address of this device's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+void *scratch_addr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t scratch_address(double **out)
+{
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_addr[dev] = p;
+    }
+    *out = static_cast<double *>(scratch_addr[dev]);
+    return hipSuccess;
 }
 
 // dst = scale * src, with a precision change if asked (multiply in double)
