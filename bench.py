@@ -73,7 +73,7 @@ def source_hash():
 
 
 def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0, chunk=None,
-            kernel_reps=0):
+            kernel_reps=0, windows=1):
     import numpy as np
     import torch
 
@@ -95,15 +95,22 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0, ch
     ctx.step(warmup)
     ctx.sync()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.step(steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ctx.sync()
-    ms = ev0.elapsed_time(ev1)
+    # `windows` timed windows of `steps` steps each, back to back from the
+    # evolving state; the figure is the median window
+    win_ms, walls = [], []
+    for _ in range(windows):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev0.record(stream)
+        ctx.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - w0)
+        ctx.sync()
+        win_ms.append(ev0.elapsed_time(ev1))
+    ms = float(np.median(win_ms))
+    wall = float(np.median(walls))
     prof = T.tdgl_profile_step(ctx.ctx, profile_steps) if profile_steps else None
     kprof = T.tdgl_profile_kernels(ctx.ctx, kernel_reps) if kernel_reps else None
     F, meanP = ctx.energies()
@@ -111,7 +118,7 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0, ch
     fused = T.tdgl_get_fft_path(ctx.ctx)
     ctx.close()
     return dict(ms=ms, wall=wall, setup_s=setup_s, prof=prof, kprof=kprof, dims=dims, F=F,
-                meanP=meanP, fused=fused)
+                meanP=meanP, fused=fused, window_ms=win_ms)
 
 
 def copy_calibration(mib=256, reps=3):
@@ -389,30 +396,79 @@ def run_c4(args, names=("y_forward", "z_tensor", "y_inverse", "update_predictor"
     return c4
 
 
-def cpu_baseline(cfg, nsteps):
-    """The oracle as it stands, timed on the host on a few Heun steps of the
-    same grid.  Its interaction table is built with mimg = 0 (the cost of a
-    step does not depend on the number of images); set-up is not timed."""
+def _one_thread():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    os.environ["MKL_NUM_THREADS"] = "1"
+
+
+def _oracle_run(name, nsteps, seed=0):
+    """The oracle as it stands on `nsteps` steps of the named recipe (its
+    own scheme); returns (cell-steps, start, end) of the timed loop (set-up
+    and one first step excluded).  The periodic film's interaction table is
+    built with mimg = 0: the cost of a step does not depend on the images."""
     import numpy as np
 
     import tdgl_inputs as I
     from oracle import tdgl_oracle as O
-    c = dict(cfg)
-    c["mimg"] = 0
-    prob = O.Problem(c)
-    P = I.initial_P(c, 0).astype(np.float64)
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):            # BLAS / OpenMP pools: one thread
-        P = O.step_heun(P, prob, c["dtau"])      # first call outside the timing
-        t0 = time.perf_counter()
+    c = I.config(name)
+    if c["periodic"][0]:
+        c["mimg"] = 0
+    prob = O.Problem(c)
+    P = I.initial_P(c, seed).astype(np.float64)
+    step = O.step_euler if c["scheme"] == "euler" else O.step_heun
+    with threadpool_limits(limits=1):
+        P = step(P, prob, c["dtau"])
+        t0 = time.time()
         for _ in range(nsteps):
-            P = O.step_heun(P, prob, c["dtau"])
-        dt = time.perf_counter() - t0
-    ncell = int(np.prod(c["n"]))
-    return dict(value=ncell * nsteps / dt, unit="cell-steps/s", cores=1, kind="oracle",
-                sample="%d Heun steps of the %dx%dx%d film (numpy FP64, single thread; "
-                       "setup excluded), %.1f s" % (nsteps, *c["n"], dt),
-                host_cpus=os.cpu_count())
+            P = step(P, prob, c["dtau"])
+        t1 = time.time()
+    return int(np.prod(c["n"])) * nsteps, t0, t1
+
+
+def _oracle_worker(a):
+    return _oracle_run(*a)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(nsteps, cores):
+    """The FP64 oracle timed on the host (never tuned for this): the metric's
+    film on a bounded sample, single-threaded and as `cores` concurrent
+    processes on their own copies (aggregate cell-steps/s over the span of
+    the timed loops), plus the small box of 1000 Euler steps and the bilayer
+    downscale, single-threaded.  Runs before anything touches the GPU (the
+    workers are fresh interpreters)."""
+    import multiprocessing as mp
+    _one_thread()
+    n, t0, t1 = _oracle_run("c2", nsteps)
+    one = n / (t1 - t0)
+    allc = None
+    if cores > 1:
+        with mp.get_context("spawn").Pool(cores, initializer=_one_thread) as pool:
+            res = pool.map(_oracle_worker, [("c2", nsteps, s) for s in range(cores)])
+        span = max(r[2] for r in res) - min(r[1] for r in res)
+        allc = sum(r[0] for r in res) / span
+    n1, a1, b1 = _oracle_run("c1", 1000)
+    n4, a4, b4 = _oracle_run("c4_small", 100)
+    return dict(
+        value=allc if allc is not None else one, unit="cell-steps/s",
+        cores=cores if allc is not None else 1, kind="oracle",
+        sample="%d Heun steps of the 128x128x32 film per process (numpy FP64, one thread "
+               "each, %d processes on their own copies; set-up excluded)" % (nsteps, cores),
+        one_thread=one, one_thread_s=round(t1 - t0, 2),
+        c1_1000_euler_one_thread=n1 / (b1 - a1), c1_s=round(b1 - a1, 2),
+        c4_32x32x8_100_heun_one_thread=n4 / (b4 - a4), c4_s=round(b4 - a4, 2),
+        cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
 
 def main():
@@ -422,7 +478,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--fp64-steps", type=int, default=2000)
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=6,
+                    help="Heun steps of the film per oracle process in the CPU baseline")
+    ap.add_argument("--cpu-cores", type=int, default=min(16, os.cpu_count() or 1),
+                    help="concurrent oracle processes of the CPU baseline")
+    ap.add_argument("--windows", type=int, default=5,
+                    help="timed windows of --steps steps; the headline is their median")
     ap.add_argument("--c4-steps", type=int, default=200,
                     help="FP32 Heun steps of the 256x256x64 open bilayer (0: skip)")
     ap.add_argument("--c4-loop-values", type=int, default=0,
@@ -496,11 +557,20 @@ def main():
             flush=True)
         return
 
+    cpu = None
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        # first, before anything touches the GPU: its workers are new processes
+        log("cpu baseline: oracle, %d Heun steps x %d processes" % (args.cpu_steps, args.cpu_cores))
+        cpu = cpu_baseline(args.cpu_steps, args.cpu_cores)
+        log("cpu: %.3e cell-steps/s on %d cores, %.3e on one" % (cpu["value"], cpu["cores"],
+                                                                cpu["one_thread"]))
+
     cfg = I.config("c2")
     ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
-    log("fp32 run: %d warmup + %d timed Heun steps" % (args.warmup, args.steps))
+    log("fp32 run: %d warmup + %d x %d timed Heun steps" % (args.warmup, args.windows, args.steps))
     r32 = run_gpu(cfg, T.TDGL_FP32, args.steps, args.warmup, args.profile_steps,
-                  args.fft_path, args.rows, args.graph_chunk, args.kernel_reps)
+                  args.fft_path, args.rows, args.graph_chunk, args.kernel_reps,
+                  windows=max(1, args.windows))
     ms_step = r32["ms"] / args.steps
     value = ncell * args.steps / (r32["ms"] / 1e3)
     log("fp32: %.4f ms/step, %.3e cell-steps/s (wall %.3f s, setup %.2f s, fused=%d)"
@@ -587,12 +657,6 @@ def main():
         c5 = run_c5(args.c5_train, args.c5_test, args.c5_data_steps, args.c5_eval_steps,
                     args.c5_train_steps, args.c5_batch, args.c5_width, augment=args.c5_augment)
 
-    cpu = None
-    if not args.no_cpu_baseline and args.cpu_steps > 0:
-        log("cpu baseline: oracle, %d Heun steps" % args.cpu_steps)
-        cpu = cpu_baseline(cfg, args.cpu_steps)
-        log("cpu: %.3e cell-steps/s" % cpu["value"])
-
     out = {
         "metric": "TDGL cell-steps/s (FP32 vs FP64) + batched time-to-relaxed vs plain, 1 GPU",
         "value": value,
@@ -606,9 +670,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "BaTiO3 film 128x128x32, periodic x,y / open z (padded 64), "
-                               "180-degree wall + 1% noise, all terms, Heun dtau=1e-3, "
-                               "mimg=16",
+        "config": {"workload": "BaTiO3 film 128x128x32 periodic x,y open z, 180-deg wall, "
+                               "all terms, FP32 Heun dtau=1e-3, mimg=16",
                    "grid": list(cfg["n"]), "padded": list(r32["dims"][3:6]),
                    "precision": "fp32 field / fp64 tensor and energies", "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -626,6 +689,7 @@ def main():
                           "frac": round(value * step_bytes / (HBM_PEAK_GBS * 1e9), 4),
                           "note": "whole step vs an HBM model of a 5-pass design"},
         "energies_J": list(r32["F"]),
+        "windows_ms": [round(w, 4) for w in r32["window_ms"]],
     }
     print(json.dumps(out), flush=True)
 

@@ -221,7 +221,10 @@ tdgl_status tdgl_set_rk_tolerances(tdgl_ctx *ctx, double atol, double rtol);
 tdgl_status tdgl_get_rk_state(const tdgl_ctx *ctx, double *tau, double *h, long long *rejected);
 
 /* Number of steps captured per HIP graph by tdgl_step (default 64; 0 runs
- * plain stream launches). */
+ * plain stream launches).  tdgl_step(n) launches n / steps graphs of that
+ * chunk and the remainder as one graph of its own length; instantiated
+ * graphs are cached per length and launch configuration (the cache is
+ * emptied when it holds 32 graphs and a new remainder length comes). */
 tdgl_status tdgl_set_graph_chunk(tdgl_ctx *ctx, int steps);
 
 /* FFT pass layout: path 0 (default) fuses the y pass, the z pass with the

@@ -1102,17 +1102,19 @@ tdgl_status tdgl_step(tdgl_ctx *c, long long nsteps)
         for (; left > 0 && c->hist_count < 2; --left)      // start-up steps, plain launches
             HIP_TRY(c, enq_step_ms(c, c->cur, &c->hist_count, &c->hist_pos, c->stream));
     }
-    int chunk = c->graph_chunk;
-    if (c->scheme == TDGL_EULER && (chunk & 1)) chunk -= 1;
-    if (chunk > 0) {
-        while (left >= chunk) {
-            hipGraphExec_t exec = nullptr;
-            st = get_graph(c, chunk, &exec);
-            if (st != TDGL_OK) return st;
-            HIP_TRY(c, hipGraphLaunch(exec, c->stream));
-            if (ms) c->hist_pos = (c->hist_pos + chunk) % 3;
-            left -= chunk;
-        }
+    // whole chunks, then the remainder as one graph of its own length (graphs
+    // are cached per length; an odd Euler graph flips the buffer parity)
+    const int chunk = c->graph_chunk;
+    while (chunk > 0 && left > 0) {
+        const int len = left >= chunk ? chunk : (int)left;
+        if (len != chunk && c->graphs.size() >= 32) drop_graphs(c);   // bound the cache
+        hipGraphExec_t exec = nullptr;
+        st = get_graph(c, len, &exec);
+        if (st != TDGL_OK) return st;
+        HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+        if (ms) c->hist_pos = (c->hist_pos + len) % 3;
+        if (c->scheme == TDGL_EULER && (len & 1)) c->cur = 1 - c->cur;
+        left -= len;
     }
     for (; left > 0; --left) {
         if (ms) {
