@@ -126,14 +126,15 @@ class Problem:
 def landau_energy_density(P, coef):
     """f_L* of eq 3 at every cell.  coef: [nz, 8] broadcast along z."""
     a1x, a1y, a1z, a11, a12, a111, a112, a123 = [coef[:, k][:, None, None] for k in range(8)]
-    Px, Py, Pz = P
-    return (a1x * Px**2 + a1y * Py**2 + a1z * Pz**2
-            + a11 * (Px**4 + Py**4 + Pz**4)
-            + a12 * (Px**2 * Py**2 + Py**2 * Pz**2 + Pz**2 * Px**2)
-            + a111 * (Px**6 + Py**6 + Pz**6)
-            + a112 * (Px**4 * (Py**2 + Pz**2) + Py**4 * (Px**2 + Pz**2)
-                      + Pz**4 * (Px**2 + Py**2))
-            + a123 * Px**2 * Py**2 * Pz**2)
+    # powers of the squares, written as products (numpy's general power
+    # routine is many times slower than a multiplication)
+    x, y, z = P[0] * P[0], P[1] * P[1], P[2] * P[2]          # Px^2, Py^2, Pz^2
+    return (a1x * x + a1y * y + a1z * z
+            + a11 * (x * x + y * y + z * z)
+            + a12 * (x * y + y * z + z * x)
+            + a111 * (x * x * x + y * y * y + z * z * z)
+            + a112 * (x * x * (y + z) + y * y * (x + z) + z * z * (x + y))
+            + a123 * x * y * z)
 
 
 def landau_field(P, coef):
@@ -143,13 +144,14 @@ def landau_field(P, coef):
     H = np.empty_like(P)
     for i in range(3):
         j, k = (i + 1) % 3, (i + 2) % 3
-        Pi, Pj, Pk = P[i], P[j], P[k]
-        dfdPi = (2 * a1[i] * Pi
-                 + 4 * a11 * Pi**3
-                 + 2 * a12 * Pi * (Pj**2 + Pk**2)
-                 + 6 * a111 * Pi**5
-                 + a112 * (4 * Pi**3 * (Pj**2 + Pk**2) + 2 * Pi * (Pj**4 + Pk**4))
-                 + 2 * a123 * Pi * Pj**2 * Pk**2)
+        Pi = P[i]
+        si, sj, sk = P[i] * P[i], P[j] * P[j], P[k] * P[k]   # squares, as products
+        dfdPi = Pi * (2 * a1[i]
+                      + 4 * a11 * si
+                      + 2 * a12 * (sj + sk)
+                      + 6 * a111 * si * si
+                      + a112 * (4 * si * (sj + sk) + 2 * (sj * sj + sk * sk))
+                      + 2 * a123 * sj * sk)
         H[i] = -dfdPi
     return H
 
@@ -409,9 +411,10 @@ def padded_sizes(prob: Problem):
     return tuple(prob.n[k] if prob.periodic[k] else 2 * prob.n[k] for k in range(3))
 
 
-def elec_field_fft(P, prob: Problem):
-    """Same sum as elec_field_direct, as a circular convolution on the padded
-    grid (section 3: FFT evaluation of the electrostatic field)."""
+def kernel_spectrum(prob: Problem):
+    """Spectrum of the interaction table placed on the padded grid in
+    wrap-around order (offset -o at index M - o; the entry at index N of an
+    open dimension stays 0)."""
     nx, ny, nz = prob.n
     Mx, My, Mz = padded_sizes(prob)
     kern = np.zeros((6, Mz, My, Mx))
@@ -427,6 +430,18 @@ def elec_field_fft(P, prob: Problem):
     kern[:, pz[:, None, None], py[None, :, None], px[None, None, :]] = \
         prob.tab[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]]
     Nk = np.fft.rfftn(kern, axes=(1, 2, 3))
+    prob._nk_cache = (prob.tab, Nk)
+    return Nk
+
+
+def elec_field_fft(P, prob: Problem):
+    """Same sum as elec_field_direct, as a circular convolution on the padded
+    grid (section 3: FFT evaluation of the electrostatic field)."""
+    nx, ny, nz = prob.n
+    Mx, My, Mz = padded_sizes(prob)
+    cached = prob.__dict__.get("_nk_cache")
+    # the kernel spectrum depends on the table only: transformed once per table
+    Nk = cached[1] if cached is not None and cached[0] is prob.tab else kernel_spectrum(prob)
     Pp = np.zeros((3, Mz, My, Mx))
     Pp[:, :nz, :ny, :nx] = P
     Pk = np.fft.rfftn(Pp, axes=(1, 2, 3))
