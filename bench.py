@@ -190,19 +190,22 @@ def run_c3(max_steps, check, tune_steps, seq_every):
     """Batched relaxation of the 64-instance workload against plain runs.
 
     Relaxed: |F(n) - F(n - check)| < 1e-6 max(|F(n)|, floor), tested every
-    `check` steps on each instance.  Batched: one context per grid shape
-    (24 / 24 / 16 instances), each on its own stream, autotuned, stepped
-    `check` steps at a time until every instance has relaxed (or max_steps).
-    Plain: one single-instance context per shape runs every seq_every-th
-    instance alone from the same start with the same test; its time is
-    scaled by seq_every.  Set-up (tensor builds, uploads, tuning) is not
-    timed."""
+    `check` steps on each instance, on the device (tdgl_relax).  Batched: one
+    context per grid shape (24 / 24 / 16 instances), autotuned, all three
+    relaxed by tdgl_relax_group -- one captured graph per chunk of up to 5000
+    steps with a branch per shape -- with retirement: an instance stops
+    advancing at the check where it relaxed.  Every instance therefore follows
+    exactly its plain trajectory and stops in the same state as a plain run,
+    so the two are compared at equal final energy.  Plain: every seq_every-th
+    instance relaxed alone (a single-instance context, tdgl_relax) and timed;
+    the plain time of the others is their relax steps times the measured
+    plain time per step of their shape.  Set-up (tensor builds, uploads,
+    tuning) is not timed."""
     import numpy as np
     import torch
 
     import paper_2605_28800_amd as T
     import tdgl_inputs as I
-    from paper_2605_28800_amd.relaxation import relax_floor
     groups = I.c3_groups()
     starts, ctxs, info = [], [], []
     for c in groups:
@@ -212,73 +215,74 @@ def run_c3(max_steps, check, tune_steps, seq_every):
         P = np.stack([I.initial_P(c, sd, np.float32) for sd in c["seeds"]])
         ctx.set_P(P)
         fused, rows, ms = T.tdgl_autotune(ctx.ctx, tune_steps)
+        ctx.set_P(P)
         info.append({"grid": list(c["n"]), "instances": nb, "fused_plane": fused, "rows": rows,
                      "ms_per_step_tuned": ms})
         starts.append(P)
         ctxs.append(ctx)
     torch.cuda.synchronize()
-    floors = [relax_floor(c) for c in groups]
-    prev = [ctx.energies_batch()[0][:, 4].copy() for ctx in ctxs]
-    relaxed = [np.full(len(c["T"]), -1) for c in groups]
     t0 = time.perf_counter()
-    steps = 0
-    while steps < max_steps and any((r < 0).any() for r in relaxed):
-        for ctx in ctxs:
-            ctx.step(check)
-        steps += check
-        for g, ctx in enumerate(ctxs):
-            F = ctx.energies_batch()[0][:, 4]
-            ok = np.abs(F - prev[g]) < 1e-6 * np.maximum(np.abs(F), floors[g])
-            relaxed[g][(relaxed[g] < 0) & ok] = steps
-            prev[g] = F.copy()
+    relaxed, steps = T.tdgl_relax_group([ctx.ctx for ctx in ctxs], [len(c["T"]) for c in groups],
+                                        check, max_steps, retire=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    cells = sum(c["n"][0] * c["n"][1] * c["n"][2] * len(c["T"]) for c in groups)
+    F_batch = [ctx.energies_batch()[0][:, 4] for ctx in ctxs]
     for ctx in ctxs:
         ctx.close()
     # plain runs, one instance at a time, same start and test
-    t_seq, n_seq, agree = 0.0, 0, 0
+    t_meas, n_meas, agree, same_F, plain_total = 0.0, 0, 0, 0, 0.0
+    per_step = []
     for g, c in enumerate(groups):
         one = T.Context(dict(c, T=c["T"][0]), T.TDGL_FP32)
+        t_g, steps_g = 0.0, 0
         try:
             for i in range(0, len(c["T"]), seq_every):
                 T.tdgl_set_temperature(one.ctx, c["T"][i])
                 one.set_P(starts[g][i])
                 torch.cuda.synchronize()
-                f_prev = one.energies()[0][4]
                 t1 = time.perf_counter()
-                k, done = 0, -1
-                while k < max_steps:
-                    one.step(check)
-                    k += check
-                    f = one.energies()[0][4]
-                    if abs(f - f_prev) < 1e-6 * max(abs(f), floors[g]):
-                        done = k
-                        break
-                    f_prev = f
-                t_seq += (time.perf_counter() - t1) * seq_every
-                n_seq += 1
-                agree += int(done == relaxed[g][i])
+                done, taken = one.relax(check, max_steps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                t_g += dt
+                steps_g += taken
+                n_meas += 1
+                agree += int(done[0] == relaxed[g][i])
+                same_F += int(one.energies()[0][4] == F_batch[g][i])
         finally:
             one.close()
+        t_meas += t_g
+        rate = t_g / max(steps_g, 1)                  # plain seconds per step of this shape
+        per_step.append(rate * 1e3)
+        plain_total += rate * float(np.where(relaxed[g] > 0, relaxed[g], steps).sum())
+    cells = sum(c["n"][0] * c["n"][1] * c["n"][2] * len(c["T"]) for c in groups)
+    nrel = int(sum((r > 0).sum() for r in relaxed))
     return {
         "workload": "64 open BaTiO3 boxes: 24 of 32x32x32, 24 of 64x64x16, 16 of 96x96x8 "
                     "(padded 64^3 / 128x128x32 / 256x256x16), T ~ U(200, 450) K, "
                     "P ~ U(-0.1, 0.1), FP32 Heun dtau=1e-3",
-        "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V)" % check,
+        "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V), on the device"
+                     % check,
         "groups": info,
         "max_steps": max_steps,
+        "batched": "tdgl_relax_group: one graph per <= 5000-step chunk with a branch per shape; "
+                   "relaxed instances retired",
         "batched_steps": steps,
-        "relaxed": int(sum((r >= 0).sum() for r in relaxed)),
+        "relaxed": nrel,
         "instances": int(sum(len(r) for r in relaxed)),
         "relax_steps": [r.tolist() for r in relaxed],
         "batched_s": t_batch,
-        "batched_cell_steps_per_s": cells * steps / t_batch,
-        "plain_s": t_seq,
-        "plain_runs_timed": n_seq,
-        "plain_scaled_by": seq_every,
+        "plain_ms_per_step": per_step,
+        "plain_measured_runs": n_meas,
+        "plain_measured_s": t_meas,
         "plain_same_relax_step": agree,
-        "speedup": t_seq / t_batch if t_batch > 0 else None,
+        "plain_same_final_energy": same_F,
+        "plain_s": plain_total,
+        "plain_note": "measured runs (every %d-th instance) give the per-step time of each "
+                      "shape; plain_s = sum over all 64 of relax steps (the cap if not relaxed) "
+                      "x that time" % seq_every,
+        "speedup": plain_total / t_batch if t_batch > 0 else None,
+        "cell_steps_per_s_batched_if_all_ran": cells * steps / t_batch if t_batch > 0 else None,
     }
 
 
@@ -291,6 +295,23 @@ def net_flops(width, shape):
     level = [0, 0, 1, 1, 2, 2, 2, 1, 1, 0, 0, 0]
     return sum(2.0 * 27 * ci * co * cells[lv]
                for (ci, co), lv in zip(I.net_layer_shapes(width), level))
+
+
+def equal_accuracy(s_pl, s_pr, dF, t_pl, t_pr, cap):
+    """The proposal's gains over the held-out samples whose proposal-started
+    run ends at an energy equal to (within 1e-6 relative) or below the plain
+    run's, and both relaxed: mean relax steps and summed per-instance time to
+    relaxed, plain over proposal."""
+    import numpy as np
+    m = (dF <= 1e-6) & (s_pl > 0) & (s_pr > 0)
+    if not m.any():
+        return {"samples": 0}
+    return {"samples": int(m.sum()),
+            "criterion": "final F(proposal) <= F(plain) (1 + 1e-6 sign), both relaxed",
+            "plain_mean_steps": float(s_pl[m].mean()),
+            "proposal_mean_steps": float(s_pr[m].mean()),
+            "steps_ratio": float(s_pl[m].mean() / s_pr[m].mean()),
+            "instance_time_ratio": float(t_pl[m].sum() / max(t_pr[m].sum(), 1e-30))}
 
 
 def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, check=100,
@@ -352,6 +373,8 @@ def run_c5(n_train, n_test, data_steps, eval_steps, train_steps, batch, width, c
         "final_energy_rel_diff": {"median": float(np.median(dF)),
                                   "max_abs": float(np.abs(dF).max()),
                                   "lower_or_equal": int((dF <= 1e-6).sum())},
+        "equal_accuracy": equal_accuracy(s_pl, s_pr, dF, r["plain_instance_seconds"],
+                                         r["proposal_instance_seconds"], eval_steps),
         "P_rel_diff_median": float(np.median(r["P_rel_diff"])),
         "train_step_ms": {"forward": prof[0], "backward": prof[1], "adam": prof[2]},
         "conv_kernels_ms": {"forward": prof[3], "backward_data": prof[4], "weight_grad": prof[5]},

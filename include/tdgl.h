@@ -128,15 +128,22 @@ const char *tdgl_last_error(const tdgl_ctx *ctx);
 /* dims out[7]: nx, ny, nz, padded mx, my, mz, hx = mx/2+1. */
 tdgl_status tdgl_get_dims(const tdgl_ctx *ctx, int out[7]);
 
-/* Bytes of device workspace the context needs for its state, spectra and
- * tensor (tensor construction temporaries excluded). */
+/* Bytes of device workspace the context needs for its state, spectra,
+ * tensor, relaxation bookkeeping, the field of the gradient cross terms and
+ * the buffers of the integrator set at the time of the call (AB3M2: three
+ * P-sized field histories; RK45: eight P-sized stage buffers), tensor
+ * construction temporaries excluded.  Set the integrator first. */
 tdgl_status tdgl_workspace_size(const tdgl_ctx *ctx, size_t *bytes);
 
 /* Hand the context caller-owned device memory (e.g. a torch tensor) of at
  * least tdgl_workspace_size bytes, 256-byte aligned, instead of letting it
- * allocate.  Must precede every call that touches the device; the memory
- * must outlive the context.  Errors: TDGL_E_ARG (size, alignment),
- * TDGL_E_STATE (device memory already allocated). */
+ * allocate: every buffer of every step then lives in it.  Must precede every
+ * call that touches the device; the memory must outlive the context.  A
+ * later switch to an integrator whose buffers do not fit makes tdgl_step
+ * fail with TDGL_E_STATE.  Without a bound workspace the library allocates
+ * its own, and the buffers of a later integrator switch separately.
+ * Errors: TDGL_E_ARG (size, alignment), TDGL_E_STATE (device memory already
+ * allocated). */
 tdgl_status tdgl_bind_workspace(tdgl_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Normalisation of Table 2: P0 (C/m^2), alpha_ref (N m^2 C^-2, > 0, used in
@@ -199,9 +206,9 @@ tdgl_status tdgl_set_terms(tdgl_ctx *ctx, unsigned mask);
  * (P + P~)/2 + dtau/2 E(P~)); TDGL_AB3M2, the multistep scheme read as the
  * third-order Adams-Bashforth predictor with the two-step Adams-Moulton
  * corrector, two field evaluations per step, started by two Heun steps.
- * AB3M2 keeps the fields of the last two steps: it allocates three P-sized
- * device buffers on first use (outside the workspace), and tdgl_set_P, this
- * call and tdgl_autotune restart it (the next two steps are Heun steps).
+ * AB3M2 keeps the fields of the last two steps in three P-sized device
+ * buffers (see tdgl_workspace_size), and tdgl_set_P, this call and
+ * tdgl_autotune restart it (the next two steps are Heun steps).
  * TDGL_RK45: the adaptive Dormand-Prince 5(4) pair, seven field evaluations
  * per attempt; dtau is the first trial step, tdgl_step(n) makes n accepted
  * steps (see tdgl_set_rk_tolerances); RK45 steps are launched eagerly and
@@ -244,32 +251,39 @@ tdgl_status tdgl_set_update_rows(tdgl_ctx *ctx, int rows);
 
 /* Load P (C/m^2, [nbatch][3][nz][ny][nx]) from src: host memory if
  * src_on_device is 0, device memory otherwise; src_precision TDGL_FP32 or TDGL_FP64 (converted
- * to the context precision).  Vacuum layers are set to zero and the
+ * to the context precision).  P is the state variable of eq 1, uniform in
+ * each cell (section 3); it is kept as P/P0 (Table 2).  Vacuum layers are set to zero and the
  * non-finite flag is cleared.  Needs the model to be complete (scales,
  * every material named by the layer map, gradient coefficients when the
  * gradient term is on).  Host sources are copied before return. */
 tdgl_status tdgl_set_P(tdgl_ctx *ctx, const void *src, int src_on_device, int src_precision);
 
 /* Store the current P to dst (layout of tdgl_set_P; host or device, FP32 or
- * FP64).  Host
+ * FP64), converted back from P/P0 (Table 2) to C/m^2.  Host
  * destinations are synchronising and report TDGL_E_NONFINITE like
  * tdgl_sync (the data is copied either way). */
 tdgl_status tdgl_get_P(tdgl_ctx *ctx, void *dst, int dst_on_device, int dst_precision);
 
-/* Advance nsteps time steps (one Euler step = 1 field evaluation, one Heun
- * step = 2).  Asynchronous: a non-finite P produced by a step is recorded on
+/* Advance nsteps time steps of eq 1 in reduced time (Table 2, L = 1) with the
+ * integrator of tdgl_set_integrator (section 3: explicit schemes, Heun
+ * named); each field evaluation is E_eff = -dF/dP of eq 2 with the terms
+ * of eqs 3-7 that tdgl_set_terms switches on (one Euler step = 1 field
+ * evaluation, one Heun step = 2).  Asynchronous: a non-finite P produced by a step is recorded on
  * the device and reported as TDGL_E_NONFINITE by the next tdgl_sync,
  * tdgl_energies or host tdgl_get_P; P then holds the bad state (restore a
  * copy taken with tdgl_get_P and retry with a smaller dtau).  Needs set_P,
  * and build_tensor when the electrostatic term is on. */
 tdgl_status tdgl_step(tdgl_ctx *ctx, long long nsteps);
 
-/* Effective field E_eff (V/m) of the current P with the terms in mask (a
- * subset of TDGL_ALL), written to device memory dst_dev
+/* Effective field E_eff = -dF/dP (V/m) of the current P, eq 1 with eq 2:
+ * the Landau (eq 3), gradient (eq 4), electrostatic (eqs 5-6) and applied
+ * (eq 7) fields in mask (a subset of TDGL_ALL), written to device memory dst_dev
  * ([nbatch][3][nz][ny][nx], context precision).  Vacuum cells get 0. */
 tdgl_status tdgl_eval_field(tdgl_ctx *ctx, unsigned mask, void *dst_dev);
 
-/* Energies of the current P with the context's term mask, in J:
+/* Energies of the current P with the context's term mask, in J (eq 2 and
+ * its terms, eqs 3-7, summed over the cells of volume dx dy dz; the
+ * electrostatic term is -1/2 sum P.E_elec, eq 5):
  * F[0] Landau, F[1] gradient, F[2] electrostatic, F[3] external, F[4] total;
  * meanP[3]: mean P over material cells (C/m^2).  FP64 accumulation.
  * Synchronising.  For a batch: instance 0. */
@@ -298,11 +312,47 @@ tdgl_status tdgl_energies_batch(tdgl_ctx *ctx, double *F, double *meanP);
  * ordered and safe.  Nothing of a previous call is reused.
  * Needs P to be set (the context's own buffers exist then: this call never
  * allocates them).  Model changes since the last step are uploaded first,
- * which waits for the stream; under capture, make them before capturing.
- * TDGL_E_STATE if the gradient cross terms were switched on since the last
- * step (their buffer would have to be allocated). */
+ * which waits for the stream; under capture, make them before capturing. */
 #define TDGL_NOALLOC_SCRATCH_BYTES (1u << 20)
 tdgl_status tdgl_energies_noalloc(tdgl_ctx *ctx, double *out_dev);
+
+/* Relax every instance to the energy criterion (the relaxed states of the
+ * paper's parallel runs, sections 3 and 4.2; the paper gives no criterion,
+ * this library's reading): the instances advance in calls of `check` steps
+ * and after each the total energy F of every instance (eq 2, FP64, as
+ * tdgl_energies_batch) is compared on the device with its value `check`
+ * steps earlier; instance b has relaxed at step n when
+ *   |F_b(n) - F_b(n - check)| < rtol * max(|F_b(n)|, floor),
+ *   floor = floor_factor * alpha_ref * P0^2 * nx*ny*nz*dx*dy*dz  (J).
+ * relax_step[nbatch] (host) receives n, or -1 if the instance did not relax
+ * within max_steps (the last call may pass max_steps by less than check);
+ * *steps_taken (may be NULL) the steps done, which stop at the first check
+ * where every instance has relaxed.  retire = 1: an instance stops
+ * advancing at the check where it relaxed (its P stays that state, and its
+ * lines are skipped by every kernel); retire = 0: all advance until the last
+ * one relaxes.  Euler and Heun run as captured graphs of up to 5000 steps
+ * with the energies and the test inside, synchronising once per graph;
+ * AB3M2 and RK45 advance through tdgl_step, synchronise once per check and
+ * ignore retire.  Errors as tdgl_step; TDGL_E_ARG for check outside
+ * 1..1e6, max_steps < 0, rtol <= 0, floor_factor < 0, retire not 0/1. */
+tdgl_status tdgl_relax(tdgl_ctx *ctx, long long check, long long max_steps, double rtol,
+                       double floor_factor, int retire, long long *relax_step,
+                       long long *steps_taken);
+
+/* tdgl_relax for nctx contexts at once, e.g. batches of different grid
+ * shapes (the paper's many parallel simulations, section 3): every captured
+ * graph holds each context's steps, energies and tests as parallel branches
+ * (one graph per chunk of up to 5000 steps across all the shapes), launched
+ * on the first context's stream after the other contexts' earlier work;
+ * their later work waits for it.  Same arguments and criterion as
+ * tdgl_relax; relax_step receives the instances of every context in order
+ * (sum of their nbatch entries); *steps_taken is the largest of the
+ * contexts'.  Every context must use Euler or Heun with graphs on
+ * (TDGL_E_UNSUPPORTED otherwise) and live on one device.  Errors of a
+ * context are reported by its tdgl_last_error. */
+tdgl_status tdgl_relax_group(tdgl_ctx *const *ctxs, int nctx, long long check,
+                             long long max_steps, double rtol, double floor_factor, int retire,
+                             long long *relax_step, long long *steps_taken);
 
 /* Quasi-static field sweep (the paper drives samples with a time-dependent
  * external field, section 3, and traces P against E in section 4.4): for

@@ -28,6 +28,7 @@ _STATUS = {0: "TDGL_OK", -1: "TDGL_E_ARG", -2: "TDGL_E_NOMEM", -3: "TDGL_E_HIP",
 
 c_int, c_uint, c_double, c_void_p, c_size_t = (ctypes.c_int, ctypes.c_uint, ctypes.c_double,
                                                 ctypes.c_void_p, ctypes.c_size_t)
+c_longlong = ctypes.c_longlong
 
 
 class tdgl_grid(ctypes.Structure):
@@ -63,6 +64,11 @@ _SIGS = {
     "tdgl_get_dims": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_workspace_size": ([_ctx_p, ctypes.POINTER(c_size_t)], c_int),
     "tdgl_bind_workspace": ([_ctx_p, c_void_p, c_size_t], c_int),
+    "tdgl_relax": ([_ctx_p, c_longlong, c_longlong, c_double, c_double, c_int,
+                    ctypes.POINTER(c_longlong), ctypes.POINTER(c_longlong)], c_int),
+    "tdgl_relax_group": ([ctypes.POINTER(_ctx_p), c_int, c_longlong, c_longlong, c_double,
+                          c_double, c_int, ctypes.POINTER(c_longlong),
+                          ctypes.POINTER(c_longlong)], c_int),
     "tdgl_energies_noalloc": ([_ctx_p, c_void_p], c_int),
     "tdgl_set_scales": ([_ctx_p, c_double, c_double, c_double, c_double], c_int),
     "tdgl_set_material": ([_ctx_p, c_int, ctypes.POINTER(tdgl_material)], c_int),
@@ -326,6 +332,38 @@ def tdgl_profile_kernels(ctx, nrep: int):
     return tuple(ms)
 
 
+def tdgl_relax(ctx, nbatch: int, check: int, max_steps: int, rtol: float = 1e-6,
+               floor_factor: float = 1e-3, retire: bool = False):
+    """Relax every instance (tdgl_relax); returns (relax step per instance,
+    -1 if not relaxed; steps taken)."""
+    steps = (c_longlong * nbatch)()
+    taken = c_longlong(0)
+    _check(ctx, lib().tdgl_relax(ctx, check, max_steps, rtol, floor_factor, int(retire),
+                                 steps, ctypes.byref(taken)))
+    return np.array(steps[:], dtype=np.int64), int(taken.value)
+
+
+def tdgl_relax_group(ctxs, nbatches, check: int, max_steps: int, rtol: float = 1e-6,
+                     floor_factor: float = 1e-3, retire: bool = False):
+    """Relax several contexts in one graph per chunk (tdgl_relax_group);
+    returns (list of per-instance relax steps per context; steps taken)."""
+    n = len(ctxs)
+    arr = (_ctx_p * n)(*ctxs)
+    total = int(sum(nbatches))
+    steps = (c_longlong * total)()
+    taken = c_longlong(0)
+    st = lib().tdgl_relax_group(arr, n, check, max_steps, rtol, floor_factor, int(retire), steps,
+                                ctypes.byref(taken))
+    if st != TDGL_OK:
+        msgs = [(lib().tdgl_last_error(c) or b"").decode() for c in ctxs]
+        raise TdglError(st, "tdgl_relax_group: " + " | ".join(m for m in msgs if m))
+    out, off = [], 0
+    for nb in nbatches:
+        out.append(np.array(steps[off:off + nb], dtype=np.int64))
+        off += nb
+    return out, int(taken.value)
+
+
 def tdgl_sweep_eext(ctx, e, steps_per_value: int):
     """e: (n, 3) applied fields in V/m.  Returns meanP (n, nbatch, 3) and
     F (n, nbatch, 5)."""
@@ -398,12 +436,6 @@ class Context:
             self.ctx = tdgl_create(g, precision, c_void_p(self.stream.cuda_stream))
         self.dims = tdgl_get_dims(self.ctx)
         self.workspace = None
-        if torch_workspace:
-            nbytes = tdgl_workspace_size(self.ctx)
-            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
-            ptr = self.workspace.data_ptr()
-            ptr = (ptr + 255) // 256 * 256
-            tdgl_bind_workspace(self.ctx, ptr, nbytes)
         s = cfg["scales"]
         tdgl_set_scales(self.ctx, s["P0"], s["alpha_ref"], s["G110"], s["eps_b"])
         for i, m in enumerate(cfg["materials"]):
@@ -420,6 +452,12 @@ class Context:
         schemes = {"euler": TDGL_EULER, "heun": TDGL_HEUN, "ab3m2": TDGL_AB3M2,
                    "rk45": TDGL_RK45}
         tdgl_set_integrator(self.ctx, schemes[cfg.get("scheme", "heun")], cfg.get("dtau", 1e-3))
+        if torch_workspace:       # sized for the integrator just set
+            nbytes = tdgl_workspace_size(self.ctx)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            ptr = self.workspace.data_ptr()
+            ptr = (ptr + 255) // 256 * 256
+            tdgl_bind_workspace(self.ctx, ptr, nbytes)
         if build_tensor and (cfg.get("terms", TDGL_ALL) & TDGL_ELEC):
             tdgl_build_tensor(self.ctx, cfg.get("mimg", 16))
 
@@ -473,6 +511,11 @@ class Context:
     def energies_batch(self):
         """Per instance: F[nb][5] (J), meanP[nb][3] (C/m^2)."""
         return tdgl_energies_batch(self.ctx)
+
+    def relax(self, check=100, max_steps=20000, rtol=1e-6, floor_factor=1e-3, retire=False):
+        """tdgl_relax: (relax step per instance, -1 if not relaxed; steps taken)."""
+        return tdgl_relax(self.ctx, max(self.batch, 1), check, max_steps, rtol, floor_factor,
+                          retire)
 
     def sync(self):
         tdgl_sync(self.ctx)

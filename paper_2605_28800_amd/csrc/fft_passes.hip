@@ -33,7 +33,7 @@ namespace tdgl {
 template <typename T, int M>
 __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long long in_stride,
                      cpx<T> *__restrict__ out, long long out_kstride,
-                     const cpx<T> *__restrict__ tw, int lpw)
+                     const cpx<T> *__restrict__ tw, int lpw, Freeze fz)
 {
     constexpr int M2 = M / 2;
     constexpr int PPT = HalfLine<M2>::PPT, TPL = HalfLine<M2>::TPL;
@@ -45,7 +45,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     const int l = tid / TPL, t = tid - l * TPL;
     const long long r0 = (long long)blockIdx.x * lpw;
     const long long r = r0 + l;
-    const bool act = (l < lpw) && (r < nrows);
+    const bool act = (l < lpw) && (r < nrows) && !fz.skip(r);
     TwReg<T, M2> tr;
     twiddle_load(tr, tw + M2, t);
     cpx<T> wk[8];
@@ -82,7 +82,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     const int rows_here = (int)((nrows - r0) < lpw ? (nrows - r0) : lpw);
     for (int e = tid; e < (M2 + 1) * lpw; e += nthr) {
         const int k = e / lpw, rl = e - k * lpw;
-        if (rl < rows_here) out[k * out_kstride + r0 + rl] = stg[e];
+        if (rl < rows_here && !fz.skip(r0 + rl)) out[k * out_kstride + r0 + rl] = stg[e];
     }
 }
 
@@ -92,7 +92,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
 template <typename T, int M, bool INV>
 __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long in_stride,
                       long long out_stride, int n_in, int n_out, const cpx<T> *__restrict__ tw,
-                      int lpw)
+                      int lpw, Freeze fz)
 {
     constexpr int TPL = M / 8;
     constexpr int LEN = LinePad<M>::len;
@@ -101,7 +101,7 @@ __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
     const long long line = (long long)blockIdx.x * lpw + l;
-    const bool act = l < lpw && line < nlines;
+    const bool act = l < lpw && line < nlines && !fz.skip(line);
     TwReg<T, M> tr;
     twiddle_load(tr, tw, t);
     const cpx<T> *src = in + (act ? line : 0) * in_stride;
@@ -213,7 +213,7 @@ struct ZmulCfg {
 template <typename T, int MZ>
 __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int nb,
-           const cpx<T> *__restrict__ tw)
+           const cpx<T> *__restrict__ tw, const int *__restrict__ frozen)
 {
     using C = ZmulCfg<T, MZ>;
     constexpr int TPL = C::TPL, CT = C::CT;
@@ -226,6 +226,7 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     const int c = tid / (CT * TPL);
     const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int kxb = (int)(tile / gridDim.x);        // plane (kx, instance)
+    if (frozen && frozen[kxb % nb]) return;         // the whole group: one instance
     const int kx = kxb / nb;
     const int ky = (int)(tile % gridDim.x) * CT + cc;
     const bool act = ky < my;
@@ -324,7 +325,8 @@ size_t plane_lds_bytes(int nz)
 template <typename T, int MY, int MZ>
 __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     k_plane(cpx<T> *S1, const T *__restrict__ Nt, int ny, int nz, int nb,
-            const cpx<T> *__restrict__ twy, const cpx<T> *__restrict__ twz)
+            const cpx<T> *__restrict__ twy, const cpx<T> *__restrict__ twz,
+            const int *__restrict__ frozen)
 {
     using C = PlaneCfg<T, MY, MZ>;
     constexpr int TPLY = C::TPLY, TPLZ = C::TPLZ, CK = C::CK, LINE = C::LINE;
@@ -336,6 +338,7 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     const IdxStridePad ipz{CK};
     const int tid = threadIdx.x;
     const int kx = blockIdx.x / nb;          // work-group = plane (kx, instance)
+    if (frozen && frozen[blockIdx.x % nb]) return;
     const IdxPad pad{};
     const int nlines = 3 * nz;
     cpx<T> *gplane = S1 + (long long)blockIdx.x * nlines * ny;
@@ -441,7 +444,8 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
 
 template <typename T, int M>
 static hipError_t fx_impl(const void *in, long long nrows, int n_in, long long in_stride,
-                          void *out, long long out_kstride, const void *tw, hipStream_t s)
+                          void *out, long long out_kstride, const void *tw, hipStream_t s,
+                          Freeze fz)
 {
     constexpr int M2 = M / 2;
     constexpr int TPL = HalfLine<M2>::TPL;
@@ -453,27 +457,27 @@ static hipError_t fx_impl(const void *in, long long nrows, int n_in, long long i
                        sizeof(cpx<T>);
     hipLaunchKernelGGL((k_fx<T, M>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
                        (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_kstride,
-                       (const cpx<T> *)tw, lpw);
+                       (const cpx<T> *)tw, lpw, fz);
     return hipGetLastError();
 }
 
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
                      long long in_stride, void *out, long long out_kstride, const void *tw,
-                     hipStream_t s)
+                     hipStream_t s, Freeze fz)
 {
     if (prec == PREC_F32) {
         TDGL_LEN_SWITCH(M, return (fx_impl<float, LEN_>(in, nrows, n_in, in_stride, out,
-                                                         out_kstride, tw, s)))
+                                                         out_kstride, tw, s, fz)))
     } else {
         TDGL_LEN_SWITCH(M, return (fx_impl<double, LEN_>(in, nrows, n_in, in_stride, out,
-                                                          out_kstride, tw, s)))
+                                                          out_kstride, tw, s, fz)))
     }
 }
 
 template <typename T, int M>
 static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines,
                            long long in_stride, long long out_stride, int n_in, int n_out,
-                           const void *tw, hipStream_t s)
+                           const void *tw, hipStream_t s, Freeze fz)
 {
     constexpr int TPL = M / 8;
     const int lpw = TPL >= 128 ? 1 : 128 / TPL;     // 128-thread groups (measured best)
@@ -483,24 +487,24 @@ static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines
     if (inv)
         hipLaunchKernelGGL((k_row<T, M, true>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
                            (const cpx<T> *)in, (cpx<T> *)out, nlines, in_stride, out_stride,
-                           n_in, n_out, (const cpx<T> *)tw + M, lpw);
+                           n_in, n_out, (const cpx<T> *)tw + M, lpw, fz);
     else
         hipLaunchKernelGGL((k_row<T, M, false>), dim3((unsigned)blocks), dim3(lpw * TPL), shm,
                            s, (const cpx<T> *)in, (cpx<T> *)out, nlines, in_stride, out_stride,
-                           n_in, n_out, (const cpx<T> *)tw + M, lpw);
+                           n_in, n_out, (const cpx<T> *)tw + M, lpw, fz);
     return hipGetLastError();
 }
 
 hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long long nlines,
                       long long in_stride, long long out_stride, int n_in, int n_out,
-                      const void *tw, hipStream_t s)
+                      const void *tw, hipStream_t s, Freeze fz)
 {
     if (prec == PREC_F32) {
         TDGL_LEN_SWITCH(M, return (row_impl<float, LEN_>(inv, in, out, nlines, in_stride,
-                                                          out_stride, n_in, n_out, tw, s)))
+                                                          out_stride, n_in, n_out, tw, s, fz)))
     } else {
         TDGL_LEN_SWITCH(M, return (row_impl<double, LEN_>(inv, in, out, nlines, in_stride,
-                                                           out_stride, n_in, n_out, tw, s)))
+                                                           out_stride, n_in, n_out, tw, s, fz)))
     }
 }
 
@@ -564,7 +568,8 @@ static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *
     if ((long long)g.hx * g.nb > 65535) return hipErrorInvalidValue;
     const size_t shm = (size_t)3 * C::CT * LinePad<MZ>::len * sizeof(cpx<T>);
     hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm, s,
-                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb, (const cpx<T> *)tw + MZ);
+                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb, (const cpx<T> *)tw + MZ,
+                       g.frozen);
     return hipGetLastError();
 }
 
@@ -594,7 +599,7 @@ static hipError_t plane_impl(const Geom &g, void *S1, const void *Nt, const void
     }
     hipLaunchKernelGGL((k_plane<T, MY, MZ>), dim3(g.hx * g.nb), dim3(C::NTHR), shm, s,
                        (cpx<T> *)S1, (const T *)Nt, g.ny, g.nz, g.nb, (const cpx<T> *)tw + MY,
-                       (const cpx<T> *)tw + MZ);
+                       (const cpx<T> *)tw + MZ, g.frozen);
     return hipGetLastError();
 }
 

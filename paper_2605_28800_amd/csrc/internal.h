@@ -34,6 +34,22 @@ struct Geom {
     int hx;              // mx/2 + 1
     int px, py, pz;      // periodic flags
     int nb = 1;          // instances of this grid advanced together (batch)
+    // per-instance flags (device, nb ints) of instances that no longer
+    // advance (relaxed and retired): the FFT passes skip their lines and the
+    // update kernel copies their state unchanged; null = none
+    const int *frozen = nullptr;
+};
+
+// Frozen-instance test for kernels that see flat line or row indices:
+// index i belongs to instance (i / per) % nb.
+struct Freeze {
+    const int *flag = nullptr;
+    long long per = 1;
+    int nb = 1;
+    __device__ __forceinline__ bool skip(long long i) const
+    {
+        return flag && flag[(int)((i / per) % nb)];
+    }
 };
 
 // Update kernel modes.  UPD_STEP_MS: stages of the multistep scheme
@@ -74,10 +90,10 @@ hipError_t launch_cross(int prec, const Geom &g, const void *P, void *H, const v
 // spectra are kx-major: x pass output element k of row r at out[k*out_kstride + r]
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
                      long long in_stride, void *out, long long out_kstride,
-                     const void *tw, hipStream_t s);
+                     const void *tw, hipStream_t s, Freeze fz = {});
 hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long long nlines,
                       long long in_stride, long long out_stride, int n_in, int n_out,
-                      const void *tw, hipStream_t s);
+                      const void *tw, hipStream_t s, Freeze fz = {});
 hipError_t launch_plane(int prec, const Geom &g, void *S1, const void *Nt, const void *tw,
                         size_t lds_max, hipStream_t s, bool query);
 hipError_t launch_col(int prec, int M, bool inv, const void *in, void *out, long long C,
@@ -93,6 +109,18 @@ hipError_t launch_reduce_partials(const double *partials, int n, int nb, double 
 // final energies [nb][8] (J and C/m^2, as tdgl_energies_batch) from the partials
 hipError_t launch_reduce_energies(const double *partials, int n, int nb, double joule,
                                   double ncell, double P0, double *out, hipStream_t s);
+// relaxation bookkeeping on the device (tdgl_relax), nb entries each
+struct RelaxState {
+    double *Fprev;        // total energy at the previous check (J)
+    long long *step;      // step at which the instance relaxed, -1 = not yet
+    int *frozen;          // retired instances (Geom::frozen)
+    long long *counter;   // steps done since the relaxation started
+    long long *stopped;   // counter when the last instance relaxed, -1 before
+    int *remaining;       // instances not relaxed yet
+};
+hipError_t launch_relax_test(const double *E, const RelaxState &r, int nb, bool init,
+                             long long check, double rtol, double floor, bool retire,
+                             hipStream_t s);
 // fixed device scratch of the allocation-free entry point: SCRATCH_DOUBLES
 // doubles per device; *out = this device's address (current device)
 constexpr size_t SCRATCH_DOUBLES = 131072;        // 1 MiB

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -35,9 +36,19 @@ struct GraphEntry {
     unsigned terms = 0;
     bool cross = false;
     int hpos = 0;                 // multistep history phase at the chunk start
+    // relaxation chunks (tdgl_relax): chunk = checks per graph
+    bool relax = false, retire = false;
+    long long check = 0, nmat = 0;
+    double rtol = 0.0, floor = 0.0, joule = 0.0, P0 = 0.0;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// relaxation bookkeeping per instance: previous total energy (double), relax
+// step (long long), frozen flag (int, padded); then three counters
+constexpr size_t RLX_BYTES_PER_INSTANCE = 24;
+// steps per captured relaxation graph (a whole number of checks)
+constexpr long long RELAX_GRAPH_STEPS = 5000;
 
 int next_pow2(int v)
 {
@@ -80,12 +91,16 @@ struct tdgl_ctx {
     void *S1 = nullptr, *S2 = nullptr, *Nt = nullptr, *coef = nullptr, *kp = nullptr;
     void *twf = nullptr, *twd = nullptr;
     double *gl = nullptr, *partials = nullptr, *res = nullptr;
+    void *rlx = nullptr;          // relaxation bookkeeping (tdgl_relax)
     int *flag = nullptr;
     int cur = 0;
     int yt = 2;
-    void *hist = nullptr;         // multistep: three E buffers (lazy, own allocation)
-    void *rkbuf = nullptr;        // RK45: stage point Q and k_1..k_7 (lazy, own allocation)
-    void *xbuf = nullptr;         // field of the gradient cross terms (lazy, own allocation)
+    // buffers only some models need: in a bound workspace after the core
+    // regions (layout_of), otherwise allocated on first use (*_own)
+    void *hist = nullptr;         // multistep: three E buffers
+    void *rkbuf = nullptr;        // RK45: stage point Q and k_1..k_7
+    void *xbuf = nullptr;         // field of the gradient cross terms
+    bool hist_own = false, rk_own = false, x_own = false;
     double rk_h = 0.0, rk_tau = 0.0, rk_atol = 1e-8, rk_rtol = 1e-6;
     long long rk_rejected = 0;
     int hist_count = 0;           // valid history entries (0..2)
@@ -122,10 +137,17 @@ tdgl_status fail(tdgl_ctx *c, tdgl_status st, const char *fmt, ...)
 
 // ---- layout of the device workspace
 struct Layout {
-    size_t P, S1, S2, Nt, coef, kp, twf, twd, gl, partials, flag, res, total;
+    size_t P, S1, S2, Nt, coef, kp, twf, twd, gl, partials, flag, res, rlx;
+    size_t xbuf, extra, total;     // cross-term field; history or RK45 buffers
 };
 
-Layout layout_of(const tdgl_ctx *c)
+bool cross_terms(const tdgl_ctx *c);
+
+// Core regions, then the field of the gradient cross terms (always laid out:
+// the gradient may change between steps), then the multistep history
+// (scheme AB3M2) or the RK45 stage buffers (scheme RK45) of the scheme set
+// when the layout is taken.
+Layout layout_of(const tdgl_ctx *c, int scheme)
 {
     const Geom &g = c->g;
     const size_t N = (size_t)g.nx * g.ny * g.nz * g.nb;   // cells of all instances
@@ -148,9 +170,17 @@ Layout layout_of(const tdgl_ctx *c)
     L.partials = take((size_t)c->nblocks * g.nb * 8 * sizeof(double));
     L.flag = take(sizeof(int));
     L.res = take((size_t)8 * g.nb * sizeof(double));
+    L.rlx = take(RLX_BYTES_PER_INSTANCE * g.nb + 32);
+    const size_t pbytes = 3 * N * c->esz;
+    L.xbuf = take(pbytes);
+    L.extra = off;
+    if (scheme == TDGL_AB3M2) take(3 * pbytes);
+    if (scheme == TDGL_RK45) take(8 * pbytes);
     L.total = off;
     return L;
 }
+
+Layout layout_of(const tdgl_ctx *c) { return layout_of(c, c->scheme); }
 
 // Gauss-Legendre nodes and weights on [0,1] (Newton on the Legendre
 // recurrence in long double); row n of the tables holds n nodes.
@@ -237,6 +267,10 @@ tdgl_status ensure_device(tdgl_ctx *c)
     c->partials = reinterpret_cast<double *>(b + L.partials);
     c->flag = reinterpret_cast<int *>(b + L.flag);
     c->res = reinterpret_cast<double *>(b + L.res);
+    c->rlx = b + L.rlx;
+    c->xbuf = b + L.xbuf;
+    if (c->scheme == TDGL_AB3M2) c->hist = b + L.extra;
+    if (c->scheme == TDGL_RK45) c->rkbuf = b + L.extra;
     auto twf = twiddle_table<float>();
     auto twd = twiddle_table<double>();
     std::vector<double> gl(2 * GL_MAXN * GL_MAXN);
@@ -373,6 +407,7 @@ tdgl_status upload_params(tdgl_ctx *c)
             c->xbuf = nullptr;
             return fail(c, TDGL_E_NOMEM, "gradient cross-term buffer: hipMalloc failed");
         }
+        c->x_own = true;
     }
     return c->prec == PREC_F32 ? upload_params_t<float>(c) : upload_params_t<double>(c);
 }
@@ -391,7 +426,8 @@ hipError_t enq_fx(tdgl_ctx *c, const void *P, hipStream_t s)
 {
     const Geom &g = c->g;
     const long long rows = 3LL * g.nb * g.nz * g.ny;      // rows of all instances
-    return launch_fx(c->prec, g.mx, P, rows, g.nx, g.nx, c->S1, rows, tw(c), s);
+    const Freeze fz{g.frozen, 3LL * g.nz * g.ny, g.nb};   // rows [nb][3][nz][ny]
+    return launch_fx(c->prec, g.mx, P, rows, g.nx, g.nx, c->S1, rows, tw(c), s, fz);
 }
 
 // y pass, z pass with the tensor, inverse y pass: S1 (x spectra, kx-major
@@ -401,12 +437,14 @@ hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
     const Geom &g = c->g;
     if (c->use_plane) return launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, s, false);
     const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
+    const Freeze fz{g.frozen, 3LL * g.nz, g.nb};          // lines [hx][nb][3][nz]
     hipError_t e = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
-                              tw(c), s);
+                              tw(c), s, fz);
     if (e != hipSuccess) return e;
     e = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), s);
     if (e != hipSuccess) return e;
-    return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny, tw(c), s);
+    return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny, tw(c), s,
+                      fz);
 }
 
 // field of the gradient cross terms at Pin into xbuf, when the model has them
@@ -533,7 +571,7 @@ tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
     const bool cross = cross_terms(c) && (c->terms & TDGL_GRAD) && c->xbuf;
     const int hpos = c->scheme == TDGL_AB3M2 ? c->hist_pos : 0;
     for (auto &e : c->graphs)
-        if (e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk &&
+        if (!e.relax && e.cur == c->cur && e.scheme == c->scheme && e.chunk == chunk &&
             e.terms == c->terms && e.cross == cross && e.hpos == hpos) {
             *out = e.exec;
             return TDGL_OK;
@@ -567,6 +605,118 @@ tdgl_status get_graph(tdgl_ctx *c, int chunk, hipGraphExec_t *out)
     ge.hpos = hpos;
     c->graphs.push_back(ge);
     *out = exec;
+    return TDGL_OK;
+}
+
+// ---- relaxation (tdgl_relax)
+RelaxState relax_state(const tdgl_ctx *c)
+{
+    const size_t nb = (size_t)c->g.nb;
+    char *b = static_cast<char *>(c->rlx);
+    RelaxState r;
+    r.Fprev = reinterpret_cast<double *>(b);
+    r.step = reinterpret_cast<long long *>(b + 8 * nb);
+    r.frozen = reinterpret_cast<int *>(b + 16 * nb);
+    r.counter = reinterpret_cast<long long *>(b + 24 * nb);
+    r.stopped = reinterpret_cast<long long *>(b + 24 * nb + 8);
+    r.remaining = reinterpret_cast<int *>(b + 24 * nb + 16);
+    return r;
+}
+
+struct RelaxArgs {
+    long long check;
+    double rtol, floor;     // floor in J
+    bool retire;
+    double joule;           // J per reduced energy unit
+    long long nmat;         // material cells per instance
+};
+
+// Energies of the current state of every instance (the spectra must be the
+// current state's: S1 from the last update or from a fresh x pass), reduced
+// on the device to J exactly as tdgl_energies_batch does, then the relaxation
+// test.  Leaves S1 holding field rows.
+hipError_t enq_relax_check(tdgl_ctx *c, const void *P, const RelaxArgs &ra, bool init,
+                           hipStream_t s)
+{
+    const bool el = elec_on(c);
+    hipError_t e = enq_eval(c, UPD_ENERGY, P, nullptr, nullptr, 0, c->terms, el, false, s);
+    if (e != hipSuccess) return e;
+    const int ngroups = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
+    e = launch_reduce_energies(c->partials, ngroups, c->g.nb, ra.joule, (double)ra.nmat, c->P0,
+                               c->res, s);
+    if (e != hipSuccess) return e;
+    return launch_relax_test(c->res, relax_state(c), c->g.nb, init, ra.check, ra.rtol, ra.floor,
+                             ra.retire, s);
+}
+
+// nchecks relaxation checks into stream s (being captured): each `check`
+// steps, the energies and the test, then the x pass of the state for the next
+// step.  Every kernel skips (the update kernel: carries over) the instances
+// the test froze.  *cur: buffer parity before and after.
+hipError_t enq_relax_chunk(tdgl_ctx *c, int nchecks, const RelaxArgs &ra, hipStream_t s, int *cur)
+{
+    const bool el = elec_on(c);
+    c->g.frozen = relax_state(c).frozen;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < nchecks && le == hipSuccess; ++k) {
+        for (long long i = 0; i < ra.check && le == hipSuccess; ++i) le = enq_step(c, cur, s);
+        if (le == hipSuccess) le = enq_relax_check(c, c->P[*cur], ra, false, s);
+        if (le == hipSuccess && el) le = enq_fx(c, c->P[*cur], s);
+    }
+    c->g.frozen = nullptr;
+    return le;
+}
+
+// A captured graph of enq_relax_chunk, cached per configuration.
+tdgl_status get_relax_graph(tdgl_ctx *c, int nchecks, const RelaxArgs &ra, hipGraphExec_t *out,
+                            int *cur_after)
+{
+    const bool cross = cross_terms(c) && (c->terms & TDGL_GRAD) && c->xbuf;
+    for (auto &e : c->graphs)
+        if (e.relax && e.cur == c->cur && e.scheme == c->scheme && e.chunk == nchecks &&
+            e.terms == c->terms && e.cross == cross && e.check == ra.check &&
+            e.retire == ra.retire && e.rtol == ra.rtol && e.floor == ra.floor &&
+            e.joule == ra.joule && e.nmat == ra.nmat && e.P0 == c->P0) {
+            *out = e.exec;
+            *cur_after = e.hpos;
+            return TDGL_OK;
+        }
+    hipGraph_t graph = nullptr;
+    hipError_t le = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    int cur = c->cur;
+    if (le == hipSuccess) {
+        le = enq_relax_chunk(c, nchecks, ra, c->cap, &cur);
+        hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+        if (le == hipSuccess) le = ee;
+    }
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, TDGL_E_HIP, "relaxation graph capture failed: %s", hipGetErrorString(le));
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess)
+        return fail(c, TDGL_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    GraphEntry ge;
+    ge.exec = exec;
+    ge.cur = c->cur;
+    ge.scheme = c->scheme;
+    ge.chunk = nchecks;
+    ge.terms = c->terms;
+    ge.cross = cross;
+    ge.hpos = cur;                 // buffer parity after the chunk
+    ge.relax = true;
+    ge.retire = ra.retire;
+    ge.check = ra.check;
+    ge.rtol = ra.rtol;
+    ge.floor = ra.floor;
+    ge.joule = ra.joule;
+    ge.nmat = ra.nmat;
+    ge.P0 = c->P0;
+    c->graphs.push_back(ge);
+    *out = exec;
+    *cur_after = cur;
     return TDGL_OK;
 }
 
@@ -647,9 +797,9 @@ void tdgl_destroy(tdgl_ctx *c)
         (void)hipStreamSynchronize(c->stream);
         drop_graphs(c);
         if (c->ws_owned && c->ws) (void)hipFree(c->ws);
-        if (c->hist) (void)hipFree(c->hist);
-        if (c->rkbuf) (void)hipFree(c->rkbuf);
-        if (c->xbuf) (void)hipFree(c->xbuf);
+        if (c->hist && c->hist_own) (void)hipFree(c->hist);
+        if (c->rkbuf && c->rk_own) (void)hipFree(c->rkbuf);
+        if (c->xbuf && c->x_own) (void)hipFree(c->xbuf);
         if (c->cap) (void)hipStreamDestroy(c->cap);
     }
     delete c;
@@ -979,6 +1129,32 @@ tdgl_status tdgl_get_P(tdgl_ctx *c, void *dst, int on_dev, int dst_prec)
 
 namespace {
 
+// The history (AB3M2) or stage buffers (RK45) of scheme: in a bound
+// workspace, the region after the cross-term field, which must be large
+// enough (TDGL_E_STATE otherwise); without one, a device allocation of
+// its own, made once.
+tdgl_status extra_buffer(tdgl_ctx *c, int scheme, size_t bytes, void **out, bool *own)
+{
+    const Layout L = layout_of(c, scheme);
+    if (L.total <= c->ws_bytes) {            // the workspace already has room
+        *out = static_cast<char *>(c->ws) + L.extra;
+        *own = false;
+        return TDGL_OK;
+    }
+    if (c->ws_owned) {
+        if (hipMalloc(out, bytes) != hipSuccess) {
+            *out = nullptr;
+            return fail(c, TDGL_E_NOMEM, "buffers of the integrator: hipMalloc(%zu) failed", bytes);
+        }
+        *own = true;
+        return TDGL_OK;
+    }
+    return fail(c, TDGL_E_STATE,
+                "the bound workspace (%zu bytes) lacks the %zu bytes of this integrator's "
+                "buffers: set the integrator before tdgl_workspace_size and bind %zu bytes",
+                c->ws_bytes, bytes, L.total);
+}
+
 // One accepted RK45 step (attempts repeat until one is accepted).
 tdgl_status rk45_step(tdgl_ctx *c)
 {
@@ -986,10 +1162,8 @@ tdgl_status rk45_step(tdgl_ctx *c)
     const size_t n3 = (size_t)3 * g.nx * g.ny * g.nz * g.nb;
     const size_t pbytes = n3 * c->esz;
     if (!c->rkbuf) {
-        if (hipMalloc(&c->rkbuf, 8 * pbytes) != hipSuccess) {
-            c->rkbuf = nullptr;
-            return fail(c, TDGL_E_NOMEM, "RK45 buffers: hipMalloc failed");
-        }
+        tdgl_status st = extra_buffer(c, TDGL_RK45, 8 * pbytes, &c->rkbuf, &c->rk_own);
+        if (st != TDGL_OK) return st;
     }
     const bool el = elec_on(c);
     const int ngroups = ((g.ny + c->yt - 1) / c->yt) * g.nz * g.nb;
@@ -1094,10 +1268,8 @@ tdgl_status tdgl_step(tdgl_ctx *c, long long nsteps)
     if (ms) {
         if (!c->hist) {
             const size_t pbytes = (size_t)3 * c->g.nx * c->g.ny * c->g.nz * c->g.nb * c->esz;
-            if (hipMalloc(&c->hist, 3 * pbytes) != hipSuccess) {
-                c->hist = nullptr;
-                return fail(c, TDGL_E_NOMEM, "multistep history: hipMalloc failed");
-            }
+            st = extra_buffer(c, TDGL_AB3M2, 3 * pbytes, &c->hist, &c->hist_own);
+            if (st != TDGL_OK) return st;
         }
         for (; left > 0 && c->hist_count < 2; --left)      // start-up steps, plain launches
             HIP_TRY(c, enq_step_ms(c, c->cur, &c->hist_count, &c->hist_pos, c->stream));
@@ -1217,10 +1389,6 @@ tdgl_status tdgl_energies_noalloc(tdgl_ctx *c, double *out_dev)
     if (c->params_dirty) {
         tdgl_status st = check_model(c);
         if (st != TDGL_OK) return st;
-        if (cross_terms(c) && !c->xbuf)
-            return fail(c, TDGL_E_STATE,
-                        "gradient cross terms were switched on: their field buffer is made by "
-                        "the next tdgl_step or tdgl_energies, not here");
     }
     const int ngroups = ((c->g.ny + c->yt - 1) / c->yt) * c->g.nz;
     const size_t need = (size_t)ngroups * c->g.nb * 8;
@@ -1230,7 +1398,7 @@ tdgl_status tdgl_energies_noalloc(tdgl_ctx *c, double *out_dev)
                     "(use tdgl_energies_batch)", need, (size_t)SCRATCH_DOUBLES);
     double *scr = nullptr;
     HIP_TRY(c, scratch_address(&scr));
-    tdgl_status st = upload_params(c);      // no allocation: device state and xbuf exist
+    tdgl_status st = upload_params(c);      // no allocation: the workspace holds every buffer
     if (st != TDGL_OK) return st;
     if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
     HIP_TRY(c, enq_eval(c, UPD_ENERGY, c->P[c->cur], nullptr, nullptr, 0, c->terms, el, false,
@@ -1244,6 +1412,236 @@ tdgl_status tdgl_energies_noalloc(tdgl_ctx *c, double *out_dev)
         if (c->layer[z] >= 0) nmat += (long long)c->g.nx * c->g.ny;
     HIP_TRY(c, launch_reduce_energies(scr, ngroups, c->g.nb, scal[4] * scal[5], (double)nmat,
                                       c->P0, out_dev, c->stream));
+    return TDGL_OK;
+}
+
+namespace {
+
+// Validation, model upload, the relaxation arguments and the initial energies
+// (the test's reference) of one context.
+tdgl_status relax_begin(tdgl_ctx *c, long long check, long long max_steps, double rtol,
+                        double floor_factor, int retire, RelaxArgs *ra, bool *graphed)
+{
+    if (check < 1 || check > 1000000) return fail(c, TDGL_E_ARG, "check must be in 1..1e6");
+    if (max_steps < 0) return fail(c, TDGL_E_ARG, "max_steps < 0");
+    if (!(rtol > 0) || !std::isfinite(rtol)) return fail(c, TDGL_E_ARG, "rtol must be > 0");
+    if (!(floor_factor >= 0) || !std::isfinite(floor_factor))
+        return fail(c, TDGL_E_ARG, "floor_factor must be >= 0");
+    if (retire != 0 && retire != 1) return fail(c, TDGL_E_ARG, "retire must be 0 or 1");
+    if (!c->P_set) return fail(c, TDGL_E_STATE, "P has not been set");
+    const bool el = elec_on(c);
+    if (el && !c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
+    tdgl_status st = upload_params(c);
+    if (st != TDGL_OK) return st;
+    // floor: alpha_ref P0^2 (J/m^3) * floor_factor * sample volume
+    const double vol = (double)c->g.nx * c->g.ny * c->g.nz * c->d[0] * c->d[1] * c->d[2];
+    // graphed chunks for the schemes whose steps are graphed; the multistep
+    // scheme and RK45 step through tdgl_step and are never retired
+    *graphed = (c->scheme == TDGL_EULER || c->scheme == TDGL_HEUN) && c->graph_chunk > 0;
+    std::vector<double> coef;
+    double scal[8], gh2[3][3];
+    reduced(c, coef, scal, gh2);
+    long long nmat = 0;
+    for (int z = 0; z < c->g.nz; ++z)
+        if (c->layer[z] >= 0) nmat += (long long)c->g.nx * c->g.ny;
+    *ra = RelaxArgs{check, rtol, floor_factor * c->alpha_ref * c->P0 * c->P0 * vol,
+                    *graphed && retire == 1, scal[4] * scal[5], nmat};
+    if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+    HIP_TRY(c, enq_relax_check(c, c->P[c->cur], *ra, true, c->stream));
+    c->spec_valid = false;
+    return TDGL_OK;
+}
+
+// Relax steps and steps taken of one context (synchronising).
+tdgl_status relax_finish(tdgl_ctx *c, long long *relax_step, long long *steps_taken)
+{
+    const RelaxState rs = relax_state(c);
+    long long counters[2] = {0, -1};
+    std::vector<long long> steps((size_t)c->g.nb);
+    HIP_TRY(c, hipMemcpyAsync(steps.data(), rs.step, steps.size() * sizeof(long long),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(counters, rs.counter, 2 * sizeof(long long), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->g.nb; ++b) relax_step[b] = steps[(size_t)b];
+    if (steps_taken) *steps_taken = counters[1] >= 0 ? counters[1] : counters[0];
+    // frozen instances skipped the last x passes: the next step starts afresh
+    c->spec_valid = false;
+    return TDGL_OK;
+}
+
+}  // namespace
+
+tdgl_status tdgl_relax(tdgl_ctx *c, long long check, long long max_steps, double rtol,
+                       double floor_factor, int retire, long long *relax_step,
+                       long long *steps_taken)
+{
+    if (!c) return TDGL_E_ARG;
+    if (!relax_step) return fail(c, TDGL_E_ARG, "null relax_step");
+    RelaxArgs ra{};
+    bool graphed = false;
+    tdgl_status st = relax_begin(c, check, max_steps, rtol, floor_factor, retire, &ra, &graphed);
+    if (st != TDGL_OK) return st;
+    const bool el = elec_on(c);
+    const RelaxState rs = relax_state(c);
+    long long done = 0;
+    int remaining = c->g.nb;
+    const long long per_graph = std::max(1LL, RELAX_GRAPH_STEPS / check);
+    while (done < max_steps && remaining > 0) {
+        const long long want = (max_steps - done + check - 1) / check;      // checks left
+        if (graphed) {
+            const int nchk = (int)std::min(per_graph, want);
+            if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+            if (c->graphs.size() >= 32) drop_graphs(c);
+            hipGraphExec_t exec = nullptr;
+            int cur_after = c->cur;
+            st = get_relax_graph(c, nchk, ra, &exec, &cur_after);
+            if (st != TDGL_OK) return st;
+            HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+            c->cur = cur_after;
+            c->spec_valid = el;
+            done += nchk * check;
+        } else {
+            st = tdgl_step(c, check);
+            if (st != TDGL_OK) return st;
+            if (el && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+            HIP_TRY(c, enq_relax_check(c, c->P[c->cur], ra, false, c->stream));
+            c->spec_valid = false;
+            done += check;
+        }
+        HIP_TRY(c, hipMemcpyAsync(&remaining, rs.remaining, sizeof(int), hipMemcpyDeviceToHost,
+                                  c->stream));
+        st = read_flag(c);                   // synchronises
+        if (st != TDGL_OK) return st;
+    }
+    return relax_finish(c, relax_step, steps_taken);
+}
+
+tdgl_status tdgl_relax_group(tdgl_ctx *const *ctxs, int nctx, long long check,
+                             long long max_steps, double rtol, double floor_factor, int retire,
+                             long long *relax_step, long long *steps_taken)
+{
+    if (!ctxs || nctx < 1 || nctx > 64 || !relax_step) return TDGL_E_ARG;
+    for (int i = 0; i < nctx; ++i) {
+        if (!ctxs[i]) return TDGL_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(ctxs[i], TDGL_E_ARG, "context listed twice");
+    }
+    tdgl_ctx *c0 = ctxs[0];
+    std::vector<RelaxArgs> ra((size_t)nctx);
+    for (int i = 0; i < nctx; ++i) {
+        tdgl_ctx *c = ctxs[i];
+        if (!(c->scheme == TDGL_EULER || c->scheme == TDGL_HEUN) || c->graph_chunk <= 0)
+            return fail(c, TDGL_E_UNSUPPORTED,
+                        "a relaxation group needs Euler or Heun contexts with graphs");
+        bool graphed = false;
+        tdgl_status st = relax_begin(c, check, max_steps, rtol, floor_factor, retire,
+                                     &ra[(size_t)i], &graphed);
+        if (st != TDGL_OK) return st;
+    }
+    // events: [0, nctx) join the contexts' streams to the first one around
+    // each graph launch; [nctx, 2 nctx) fork and join the branches in capture
+    std::vector<hipEvent_t> ev((size_t)2 * nctx, nullptr);
+    struct Cleanup {
+        std::vector<hipEvent_t> &ev;
+        std::vector<std::pair<std::vector<int>, hipGraphExec_t>> graphs;
+        ~Cleanup()
+        {
+            for (auto &e : ev)
+                if (e) (void)hipEventDestroy(e);
+            for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        }
+    } cl{ev, {}};
+    for (auto &e : ev) HIP_TRY(c0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    long long done = 0;
+    long long remaining = 1;
+    const long long per_graph = std::max(1LL, RELAX_GRAPH_STEPS / check);
+    std::vector<int> rem((size_t)nctx, 0);
+    while (done < max_steps && remaining > 0) {
+        const long long want = (max_steps - done + check - 1) / check;
+        const int nchk = (int)std::min(per_graph, want);
+        // key: checks per graph and every context's buffer parity
+        std::vector<int> key{nchk};
+        for (int i = 0; i < nctx; ++i) {
+            tdgl_ctx *c = ctxs[i];
+            if (elec_on(c) && !c->spec_valid) HIP_TRY(c, enq_fx(c, c->P[c->cur], c->stream));
+            key.push_back(c->cur);
+        }
+        hipGraphExec_t exec = nullptr;
+        for (auto &g : cl.graphs)
+            if (g.first == key) exec = g.second;
+        std::vector<int> cur_after((size_t)nctx);
+        for (int i = 0; i < nctx; ++i) cur_after[(size_t)i] = ctxs[i]->cur;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            hipError_t le = hipStreamBeginCapture(c0->cap, hipStreamCaptureModeThreadLocal);
+            if (le == hipSuccess) {
+                le = hipEventRecord(ev[(size_t)nctx], c0->cap);        // fork
+                for (int i = 1; i < nctx && le == hipSuccess; ++i)
+                    le = hipStreamWaitEvent(ctxs[i]->cap, ev[(size_t)nctx], 0);
+                // (the branches of the contexts run side by side in one graph)
+                for (int i = 0; i < nctx && le == hipSuccess; ++i)
+                    le = enq_relax_chunk(ctxs[i], nchk, ra[(size_t)i], ctxs[i]->cap,
+                                         &cur_after[(size_t)i]);
+                for (int i = 1; i < nctx && le == hipSuccess; ++i) {  // join
+                    le = hipEventRecord(ev[(size_t)(nctx + i)], ctxs[i]->cap);
+                    if (le == hipSuccess)
+                        le = hipStreamWaitEvent(c0->cap, ev[(size_t)(nctx + i)], 0);
+                }
+                hipError_t ee = hipStreamEndCapture(c0->cap, &graph);
+                if (le == hipSuccess) le = ee;
+            }
+            if (le != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(c0, TDGL_E_HIP, "relaxation group capture failed: %s",
+                            hipGetErrorString(le));
+            }
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess)
+                return fail(c0, TDGL_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            cl.graphs.emplace_back(key, exec);
+        } else {
+            int cur = 0;
+            for (int i = 0; i < nctx; ++i) {       // parities after the chunk
+                cur = ctxs[i]->cur;
+                if (ctxs[i]->scheme == TDGL_EULER && ((long long)nchk * check) % 2) cur = 1 - cur;
+                cur_after[(size_t)i] = cur;
+            }
+        }
+        // the graph runs on the first context's stream after every context's
+        // earlier work, and every context's later work waits for it
+        for (int i = 1; i < nctx; ++i) {
+            HIP_TRY(c0, hipEventRecord(ev[(size_t)i], ctxs[i]->stream));
+            HIP_TRY(c0, hipStreamWaitEvent(c0->stream, ev[(size_t)i], 0));
+        }
+        HIP_TRY(c0, hipGraphLaunch(exec, c0->stream));
+        HIP_TRY(c0, hipEventRecord(ev[0], c0->stream));
+        for (int i = 0; i < nctx; ++i) {
+            tdgl_ctx *c = ctxs[i];
+            if (i > 0) HIP_TRY(c, hipStreamWaitEvent(c->stream, ev[0], 0));
+            c->cur = cur_after[(size_t)i];
+            c->spec_valid = elec_on(c);
+            HIP_TRY(c, hipMemcpyAsync(&rem[(size_t)i], relax_state(c).remaining, sizeof(int),
+                                      hipMemcpyDeviceToHost, c->stream));
+        }
+        done += nchk * check;
+        remaining = 0;
+        for (int i = 0; i < nctx; ++i) {
+            tdgl_status st = read_flag(ctxs[i]);  // synchronises
+            if (st != TDGL_OK) return st;
+            remaining += rem[(size_t)i];
+        }
+    }
+    long long off = 0, most = 0;
+    for (int i = 0; i < nctx; ++i) {
+        long long taken = 0;
+        tdgl_status st = relax_finish(ctxs[i], relax_step + off, &taken);
+        if (st != TDGL_OK) return st;
+        off += ctxs[i]->g.nb;
+        most = std::max(most, taken);
+    }
+    if (steps_taken) *steps_taken = most;
     return TDGL_OK;
 }
 

@@ -140,6 +140,24 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int zb = (int)(tile / gridDim.x);
     const int z = zb % nz, b = zb / nz, y0 = (int)(tile % gridDim.x) * yt;
+    if constexpr (MODE == UPD_STEP || MODE == UPD_ENERGY) {
+        if (g.frozen && g.frozen[b]) {            // a retired instance (whole group)
+            if constexpr (MODE == UPD_STEP) {     // its state is carried over unchanged
+                const long long cm = (long long)nz * ny * nx;
+                const int nrow = ny - y0 < yt ? ny - y0 : yt;
+                const T *src = reinterpret_cast<const T *>(a.P_in) + 3LL * b * cm;
+                T *dst = reinterpret_cast<T *>(a.P_out) + 3LL * b * cm;
+                const long long base = ((long long)z * ny + y0) * nx;
+                for (int e = threadIdx.x; e < 3 * nrow * nx; e += blockDim.x) {
+                    const int c = e / (nrow * nx), r = e - c * nrow * nx;
+                    dst[c * cm + base + r] = src[c * cm + base + r];
+                }
+            } else if (threadIdx.x < 8) {
+                a.partials[(long long)tile * 8 + threadIdx.x] = 0.0;
+            }
+            return;
+        }
+    }
     // LDS: rows hs[(c*yt + yy)*HS + x] (HS = nx + 2, even, so that (even,
     // odd) sample pairs are 8-byte aligned), then the FFT scratch per line.
     const int HS = nx + 2;
@@ -170,23 +188,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const long long kst = 3LL * g.nb * nz * ny;   // S1 stride between kx
     cpx<T> *s1row = S1 + ((long long)(b * 3 + lc) * nz + z) * ny + y0 + (has ? lyy : 0);
 
-    // ---- prologue: issue the global loads up front
-    TwReg<T, M2> tr;
-    cpx<T> wk[8];                              // W_M^k, k = t + q*TPL
-    if (a.elec_in || do_fx) {
-        twiddle_load(tr, tw + M2, t);
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
-    }
-    // spectrum X[k], k = t + q*TPL, of this thread's row; lane t = 0 also
-    // reads X[M/2]
-    cpx<T> xa[8], xn = {T(0), T(0)};
-    if (a.elec_in) {
-#pragma unroll
-        for (int q = 0; q < PPT; ++q)
-            xa[q] = has ? s1row[(long long)(t + q * TPL) * kst] : cpx<T>{T(0), T(0)};
-        if (has && t == 0) xn = s1row[(long long)M2 * kst];
-    }
+    // ---- prologue: issue the global loads up front, the cells first
     // cells: centre, neighbours (-x +x -y +y -z +z; a missing neighbour is
     // the centre itself, so its difference vanishes), old state
     const int zm = z > 0 ? z - 1 : (g.pz ? nz - 1 : -1);
@@ -234,58 +236,31 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         }
     }
 
-    // ---- 1. electrostatic field rows (inverse x transform, half length)
-    if (a.elec_in) {
-        cpx<T> v[8];
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            // X[M2 - k]: lane TPL - t, point PPT-1-q; for t = 0 it is this
-            // lane's point PPT - q (or X[M2] at q = 0)
-            const int qs = PPT - 1 - q;
-            cpx<T> b = {__shfl(xa[qs].x, partner, 64), __shfl(xa[qs].y, partner, 64)};
-            if (t == 0) b = q == 0 ? xn : xa[(PPT - q) % PPT];
-            cpx<T> A = xa[q];
-            if (t == 0 && q == 0) {                    // X[0], X[M/2] are real
-                A.y = T(0);
-                b.y = T(0);
-            }
-            v[q] = real_merge(A, b, wk[q]);
-        }
-        half_fft<T, M2, true>(v, L, t, tr, lact);
-        if (lact) {
-            T *ha = hs + l * HS;
-#pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                const int n = t + q * TPL;
-                if (2 * n + 1 < nx) {
-                    *reinterpret_cast<cpx<T> *>(ha + 2 * n) = v[q];
-                } else if (2 * n < nx) {
-                    ha[2 * n] = v[q].x;
-                }
-            }
-        }
-        __syncthreads();
-    }
 
-    // ---- 2. local terms and the update
+    // the spectrum X[k], k = t + q*TPL, of this thread's row (lane t = 0 also
+    // reads X[M/2]), issued behind the cell loads: the local terms below wait
+    // for the cells only, the transform for these
+    cpx<T> xa[8], xn = {T(0), T(0)};
+    if (a.elec_in) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            xa[q] = has ? s1row[(long long)(t + q * TPL) * kst] : cpx<T>{T(0), T(0)};
+        if (has && t == 0) xn = s1row[(long long)M2 * kst];
+    }
+    // ---- 0. local terms of every cell (Landau, gradient, cross terms) while
+    // the spectra are still arriving; the neighbours are dead afterwards
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    const T dtau = kp->dtau;
-    T *Pout = reinterpret_cast<T *>(a.P_out) + 3 * b * comp;
+    T Eloc[CPT][3];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
+        T *E = Eloc[i];
+        E[0] = E[1] = E[2] = T(0);
         if (!cok[i]) continue;
-        const int yy = cyy[i], x = cx[i];
         const int off = coff[i];
         const T *p = cp[i];
-        T E[3] = {T(0), T(0), T(0)};
         T sq[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) sq[c] = p[c] * p[c];
-        T hel[3] = {T(0), T(0), T(0)};
-        if (a.elec_in) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) hel[c] = hs[((c << ysh) + yy) * HS + x];
-        }
         T fg = T(0);
         if (material) {
             if (terms & T_LANDAU) {
@@ -325,6 +300,81 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                     for (int c = 0; c < 3; ++c) E[c] += hx[c * comp];
                 }
             }
+        }
+        if constexpr (MODE == UPD_ENERGY) {
+            if (material) {
+                if (terms & T_LANDAU) acc[0] += (double)landau_f(sq, coefz);
+                acc[1] += (double)fg;
+                if (terms & T_EXT)
+                    acc[3] += -((double)p[0] * kp->eext[0] + (double)p[1] * kp->eext[1] +
+                                (double)p[2] * kp->eext[2]);
+                acc[4] += (double)p[0];
+                acc[5] += (double)p[1];
+                acc[6] += (double)p[2];
+            }
+        }
+        (void)fg;
+    }
+
+    // twiddles of the transforms (a small table, cached): loaded here, not in
+    // the prologue, so that they do not occupy registers during the local terms
+    TwReg<T, M2> tr;
+    cpx<T> wk[8];                              // W_M^k, k = t + q*TPL
+    if (a.elec_in || do_fx) {
+        twiddle_load(tr, tw + M2, t);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
+    }
+
+    // ---- 1. electrostatic field rows (inverse x transform, half length)
+    if (a.elec_in) {
+        cpx<T> v[8];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            // X[M2 - k]: lane TPL - t, point PPT-1-q; for t = 0 it is this
+            // lane's point PPT - q (or X[M2] at q = 0)
+            const int qs = PPT - 1 - q;
+            cpx<T> b = {__shfl(xa[qs].x, partner, 64), __shfl(xa[qs].y, partner, 64)};
+            if (t == 0) b = q == 0 ? xn : xa[(PPT - q) % PPT];
+            cpx<T> A = xa[q];
+            if (t == 0 && q == 0) {                    // X[0], X[M/2] are real
+                A.y = T(0);
+                b.y = T(0);
+            }
+            v[q] = real_merge(A, b, wk[q]);
+        }
+        half_fft<T, M2, true>(v, L, t, tr, lact);
+        if (lact) {
+            T *ha = hs + l * HS;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const int n = t + q * TPL;
+                if (2 * n + 1 < nx) {
+                    *reinterpret_cast<cpx<T> *>(ha + 2 * n) = v[q];
+                } else if (2 * n < nx) {
+                    ha[2 * n] = v[q].x;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- 2. the electrostatic and applied fields, and the update
+    const T dtau = kp->dtau;
+    T *Pout = reinterpret_cast<T *>(a.P_out) + 3 * b * comp;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        if (!cok[i]) continue;
+        const int yy = cyy[i], x = cx[i];
+        const int off = coff[i];
+        const T *p = cp[i];
+        T *E = Eloc[i];
+        T hel[3] = {T(0), T(0), T(0)};
+        if (a.elec_in) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hel[c] = hs[((c << ysh) + yy) * HS + x];
+        }
+        if (material) {
             if (a.elec_in) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) E[c] += hel[c];
@@ -410,19 +460,9 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
 #pragma unroll
             for (int c = 0; c < 3; ++c) Pout[c * comp + off] = material ? sc * E[c] : T(0);
         } else {
-            if (material) {
-                if (terms & T_LANDAU) acc[0] += (double)landau_f(sq, coefz);
-                acc[1] += (double)fg;
-                if (a.elec_in)
-                    acc[2] += -0.5 * ((double)p[0] * hel[0] + (double)p[1] * hel[1] +
-                                      (double)p[2] * hel[2]);
-                if (terms & T_EXT)
-                    acc[3] += -((double)p[0] * kp->eext[0] + (double)p[1] * kp->eext[1] +
-                                (double)p[2] * kp->eext[2]);
-                acc[4] += (double)p[0];
-                acc[5] += (double)p[1];
-                acc[6] += (double)p[2];
-            }
+            if (material && a.elec_in)
+                acc[2] += -0.5 * ((double)p[0] * hel[0] + (double)p[1] * hel[1] +
+                                  (double)p[2] * hel[2]);
         }
     }
 
@@ -623,6 +663,7 @@ __global__ void k_cross(const T *__restrict__ P, T *__restrict__ H, Geom g,
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell;
          e += (long long)gridDim.x * blockDim.x) {
         const int b = (int)(e / comp);
+        if (g.frozen && g.frozen[b]) continue;          // retired: its field is not used
         const int off = (int)(e - (long long)b * comp);
         const int z = off / plane, y = (off - z * plane) / nx, x = off - z * plane - y * nx;
         const T *cf = coef + (long long)b * nz * NCOEF;
@@ -751,6 +792,66 @@ hipError_t launch_reduce_energies(const double *partials, int n, int nb, double 
 {
     hipLaunchKernelGGL(k_reduce_energies, dim3(nb), dim3(256), 0, s, partials, n, joule, ncell,
                        P0, out);
+    return hipGetLastError();
+}
+
+// Relaxation test on the device (FP64).  E[b*8 + 4]: total energy of
+// instance b (J, k_reduce_energies).  init: Fprev = F, step = -1, frozen = 0,
+// counter = 0, stopped = -1.  Otherwise, until every instance has relaxed,
+// the step counter advances by `check` and every instance b that has not
+// relaxed yet is tested,
+//   |F_b - Fprev_b| < rtol * max(|F_b|, floor),
+// and on success gets step_b = counter (frozen_b = 1 if retire); Fprev_b = F_b.
+// remaining = number of instances with step < 0; when it reaches 0, stopped =
+// counter and every instance is frozen, so later launches change nothing.
+__global__ void k_relax_test(const double *__restrict__ E, RelaxState r, int nb, int init,
+                             long long check, double rtol, double floor, int retire)
+{
+    __shared__ int cnt[256];
+    const int tid = threadIdx.x;
+    if (!init && r.stopped[0] >= 0) return;
+    const long long n = init ? 0 : r.counter[0] + check;
+    int left = 0;
+    for (int b = tid; b < nb; b += 256) {
+        const double F = E[(long long)b * 8 + 4];
+        if (init) {
+            r.step[b] = -1;
+            r.frozen[b] = 0;
+            ++left;
+        } else if (r.step[b] < 0) {
+            const double dF = fabs(F - r.Fprev[b]);
+            const double sc = fabs(F) > floor ? fabs(F) : floor;
+            if (dF < rtol * sc) {
+                r.step[b] = n;
+                if (retire) r.frozen[b] = 1;
+            } else {
+                ++left;
+            }
+        }
+        r.Fprev[b] = F;
+    }
+    cnt[tid] = left;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) cnt[tid] += cnt[tid + w];
+        __syncthreads();
+    }
+    const int total = cnt[0];
+    if (!init && total == 0)
+        for (int b = tid; b < nb; b += 256) r.frozen[b] = 1;
+    if (tid == 0) {
+        r.remaining[0] = total;
+        r.counter[0] = n;
+        r.stopped[0] = (!init && total == 0) ? n : -1;
+    }
+}
+
+hipError_t launch_relax_test(const double *E, const RelaxState &r, int nb, bool init,
+                             long long check, double rtol, double floor, bool retire,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_relax_test, dim3(1), dim3(256), 0, s, E, r, nb, init ? 1 : 0, check,
+                       rtol, floor, retire ? 1 : 0);
     return hipGetLastError();
 }
 

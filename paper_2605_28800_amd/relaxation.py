@@ -1,10 +1,10 @@
 """Relaxation drivers on the C ABI: batched TDGL relaxation to the energy
 criterion, and the training loop of the initial-state proposal network.
 
-Host-side control only: the steps, energies, network passes and Adam
-updates run in libtdgl's kernels.  "Relaxed" means the total free energy
-changed by less than 1e-6 of max(|F|, floor) over the last `check` steps,
-tested every `check` steps on each instance.
+Host-side control only: the steps, energies, relaxation test, network
+passes and Adam updates run in libtdgl's kernels.  "Relaxed" means the total
+free energy changed by less than 1e-6 of max(|F|, floor) over the last
+`check` steps, tested every `check` steps on each instance (tdgl_relax).
 """
 from __future__ import annotations
 
@@ -24,24 +24,15 @@ def relax_floor(cfg):
     return s["alpha_ref"] * s["P0"] ** 2 * 1e-3 * n * dv
 
 
-def relax(ctx, floor, check=100, max_steps=20000):
-    """Step a batch context until every instance has relaxed or max_steps.
+def relax(ctx, check=100, max_steps=20000, retire=False):
+    """Step a batch context until every instance has relaxed or max_steps
+    (tdgl_relax with rtol 1e-6 and the floor alpha_ref P0^2 1e-3 V).
     Returns (relax step per instance, -1 if not relaxed; steps taken)."""
-    f_prev = ctx.energies_batch()[0][:, 4].copy()
-    done = np.full(len(f_prev), -1)
-    steps = 0
-    while steps < max_steps and (done < 0).any():
-        ctx.step(check)
-        steps += check
-        f = ctx.energies_batch()[0][:, 4]
-        ok = np.abs(f - f_prev) < 1e-6 * np.maximum(np.abs(f), floor)
-        done[(done < 0) & ok] = steps
-        f_prev = f.copy()
-    return done, steps
+    return ctx.relax(check, max_steps, 1e-6, 1e-3, retire)
 
 
 def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=256,
-                  tune_steps=100, log=None):
+                  tune_steps=100, log=None, retire=False):
     """Relax samples that share a recipe per key (e.g. film thickness) in
     batches of at most group_max.
 
@@ -53,7 +44,8 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
     stepping (set-up excluded) and, per sample, its time to relaxed: its
     relax step count times its batch's measured time per step and instance
     (the cap for samples that did not relax).  log(message), if given, hears
-    of each finished group."""
+    of each finished group.  retire: relaxed samples stop advancing (their
+    state is the one that met the criterion)."""
     import torch
     keys = np.asarray(keys)
     n = len(keys)
@@ -78,7 +70,7 @@ def relax_grouped(recipe, keys, T, start, check=100, max_steps=20000, group_max=
                     ctx.set_P(start.index_select(0, ridx).contiguous())
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                done, taken = relax(ctx, relax_floor(cfg), check, max_steps)
+                done, taken = relax(ctx, check, max_steps, retire=retire)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 seconds += dt
@@ -164,7 +156,7 @@ def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_tra
                    for a in (T, thick, noise))
     tr, te = np.arange(n_train), np.arange(n_train, n)
     P_tr, s_tr, F_tr, t_data, _ = relax_grouped(recipe, thick[tr], T[tr], starts[:n_train],
-                                                check, data_steps, log=log)
+                                                check, data_steps, log=log, retire=True)
     target = torch.zeros((n, 3) + tuple(shape), dtype=torch.float32, device=starts.device)
     target[:n_train] = P_tr
     net = Net(shape, width=width, noise_div=noise_div, max_batch=batch)
@@ -184,9 +176,9 @@ def proposal_experiment(recipe, shape, noise_div, T, thick, noise, starts, n_tra
     finally:
         net.close()
     P_pl, s_pl, F_pl, t_pl, i_pl = relax_grouped(recipe, thick[te], T[te], starts[n_train:],
-                                                 check, eval_steps, log=log)
+                                                 check, eval_steps, log=log, retire=True)
     P_pr, s_pr, F_pr, t_pr, i_pr = relax_grouped(recipe, thick[te], T[te], prop, check,
-                                                 eval_steps, log=log)
+                                                 eval_steps, log=log, retire=True)
     floor = np.array([relax_floor(recipe(k)) for k in thick[te]])
     dP = [(torch.linalg.norm(P_pr[i] - P_pl[i]) / max(torch.linalg.norm(P_pl[i]).item(), 1e-30)).item()
           for i in range(len(te))]

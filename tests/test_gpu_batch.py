@@ -1,12 +1,14 @@
 """Batched contexts: nbatch instances of one grid advanced by the same
 launches give, instance by instance, exactly the results of separate
-contexts (same kernels, same arithmetic, other indices)."""
+contexts (same kernels, same arithmetic, other indices), and each instance
+follows the oracle's run at its own temperature."""
 import numpy as np
 import pytest
 
 import paper_2605_28800_amd as T
 import tdgl_inputs as I
-from tests.gpu_helpers import PREC, announce, gpu_context
+from oracle import tdgl_oracle as O
+from tests.gpu_helpers import PREC, announce, gpu_context, ps_of
 from tests.test_gpu_parity import CASES, _cfg
 
 pytestmark = pytest.mark.gpu
@@ -118,3 +120,37 @@ def test_autotune_restores_state_and_keeps_its_choice():
     finally:
         ref.close()
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_batch_against_oracle_fp64(path):
+    """Three instances of the 16x16x8 box at 250, 300 and 350 K (one shared
+    alpha_ref, per-instance coefficients) advanced by one batched context,
+    each against the oracle's own run at its temperature: 200 Heun steps,
+    |dP|/Ps <= 1e-12, energies to 1e-12 of their scale."""
+    cfg = I.config("c1")
+    cfg["scheme"] = "heun"
+    temps = [250.0, 300.0, 350.0]
+    Ps = [I.initial_P(cfg, 20 + s) for s in range(3)]
+    announce("batch of 3 c1 fp64 vs oracle, path %d" % path)
+    ctx = _batch_context(cfg, "f64", 3, temps, path)
+    try:
+        ctx.set_P(np.stack(Ps))
+        ctx.step(200)
+        Fb, mb = ctx.energies_batch()
+        Pb = ctx.get_P(T.TDGL_FP64)
+    finally:
+        ctx.close()
+    for b in range(3):
+        c = dict(cfg)
+        c["T"] = temps[b]
+        prob = O.Problem(c)
+        ref = O.run(Ps[b], prob, "heun", cfg["dtau"], 200)
+        err = np.abs(Pb[b] - ref).max() / ps_of(c)
+        assert err <= 1e-12, (b, err)
+        E = O.energies(ref, prob)
+        want = [E[k] * prob.energy_scale for k in ("F_land", "F_grad", "F_elec", "F_ext",
+                                                  "F_total")]
+        scale = max(abs(v) for v in want)
+        assert np.abs(np.array(Fb[b]) - want).max() <= 1e-12 * scale, (b, Fb[b], want)
+        assert np.abs(np.array(mb[b]) - E["meanP"] * prob.P0).max() <= 1e-14

@@ -1,0 +1,92 @@
+"""Section 4.2 on the GPU: 1500 single BaTiO3 cells per temperature, the
+Landau energy only (eq 3), random starts of random orientation and
+magnitude up to 1e-3 C/m^2, relaxed as one batch per temperature.
+
+Every final state must be one of the 26 stationary orientations of the
+three phases (tetragonal <100>, orthorhombic <110>, rhombohedral <111>)
+with the magnitude of that phase's closed-form root of eq 12 (FP64, to
+1e-9), and the phase counts must follow the paper's description: all
+rhombohedral at low temperature, the orthorhombic phase dominant near
+250 K with almost no rhombohedral states, all tetragonal above 300 K, and
+the minima of the dominant phase all reached.
+"""
+import numpy as np
+import pytest
+
+import paper_2605_28800_amd as T
+import tdgl_inputs as I
+from tests.gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+
+NSTART = 1500
+
+
+def _roots(temp):
+    """Component magnitude p of the tetragonal (p,0,0), orthorhombic (p,p,0)
+    and rhombohedral (p,p,p) roots of eq 12: with x = p^2 the Landau energy
+    along the phase is a x + b x^2 + c x^3 and x solves a + 2 b x + 3 c x^2 = 0
+    (|P| = sqrt(k) p for k nonzero components)."""
+    m = I.BATIO3
+    a1 = m["a1_slope"] * (temp - m["a1_T0"])
+    a11 = m["a11_slope"] * (temp - m["a11_Tref"]) + m["a11_offset"]
+    a111 = m["a111_slope"] * (temp - m["a111_Tref"]) + m["a111_offset"]
+    a12, a112, a123 = m["a12"], m["a112"], m["a123"]
+    abc = {1: (a1, a11, a111),
+           2: (2 * a1, 2 * a11 + a12, 2 * a111 + 2 * a112),
+           3: (3 * a1, 3 * a11 + 3 * a12, 3 * a111 + 6 * a112 + a123)}
+    out = {}
+    for k, (a, b, c) in abc.items():
+        disc = b * b - 3 * a * c
+        x = (-b + np.sqrt(disc)) / (3 * c) if disc > 0 else -1.0
+        out[k] = np.sqrt(x) if x > 0 else None
+    return out
+
+
+def _relax_cells(temp):
+    cfg = I.config("c1")
+    cfg.update(n=(1, 1, 1), layers=[0], terms=T.TDGL_LANDAU, scheme="heun", dtau=1e-3,
+               T=[temp] * NSTART, init=dict(kind="random_dir", amp=1e-3))
+    P = np.stack([I.initial_P(cfg, 1000 + s) for s in range(NSTART)])
+    ctx = T.Context(cfg, T.TDGL_FP64, batch=NSTART)
+    try:
+        ctx.set_P(P)
+        steps, taken = ctx.relax(100, 400000, rtol=1e-12)
+        Pf = ctx.get_P(T.TDGL_FP64).reshape(NSTART, 3)
+    finally:
+        ctx.close()
+    return steps, Pf
+
+
+@pytest.mark.timeout(900)
+def test_single_cell_phase_statistics_follow_section_4_2():
+    counts = {}
+    for temp in (50.0, 150.0, 250.0, 300.0, 350.0):
+        announce("1500 single cells at %.0f K, Landau only" % temp)
+        steps, Pf = _relax_cells(temp)
+        assert (steps > 0).all(), (temp, (steps < 0).sum())
+        roots = _roots(temp)
+        mag = np.abs(Pf)
+        big = mag > 0.5 * mag.max(axis=1, keepdims=True)
+        ncomp = big.sum(axis=1)                 # 1: T <100>, 2: O <110>, 3: R <111>
+        found = {}
+        for k, name in ((1, "T"), (2, "O"), (3, "R")):
+            sel = ncomp == k
+            found[name] = int(sel.sum())
+            if not sel.any():
+                continue
+            assert roots[k] is not None, (temp, name)
+            # the nonzero components equal the root p, the others vanish
+            assert np.abs(mag[sel][big[sel]] / roots[k] - 1).max() < 1e-9, (temp, name)
+            assert np.abs(mag[sel][~big[sel]]).max(initial=0.0) < 1e-9, (temp, name)
+            # orientations reached: sign patterns of the nonzero components
+            keys = {tuple(np.sign(p) * b) for p, b in zip(Pf[sel], big[sel])}
+            found[name + "_orientations"] = len(keys)
+        counts[temp] = found
+        print("%.0f K: %s" % (temp, found))
+    assert counts[50.0]["R"] == NSTART and counts[50.0]["R_orientations"] == 8
+    assert counts[350.0]["T"] == NSTART and counts[350.0]["T_orientations"] == 6
+    c250 = counts[250.0]
+    assert c250["O"] > max(c250["R"], c250["T"]) and c250["R"] <= 0.05 * NSTART
+    assert c250["O_orientations"] == 12
+    assert counts[150.0]["R"] > 0 and counts[300.0]["T"] > counts[300.0]["O"]

@@ -7,8 +7,12 @@ most 8000 steps, 32 held-out samples): relax the training starts into a
 dataset, train the network on the GPU through the library's own kernels on
 the states that relaxed (no symmetry augmentation: with this few states it
 lowers the gain), then relax the held-out samples from their random starts
-and from the network's proposals to the same energy criterion.  The run is seeded and the kernels are
-deterministic, so the numbers repeat on the same build."""
+and from the network's proposals to the same energy criterion (relaxed
+instances retired, so each ends in the state it relaxed in).  The gain is
+asserted over all held-out samples and over those where the proposal-started
+run ends at an equal (within 1e-6) or lower energy than the plain run.  The
+run is seeded and the kernels are deterministic, so the numbers repeat on
+the same build."""
 import numpy as np
 import pytest
 
@@ -42,3 +46,13 @@ def test_trained_proposal_relaxes_in_fewer_steps():
     assert np.isfinite(r["losses"]).all() and r["losses"][-20:].mean() < r["losses"][:20].mean()
     assert (r["proposal_steps"] > 0).sum() >= (r["plain_steps"] > 0).sum()
     assert prop.mean() < 0.85 * plain.mean()
+    # at equal final-energy accuracy: the samples whose proposal-started run
+    # ends within 1e-6 of, or below, the plain run's energy, both relaxed
+    dF = (r["proposal_F"] - r["plain_F"]) / np.maximum(np.abs(r["plain_F"]), r["energy_floor"])
+    m = (dF <= 1e-6) & (r["plain_steps"] > 0) & (r["proposal_steps"] > 0)
+    print("[gain at equal energy] %d samples: plain mean %.0f, proposal mean %.0f"
+          % (m.sum(), r["plain_steps"][m].mean(), r["proposal_steps"][m].mean()), flush=True)
+    # (measured: 15 of 32 samples, 8333 -> 6687 steps; the rest end in another
+    # minimum, mostly at a higher energy)
+    assert m.sum() >= n_test // 4
+    assert r["proposal_steps"][m].mean() < 0.85 * r["plain_steps"][m].mean()

@@ -251,3 +251,49 @@ def test_graph_cache_follows_term_and_gradient_changes():
     err = np.abs(got - ref).max() / ps_of(cfg)
     print("max |dP|/Ps = %.3e" % err)
     assert err < 1e-12, err
+
+
+def test_integrator_buffers_live_in_the_bound_workspace():
+    """The RK45 stage buffers and the AB3M2 history come from a bound
+    workspace sized after the integrator is set; a workspace sized for Heun
+    refuses a later switch to RK45 with TDGL_E_STATE and stays usable."""
+    cfg = I.config("c1")
+    cfg["n"] = (8, 8, 4)
+    cfg["layers"] = [0] * 4
+    P0 = I.initial_P(cfg, 2)
+    announce("integrator buffers in the bound workspace")
+    sizes = {}
+    for scheme in ("heun", "ab3m2", "rk45"):
+        c = dict(cfg, scheme=scheme)
+        ctx = gpu_context(c, "f64")
+        try:
+            sizes[scheme] = T.tdgl_workspace_size(ctx.ctx)
+            ctx.set_P(P0)
+            ctx.step(5)
+            got = ctx.get_P()
+        finally:
+            ctx.close()
+        prob = O.Problem(c)
+        if scheme == "rk45":
+            ref = O.run_rk45(P0, prob, c["dtau"], 5, 1e-8, 1e-6)[0]
+        else:
+            ref = O.run(P0, prob, scheme, c["dtau"], 5)
+        assert np.abs(got - ref).max() / ps_of(c) <= 1e-12, scheme
+    pbytes = 3 * 8 * 8 * 4 * 8
+    assert sizes["ab3m2"] - sizes["heun"] >= 3 * pbytes
+    assert sizes["rk45"] - sizes["heun"] >= 8 * pbytes
+    ctx = gpu_context(dict(cfg, scheme="heun"), "f64")
+    try:
+        ctx.set_P(P0)
+        ctx.step(2)
+        T.tdgl_set_integrator(ctx.ctx, T.TDGL_RK45, 1e-3)
+        with pytest.raises(T.TdglError) as ei:
+            ctx.step(1)
+        assert ei.value.status == T.TDGL_E_STATE
+        T.tdgl_set_integrator(ctx.ctx, T.TDGL_HEUN, 1e-3)
+        ctx.step(3)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    ref = O.run(P0, O.Problem(dict(cfg, scheme="heun")), "heun", cfg["dtau"], 5)
+    assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-12
