@@ -106,18 +106,29 @@ __device__ __forceinline__ void dftR(cpx<T> *v)
     else dft2<T, INV>(v);
 }
 
-// LDS index policies for one line's scratch.
+// LDS index policies for one line's scratch.  Besides the index of element
+// e, each gives the index difference idx(e + d) - idx(e) for a displacement
+// d that is a multiple of 8 (shift) and for 0 <= d < 8 from an e that is a
+// multiple of 8 (near): the stages form one base index per butterfly and
+// reach its R elements by constant offsets, which fold into the LDS
+// instructions' immediate offsets.
 struct IdxStride {      // element e of the line at e * s (lines interleaved)
     int s;
     __device__ __forceinline__ int operator()(int e) const { return e * s; }
+    __device__ __forceinline__ int shift(int d) const { return d * s; }
+    __device__ __forceinline__ int near(int d) const { return d * s; }
 };
 struct IdxPad {         // contiguous line, one pad slot after every 8 elements
     __device__ __forceinline__ int operator()(int e) const { return e + (e >> 3); }
+    __device__ __forceinline__ int shift(int d) const { return d + (d >> 3); }
+    __device__ __forceinline__ int near(int d) const { return d; }
 };
 struct IdxStridePad {   // lines interleaved at stride s, one pad row after every 8
     int s;              // elements: 64 lanes of 8-byte accesses hit the minimum of
                         // two LDS bank cycles in every radix stage
     __device__ __forceinline__ int operator()(int e) const { return (e + (e >> 3)) * s; }
+    __device__ __forceinline__ int shift(int d) const { return (d + (d >> 3)) * s; }
+    __device__ __forceinline__ int near(int d) const { return d * s; }
 };
 
 template <int M>
@@ -188,13 +199,25 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx,
     constexpr int R = St::R, NB = St::NB, P = St::P;
     constexpr int TPL = M / 8;
     constexpr int MR = M / R;
+    // element i + d of a read, j + r P of a write: constant offsets from one
+    // base index when the displacements are multiples of 8
+    constexpr bool FAST_READ = TPL % 8 == 0 && MR % 8 == 0;
+    constexpr bool FAST_WRITE = P % 8 == 0;
     __syncthreads();
     if (act) {
+        if constexpr (FAST_READ) {
+            const int f0 = idx(t);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int i = t + b * TPL;
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b * R + r] = lds[idx(i + r * MR)];
+                for (int r = 0; r < R; ++r) v[b * R + r] = lds[f0 + idx.shift(b * TPL + r * MR)];
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int i = t + b * TPL;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b * R + r] = lds[idx(i + r * MR)];
+            }
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -224,8 +247,14 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx,
                 const int i = t + b * TPL;
                 const int k = i & (P - 1);
                 const int j = (i - k) * R + k;
+                if constexpr (FAST_WRITE) {
+                    const int fj = idx(j);
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[idx(j + r * P)] = v[b * R + r];
+                    for (int r = 0; r < R; ++r) lds[fj + idx.shift(r * P)] = v[b * R + r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) lds[idx(j + r * P)] = v[b * R + r];
+                }
             }
         }
         fft_stages<T, M, S + 1, INV, Idx>(v, lds, idx, t, tr, act);
@@ -244,11 +273,30 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, i
     if (act) dft8<T, INV>(v);
     if constexpr (M > 8) {
         if (act) {
+            const int f8 = idx(8 * t);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) lds[idx(8 * t + r)] = v[r];
+            for (int r = 0; r < 8; ++r) lds[f8 + idx.near(r)] = v[r];
         }
         fft_stages<T, M, 1, INV, Idx>(v, lds, idx, t, tr, act);
     }
+}
+
+// Quotient n / d of uniform operands through d's magic number m =
+// ceil(2^32 / d) (div_magic on the host; 0 for d = 1): one scalar high
+// multiply instead of the vector division sequence.  Exact while n * d < 2^32;
+// the launchers check that bound and pass m = DIV_SLOW otherwise.
+constexpr unsigned DIV_SLOW = 0xffffffffu;
+__host__ __device__ __forceinline__ unsigned div_magic(unsigned d, unsigned long long nmax)
+{
+    if (d <= 1) return 0u;
+    if (nmax * d >= (1ULL << 32)) return DIV_SLOW;
+    return (unsigned)(((1ULL << 32) + d - 1) / d);
+}
+__device__ __forceinline__ unsigned udiv(unsigned n, unsigned d, unsigned m)
+{
+    if (m == 0u) return n;
+    if (m == DIV_SLOW) return n / d;
+    return __umulhi(n, m);
 }
 
 // Work-groups of a launch are dealt round-robin to the eight XCDs of the

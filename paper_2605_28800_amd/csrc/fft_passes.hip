@@ -89,7 +89,10 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
 // ---------------------------------------------------------- row pass
 // Line r: n_in points at in + r*in_stride, n_out points to out + r*out_stride.
 // In-place use is safe (each thread stores exactly the positions it loaded).
-template <typename T, int M, bool INV>
+// HALF: n_in == M/2 for a forward pass, n_out == M/2 for an inverse one (an
+// open dimension padded to twice its length): the zero inputs or the
+// discarded outputs are known at compile time and their arithmetic drops out.
+template <typename T, int M, bool INV, bool HALF>
 __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long in_stride,
                       long long out_stride, int n_in, int n_out, const cpx<T> *__restrict__ tw,
                       int lpw, Freeze fz)
@@ -109,14 +112,16 @@ __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int e = t + q * TPL;
-        v[q] = (act && e < n_in) ? src[e] : cpx<T>{T(0), T(0)};
+        const bool in_ok = (HALF && !INV) ? q < 4 : e < n_in;
+        v[q] = (act && in_ok) ? src[e] : cpx<T>{T(0), T(0)};
     }
     fft_line<T, M, INV>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr, act);
     cpx<T> *dst = out + (act ? line : 0) * out_stride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int e = t + q * TPL;
-        if (act && e < n_out) dst[e] = v[q];
+        const bool out_ok = (HALF && INV) ? q < 4 : e < n_out;
+        if (act && out_ok) dst[e] = v[q];
     }
 }
 
@@ -210,10 +215,15 @@ struct ZmulCfg {
     static constexpr int NTHR = 3 * CT * TPL;
 };
 
-template <typename T, int MZ>
+// HALF: nz == MZ/2 (an open dimension padded to twice its length): the upper
+// half of the forward transform's inputs is zero and the upper half of the
+// inverse transform's outputs is discarded, both known at compile time, so
+// their arithmetic drops out.
+template <typename T, int MZ, bool HALF>
 __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int nb,
-           const cpx<T> *__restrict__ tw, const int *__restrict__ frozen)
+           const cpx<T> *__restrict__ tw, const int *__restrict__ frozen, unsigned mgx,
+           unsigned mnb)
 {
     using C = ZmulCfg<T, MZ>;
     constexpr int TPL = C::TPL, CT = C::CT;
@@ -225,10 +235,10 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     const int t = (tid / CT) % TPL;
     const int c = tid / (CT * TPL);
     const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const int kxb = (int)(tile / gridDim.x);        // plane (kx, instance)
-    if (frozen && frozen[kxb % nb]) return;         // the whole group: one instance
-    const int kx = kxb / nb;
-    const int ky = (int)(tile % gridDim.x) * CT + cc;
+    const unsigned kxb = udiv(tile, gridDim.x, mgx);           // plane (kx, instance)
+    const unsigned kx = udiv(kxb, (unsigned)nb, mnb);
+    if (frozen && frozen[kxb - kx * nb]) return;    // the whole group: one instance
+    const int ky = (int)(tile - kxb * gridDim.x) * CT + cc;
     const bool act = ky < my;
     const int kyc = act ? ky : 0;
     // uniform bases, unsigned 32-bit offsets within one kx plane
@@ -243,7 +253,8 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
-        v[q] = (act && z < nz) ? plane[col + (unsigned)z * my] : cpx<T>{T(0), T(0)};
+        const bool in = HALF ? q < 4 : z < nz;
+        v[q] = (act && in) ? plane[col + (unsigned)z * my] : cpx<T>{T(0), T(0)};
     }
     // row c of the tensor: components (c,x) (c,y) (c,z) of the octant store
     // Nt[kx][comp][kz'][ky'] (comp: xx yy zz xy xz yz); xy is odd in ky, xz
@@ -272,19 +283,25 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     const IdxStridePad ip{CT};
     cpx<T> *L = lds + c * LZ * CT + cc;
     fft_line<T, MZ, false>(v, L, ip, t, tr, act);
+    // element kz = t + q*TPL of a line sits at ip(t) + ip.shift(q*TPL) when
+    // TPL is a multiple of 8 (a constant offset per q)
+    auto ipq = [&](int q) {
+        if constexpr (TPL % 8 == 0) return ip(t) + ip.shift(q * TPL);
+        else return ip(t + q * TPL);
+    };
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) L[ip(t + q * TPL)] = v[q];
+        for (int q = 0; q < 8; ++q) L[ipq(q)] = v[q];
     }
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int kz = t + q * TPL;
-            const cpx<T> p0 = lds[0 * LZ * CT + ip(kz) + cc];
-            const cpx<T> p1 = lds[1 * LZ * CT + ip(kz) + cc];
-            const cpx<T> p2 = lds[2 * LZ * CT + ip(kz) + cc];
+            const int o = ipq(q) + cc;
+            const cpx<T> p0 = lds[0 * LZ * CT + o];
+            const cpx<T> p1 = lds[1 * LZ * CT + o];
+            const cpx<T> p2 = lds[2 * LZ * CT + o];
             const T n0 = nrow[q][0], n1 = nrow[q][1], n2 = nrow[q][2];
             v[q] = {n0 * p0.x + n1 * p1.x + n2 * p2.x, n0 * p0.y + n1 * p1.y + n2 * p2.y};
         }
@@ -294,7 +311,8 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
-        if (act && z < nz) plane[col + (unsigned)z * my] = v[q];
+        const bool out = HALF ? q < 4 : z < nz;
+        if (act && out) plane[col + (unsigned)z * my] = v[q];
     }
 }
 
@@ -484,14 +502,24 @@ static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines
     const long long blocks = (nlines + lpw - 1) / lpw;
     if (blocks <= 0) return hipSuccess;
     const size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
-    if (inv)
-        hipLaunchKernelGGL((k_row<T, M, true>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
-                           (const cpx<T> *)in, (cpx<T> *)out, nlines, in_stride, out_stride,
-                           n_in, n_out, (const cpx<T> *)tw + M, lpw, fz);
+    const dim3 grid((unsigned)blocks), blk(lpw * TPL);
+    const cpx<T> *ci = (const cpx<T> *)in;
+    cpx<T> *co = (cpx<T> *)out;
+    const cpx<T> *twm = (const cpx<T> *)tw + M;
+    // (the HALF forms need M >= 16: 8 points per thread, the upper 4 zero)
+    const bool half = M >= 16 && (inv ? (n_out == M / 2 && n_in == M) : (n_in == M / 2));
+    if (inv && half)
+        hipLaunchKernelGGL((k_row<T, M, true, true>), grid, blk, shm, s, ci, co, nlines,
+                           in_stride, out_stride, n_in, n_out, twm, lpw, fz);
+    else if (inv)
+        hipLaunchKernelGGL((k_row<T, M, true, false>), grid, blk, shm, s, ci, co, nlines,
+                           in_stride, out_stride, n_in, n_out, twm, lpw, fz);
+    else if (half)
+        hipLaunchKernelGGL((k_row<T, M, false, true>), grid, blk, shm, s, ci, co, nlines,
+                           in_stride, out_stride, n_in, n_out, twm, lpw, fz);
     else
-        hipLaunchKernelGGL((k_row<T, M, false>), dim3((unsigned)blocks), dim3(lpw * TPL), shm,
-                           s, (const cpx<T> *)in, (cpx<T> *)out, nlines, in_stride, out_stride,
-                           n_in, n_out, (const cpx<T> *)tw + M, lpw, fz);
+        hipLaunchKernelGGL((k_row<T, M, false, false>), grid, blk, shm, s, ci, co, nlines,
+                           in_stride, out_stride, n_in, n_out, twm, lpw, fz);
     return hipGetLastError();
 }
 
@@ -567,9 +595,17 @@ static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *
     const int gx = (g.my + C::CT - 1) / C::CT;
     if ((long long)g.hx * g.nb > 65535) return hipErrorInvalidValue;
     const size_t shm = (size_t)3 * C::CT * LinePad<MZ>::len * sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_zmul<T, MZ>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm, s,
-                       (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb, (const cpx<T> *)tw + MZ,
-                       g.frozen);
+    const unsigned long long ntile = (unsigned long long)gx * g.hx * g.nb;
+    const unsigned mgx = div_magic((unsigned)gx, ntile);
+    const unsigned mnb = div_magic((unsigned)g.nb, (unsigned long long)g.hx * g.nb);
+    if (2 * g.nz == MZ)
+        hipLaunchKernelGGL((k_zmul<T, MZ, true>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm, s,
+                           (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb,
+                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb);
+    else
+        hipLaunchKernelGGL((k_zmul<T, MZ, false>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm,
+                           s, (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb,
+                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb);
     return hipGetLastError();
 }
 

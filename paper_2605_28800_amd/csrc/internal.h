@@ -81,6 +81,7 @@ struct UpdArgs {
     double rk_h;           // STEP_RK: step size
     double rk_atol, rk_rtol;
     const void *cross;     // field of the gradient cross terms (k_cross), or null
+    unsigned mgx, mnz;     // magic numbers of the launch's grid divisions (set by the launcher)
 };
 
 // field of the cross terms of the gradient energy (G12, G44 - G44') of P

@@ -138,8 +138,9 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     // tile = (instance b, layer z, row group), instance-major
     const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int zb = (int)(tile / gridDim.x);
-    const int z = zb % nz, b = zb / nz, y0 = (int)(tile % gridDim.x) * yt;
+    const unsigned zb = udiv(tile, gridDim.x, a.mgx);
+    const unsigned bq = udiv(zb, (unsigned)nz, a.mnz);
+    const int z = (int)(zb - bq * nz), b = (int)bq, y0 = (int)(tile - zb * gridDim.x) * yt;
     if constexpr (MODE == UPD_STEP || MODE == UPD_ENERGY) {
         if (g.frozen && g.frozen[b]) {            // a retired instance (whole group)
             if constexpr (MODE == UPD_STEP) {     // its state is carried over unchanged
@@ -190,12 +191,13 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
 
     // ---- prologue: issue the global loads up front, the cells first
     // cells: centre, neighbours (-x +x -y +y -z +z; a missing neighbour is
-    // the centre itself, so its difference vanishes), old state
+    // the centre itself, so its difference vanishes), old state.  Nothing
+    // here waits for a loaded value: the z neighbours are the geometric ones
+    // and a vacuum neighbour layer is dropped afterwards (hzm, hzp), so the
+    // layer flags arrive while the cells do
     const int zm = z > 0 ? z - 1 : (g.pz ? nz - 1 : -1);
     const int zp = z < nz - 1 ? z + 1 : (g.pz ? 0 : -1);
-    const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
-    const bool hzp = zp >= 0 && coef0[(long long)zp * NCOEF + 8] != T(0);
-    const bool need_nb = material && (terms & T_GRAD);
+    const bool need_nb = (terms & T_GRAD) != 0;
     const bool need_old = (MODE == UPD_STEP && a.stage == 1) || (MODE == UPD_STEP_MS && a.stage == 3);
     const T *Pin0 = reinterpret_cast<const T *>(a.P_in) + 3 * b * comp;
     const T *Pold0 = a.P_old ? reinterpret_cast<const T *>(a.P_old) + 3 * b * comp : nullptr;
@@ -222,8 +224,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             const int xp = xc < nx - 1 ? off + 1 : (g.px ? off - nx + 1 : off);
             const int ym = yc > 0 ? off - nx : (g.py ? off + plane - nx : off);
             const int yp = yc < ny - 1 ? off + nx : (g.py ? off - plane + nx : off);
-            const int zmo = hzm ? off + (zm - z) * plane : off;
-            const int zpo = hzp ? off + (zp - z) * plane : off;
+            const int zmo = zm >= 0 ? off + (zm - z) * plane : off;
+            const int zpo = zp >= 0 ? off + (zp - z) * plane : off;
             const int nb[6] = {xm, xp, ym, yp, zmo, zpo};
 #pragma unroll
             for (int d = 0; d < 6; ++d)
@@ -246,6 +248,18 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         for (int q = 0; q < PPT; ++q)
             xa[q] = has ? s1row[(long long)(t + q * TPL) * kst] : cpx<T>{T(0), T(0)};
         if (has && t == 0) xn = s1row[(long long)M2 * kst];
+    }
+    // z neighbours in vacuum layers are dropped (they read as the centre)
+    const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
+    const bool hzp = zp >= 0 && coef0[(long long)zp * NCOEF + 8] != T(0);
+    if (need_nb) {
+#pragma unroll
+        for (int i = 0; i < CPT; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!hzm) cn[i][4][c] = cp[i][c];
+                if (!hzp) cn[i][5][c] = cp[i][c];
+            }
     }
     // ---- 0. local terms of every cell (Landau, gradient, cross terms) while
     // the spectra are still arriving; the neighbours are dead afterwards
@@ -612,7 +626,10 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
     if ((long long)g.nz * g.nb > 65535) return hipErrorInvalidValue;
     dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz * g.nb);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
-    hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, a, g,
+    UpdArgs am = a;
+    am.mgx = div_magic(grid.x, (unsigned long long)grid.x * grid.y);
+    am.mnz = div_magic((unsigned)g.nz, (unsigned long long)g.nz * g.nb);
+    hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, am, g,
                        (const cpx<T> *)tw);
     return hipGetLastError();
 }
