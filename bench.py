@@ -137,10 +137,10 @@ def copy_calibration(mib=256, reps=3):
 
 
 KERNEL_KEYS = {        # rocprofv3 kernel-name fragments of the step kernels
-    "y_forward": "k_row<float, 128, false>",
-    "z_tensor": "k_zmul<float, 64>",
-    "y_inverse": "k_row<float, 128, true>",
-    "update": "k_update<float, 128, 0>",
+    "y_forward": "k_rowb<float, 128, false,",
+    "z_tensor": "k_zmul<float, 64,",
+    "y_inverse": "k_rowb<float, 128, true,",
+    "update": "k_update<float, 128, 0,",
 }
 
 

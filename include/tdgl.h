@@ -249,6 +249,23 @@ tdgl_status tdgl_get_fft_path(const tdgl_ctx *ctx, int *fused);
  * fail with TDGL_E_HIP at the next step. */
 tdgl_status tdgl_set_update_rows(tdgl_ctx *ctx, int rows);
 
+/* Column tile of the z pass: bytes of each z row a work-group loads (64,
+ * 128 or 256; 0 restores the built-in choice: 128, or 64 where that leaves
+ * fewer than 1024 work-groups).  A tuning knob: results do not depend on
+ * it.  tdgl_get_z_tile reports the tile in use (the built-in choice
+ * resolved). */
+tdgl_status tdgl_set_z_tile(tdgl_ctx *ctx, int row_bytes);
+tdgl_status tdgl_get_z_tile(const tdgl_ctx *ctx, int *row_bytes);
+
+/* How the step kernels store the spectra and states that the next kernel
+ * reads: 1 non-temporal (streamed past the L2), 2 plain, 0 the built-in
+ * choice (non-temporal for a single instance, plain for a batch, as measured
+ * on the 128x128x32 film, the 256x256x64 bilayer and batches of small boxes).
+ * A tuning knob: results do not depend on it.  tdgl_get_store_mode reports
+ * 1 or 2. */
+tdgl_status tdgl_set_store_mode(tdgl_ctx *ctx, int mode);
+tdgl_status tdgl_get_store_mode(const tdgl_ctx *ctx, int *mode);
+
 /* Load P (C/m^2, [nbatch][3][nz][ny][nx]) from src: host memory if
  * src_on_device is 0, device memory otherwise; src_precision TDGL_FP32 or TDGL_FP64 (converted
  * to the context precision).  P is the state variable of eq 1, uniform in
@@ -395,11 +412,14 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *ctx, int nrep, double ms_out[5]);
 
 /* Pick the fastest launch configuration for this context by measurement:
  * each candidate (fused plane pass where it fits or the three passes,
- * times update tiles of 2, 4, 8, 16 rows) advances the current state by
- * nsteps steps as one graph, once to warm up and once timed with HIP events,
- * always from the same saved P.  The fastest stays set (as with
- * tdgl_set_fft_path and tdgl_set_update_rows); choice[0] = 1 if it uses the
- * fused pass, choice[1] = rows; *ms_per_step (may be NULL) its time.  P, the
+ * times update tiles of 2, 4, 8, 16 rows; then, for the three passes, the
+ * z-pass tiles of 64, 128 and 256 bytes with the rows found; last, the
+ * other store mode) advances the current state by nsteps steps as one
+ * graph, once to warm up and once timed with HIP events, always from the
+ * same saved P.  The fastest stays set (as with tdgl_set_fft_path,
+ * tdgl_set_update_rows, tdgl_set_z_tile and tdgl_set_store_mode);
+ * choice[0] = 1 if it uses the fused pass, choice[1] = rows; *ms_per_step
+ * (may be NULL) its time.  P, the
  * step parity and the non-finite flag are restored.  Allocates and frees
  * one P-sized device buffer; synchronising.  1 <= nsteps <= 100000. */
 tdgl_status tdgl_autotune(tdgl_ctx *ctx, int nsteps, int choice[2], double *ms_per_step);

@@ -95,6 +95,10 @@ _SIGS = {
     "tdgl_profile_step": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_profile_kernels": ([_ctx_p, c_int, ctypes.POINTER(c_double)], c_int),
     "tdgl_autotune": ([_ctx_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)], c_int),
+    "tdgl_set_z_tile": ([_ctx_p, c_int], c_int),
+    "tdgl_set_store_mode": ([_ctx_p, c_int], c_int),
+    "tdgl_get_store_mode": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
+    "tdgl_get_z_tile": ([_ctx_p, ctypes.POINTER(c_int)], c_int),
     "tdgl_sweep_eext": ([_ctx_p, ctypes.POINTER(c_double), c_int, ctypes.c_longlong,
                          ctypes.POINTER(c_double), ctypes.POINTER(c_double)], c_int),
     "tdgl_set_fft_path": ([_ctx_p, c_int], c_int),
@@ -240,6 +244,26 @@ def tdgl_set_fft_path(ctx, path: int):
 
 def tdgl_set_update_rows(ctx, rows: int):
     _check(ctx, lib().tdgl_set_update_rows(ctx, rows))
+
+
+def tdgl_set_z_tile(ctx, row_bytes: int):
+    _check(ctx, lib().tdgl_set_z_tile(ctx, row_bytes))
+
+
+def tdgl_get_z_tile(ctx):
+    v = c_int()
+    _check(ctx, lib().tdgl_get_z_tile(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def tdgl_set_store_mode(ctx, mode: int):
+    _check(ctx, lib().tdgl_set_store_mode(ctx, mode))
+
+
+def tdgl_get_store_mode(ctx):
+    v = c_int()
+    _check(ctx, lib().tdgl_get_store_mode(ctx, ctypes.byref(v)))
+    return v.value
 
 
 def tdgl_get_fft_path(ctx):

@@ -3,9 +3,12 @@
 // intermediate operations; eq 6 as a zero-padded convolution with the
 // cell-averaged dipolar tensor).
 //
-// Spectra are stored kx-major: element (kx, c, z, y) of the x-transformed
-// field at ((kx*3 + c)*nz + z)*L + y with L = ny (physical rows) or my
-// (after the y pass), so one kx plane of all components is contiguous.
+// The spectra of a context are stored in blocks of KB consecutive kx
+// (internal.h): the x spectra S1 as element (kx, row) at
+// ((kx/KB)*rows + row)*KB + kx%KB with row = (c*nz + z)*ny + y, the y spectra
+// S2 likewise with rows of my points.  One block of KB kx planes of all
+// components is contiguous; in it, column j = ky*KB + kx%KB of line
+// (c, z) sits at (c*nz + z)*my*KB + j.
 //
 //   k_fx    : real rows -> half spectra along x (each row one complex line
 //             of half length), zero padding beyond n_in implicit; output
@@ -30,7 +33,8 @@ namespace tdgl {
 // work-group transforms lpw consecutive rows and writes the spectra through
 // an LDS staging area, so that stores along r are contiguous.  tw: base of
 // the twiddle tables (table of length L at offset L).
-template <typename T, int M>
+// BLK: out is KB-blocked with out_kstride = nrows (internal.h).
+template <typename T, int M, bool BLK>
 __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long long in_stride,
                      cpx<T> *__restrict__ out, long long out_kstride,
                      const cpx<T> *__restrict__ tw, int lpw, Freeze fz)
@@ -80,9 +84,20 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     }
     __syncthreads();
     const int rows_here = (int)((nrows - r0) < lpw ? (nrows - r0) : lpw);
-    for (int e = tid; e < (M2 + 1) * lpw; e += nthr) {
-        const int k = e / lpw, rl = e - k * lpw;
-        if (rl < rows_here && !fz.skip(r0 + rl)) out[k * out_kstride + r0 + rl] = stg[e];
+    if constexpr (BLK) {
+        // e = (block of KB kx, row, kx in block): contiguous stores
+        constexpr int NKB = (M2 + KB) / KB;            // blocks covering k = 0..M2
+        for (int e = tid; e < NKB * KB * lpw; e += nthr) {
+            const int sub = e & (KB - 1), rest = e >> KBS;
+            const int kb = rest / lpw, rl = rest - kb * lpw, k = kb * KB + sub;
+            if (k <= M2 && rl < rows_here && !fz.skip(r0 + rl))
+                out[((long long)kb * out_kstride + r0 + rl) * KB + sub] = stg[k * lpw + rl];
+        }
+    } else {
+        for (int e = tid; e < (M2 + 1) * lpw; e += nthr) {
+            const int k = e / lpw, rl = e - k * lpw;
+            if (rl < rows_here && !fz.skip(r0 + rl)) out[k * out_kstride + r0 + rl] = stg[e];
+        }
     }
 }
 
@@ -125,6 +140,61 @@ __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long
     }
 }
 
+// ------------------------------------------------- row pass, kx blocks
+// The y passes of a context: lines (kx, r), r < R, between the KB-blocked
+// x spectra S1 (line of ny points at ((kx/KB)*R + r)*ny*KB + kx%KB, point
+// stride KB) and the KB-blocked y spectra S2 (line of my points, same form).
+// Forward: S1 -> S2; inverse: S2 -> S1.  The KB lines of one block sit in
+// adjacent lanes, so that every load and store of a wave is contiguous.
+// Lines of kx >= hx (the padding of the last block) are idle.
+template <typename T, int M, bool INV, bool HALF>
+__global__ void k_rowb(const cpx<T> *in, cpx<T> *out, int hx, unsigned R, unsigned mR, int ny,
+                       int my, int n_in, int n_out, const cpx<T> *__restrict__ tw, int lpw,
+                       Freeze fz, int nt)
+{
+    constexpr int TPL = M / 8;
+    constexpr int LEN = LinePad<M>::len;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int sub = tid & (KB - 1), tq = tid >> KBS;
+    const int t = tq & (TPL - 1), lg = tq / TPL;
+    const int l = lg * KB + sub;                         // LDS line slot
+    const unsigned rb = blockIdx.x * (unsigned)(lpw / KB) + lg;   // (kx / KB) * R + r
+    const unsigned kxb = udiv(rb, R, mR), r = rb - kxb * R;
+    const int kx = (int)kxb * KB + sub;
+    const bool act = l < lpw && kx < hx && !fz.skip((long long)kx * R + r);
+    TwReg<T, M> tr;
+    twiddle_load(tr, tw, t);
+    const long long b1 = (long long)rb * ny * KB + sub;     // S1 line
+    const long long b2 = (long long)rb * my * KB + sub;     // S2 line
+    const cpx<T> *src = in + (act ? (INV ? b2 : b1) : 0);
+    cpx<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = t + q * TPL;
+        const bool in_ok = (HALF && !INV) ? q < 4 : e < n_in;
+        v[q] = (act && in_ok) ? src[(long long)e * KB] : cpx<T>{T(0), T(0)};
+    }
+    fft_line<T, M, INV>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr, act);
+    cpx<T> *dst = out + (act ? (INV ? b1 : b2) : 0);
+    if (nt) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = t + q * TPL;
+            const bool out_ok = (HALF && INV) ? q < 4 : e < n_out;
+            if (act && out_ok) st_nt(&dst[(long long)e * KB], v[q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = t + q * TPL;
+            const bool out_ok = (HALF && INV) ? q < 4 : e < n_out;
+            if (act && out_ok) dst[(long long)e * KB] = v[q];
+        }
+    }
+}
+
 // ------------------------------------------------------------ column pass
 // Element e of column col in batch b sits at  b*bstride + e*lstride + col.
 // Columns of all batches are numbered j = b*C + col and tiled CT at a time.
@@ -163,8 +233,9 @@ __global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, long long ncol
 
 // ---------------------------------------------------- tensor row fetch
 // Row c of the interaction tensor at (kx, ky, kz) from the octant store
-// Nt[kx][q][kz'][ky'] (q: xx yy zz xy xz yz; kz' <= mz/2, ky' <= my/2).
-// xy is odd in ky, xz odd in kz, yz odd in both.
+// Nt(kx, q, kz', ky') (q: xx yy zz xy xz yz; kz' <= mz/2, ky' <= my/2), in
+// blocks of KB kx as the spectra.  xy is odd in ky, xz odd in kz, yz odd in
+// both.
 struct TensorRow {
     int i0, i1, i2;    // components (c,x) (c,y) (c,z) of row c
     __device__ explicit TensorRow(int c, int)
@@ -188,19 +259,21 @@ __device__ __forceinline__ void tensor_row(const T *__restrict__ Nt, int kx, int
     const int kzo = kz <= mz / 2 ? kz : mz - kz;
     const T sy = ky > my / 2 ? T(-1) : T(1);
     const T sz = kz > mz / 2 ? T(-1) : T(1);
-    const long long qs = (long long)hz * hy;
-    const T *b = Nt + (long long)kx * 6 * qs + (long long)kzo * hy + kyo;
+    const long long qs = (long long)hz * hy * KB;
+    const T *b = Nt + (long long)(kx >> KBS) * 6 * qs + ((long long)kzo * hy + kyo) * KB +
+                 (kx & (KB - 1));
     n0 = b[r.i0 * qs] * odd_sign(r.i0, sy, sz);
     n1 = b[r.i1 * qs] * odd_sign(r.i1, sy, sz);
     n2 = b[r.i2 * qs] * odd_sign(r.i2, sy, sz);
 }
 
 // ------------------------------------------------- z pass with multiply
-// S: [hx][nb][3][nz][my] complex (in place); work-group = (kx, instance,
-// tile of CT ky columns) x 3 components; the tensor is shared by the
-// instances.  Columns per group: 64-byte rows where threads
-// (<= 1024 FP32 / 512 FP64) and LDS (<= 64 KiB) allow.
-template <typename T, int MZ>
+// S: the KB-blocked y spectra (in place); work-group = (block of KB kx,
+// instance, tile of CT consecutive columns j = ky*KB + kx%KB) x 3
+// components, so that each z row of the tile is CT contiguous values; the
+// tensor is shared by the instances.  Columns per group: 64-byte rows where
+// threads (<= 1024 FP32 / 512 FP64) and LDS (<= 64 KiB) allow.
+template <typename T, int MZ, int RB>
 struct ZmulCfg {
     static constexpr int TPL = MZ / 8;
     static constexpr int MAXT = sizeof(T) == 8 ? 512 : 1024;
@@ -211,7 +284,7 @@ struct ZmulCfg {
                    ? fit(ct / 2)
                    : ct;
     }
-    static constexpr int CT = fit(64 / (int)sizeof(cpx<T>));    // 64-byte rows (measured best)
+    static constexpr int CT = fit(RB / (int)sizeof(cpx<T>));    // rows of RB bytes
     static constexpr int NTHR = 3 * CT * TPL;
 };
 
@@ -219,13 +292,13 @@ struct ZmulCfg {
 // half of the forward transform's inputs is zero and the upper half of the
 // inverse transform's outputs is discarded, both known at compile time, so
 // their arithmetic drops out.
-template <typename T, int MZ, bool HALF>
-__global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
-    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int nb,
+template <typename T, int MZ, int RB, bool HALF>
+__global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
+    k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int hx, int nb,
            const cpx<T> *__restrict__ tw, const int *__restrict__ frozen, unsigned mgx,
-           unsigned mnb)
+           unsigned mnb, int nt)
 {
-    using C = ZmulCfg<T, MZ>;
+    using C = ZmulCfg<T, MZ, RB>;
     constexpr int TPL = C::TPL, CT = C::CT;
     constexpr int LZ = LinePad<MZ>::len;
     extern __shared__ unsigned char smem_raw[];
@@ -235,18 +308,20 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     const int t = (tid / CT) % TPL;
     const int c = tid / (CT * TPL);
     const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    const unsigned kxb = udiv(tile, gridDim.x, mgx);           // plane (kx, instance)
-    const unsigned kx = udiv(kxb, (unsigned)nb, mnb);
-    if (frozen && frozen[kxb - kx * nb]) return;    // the whole group: one instance
-    const int ky = (int)(tile - kxb * gridDim.x) * CT + cc;
-    const bool act = ky < my;
-    const int kyc = act ? ky : 0;
-    // uniform bases, unsigned 32-bit offsets within one kx plane
-    cpx<T> *plane = S + (long long)kxb * 3 * nz * my;
+    const unsigned kbb = udiv(tile, gridDim.x, mgx);           // (kx block, instance)
+    const unsigned kblk = udiv(kbb, (unsigned)nb, mnb);
+    if (frozen && frozen[kbb - kblk * nb]) return;  // the whole group: one instance
+    const int myb = my * KB;                         // columns of a block plane
+    const int j = (int)(tile - kbb * gridDim.x) * CT + cc;
+    const int ky = j >> KBS, kx = (int)kblk * KB + (j & (KB - 1));
+    const bool act = j < myb && kx < hx;
+    const int kyc = act ? ky : 0, kxc = act ? kx : 0;
+    // uniform base, unsigned 32-bit offsets within one block plane
+    cpx<T> *plane = S + (long long)kbb * 3 * nz * myb;
     const int hy = my / 2 + 1, hz = MZ / 2 + 1;
-    const unsigned qs = (unsigned)hz * hy;
-    const T *tplane = Nt + (long long)kx * 6 * qs;
-    const unsigned col = (unsigned)(c * nz) * my + kyc;
+    const unsigned qs = (unsigned)hz * hy * KB;      // one tensor component of a block
+    const T *tplane = Nt + (long long)kblk * 6 * qs + (kxc & (KB - 1));
+    const unsigned col = (unsigned)(c * nz) * myb + (act ? j : 0);
     // data first: the forward transform waits for these loads only, the
     // tensor loads behind them complete during the transform
     cpx<T> v[8];
@@ -254,11 +329,11 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
         const bool in = HALF ? q < 4 : z < nz;
-        v[q] = (act && in) ? plane[col + (unsigned)z * my] : cpx<T>{T(0), T(0)};
+        v[q] = (act && in) ? plane[col + (unsigned)z * myb] : cpx<T>{T(0), T(0)};
     }
     // row c of the tensor: components (c,x) (c,y) (c,z) of the octant store
-    // Nt[kx][comp][kz'][ky'] (comp: xx yy zz xy xz yz); xy is odd in ky, xz
-    // odd in kz, yz odd in both
+    // Nt(kx, comp, kz', ky') (comp: xx yy zz xy xz yz), KB-blocked in kx; xy
+    // is odd in ky, xz odd in kz, yz odd in both
     const int i0 = c == 0 ? 0 : (c == 1 ? 3 : 4);
     const int i1 = c == 0 ? 3 : (c == 1 ? 1 : 5);
     const int i2 = c == 0 ? 4 : (c == 1 ? 5 : 2);
@@ -267,13 +342,13 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     auto ysign = [&](int i) { return (yneg && (i == 3 || i == 5)) ? T(-1) : T(1); };
     const T ys0 = ysign(i0), ys1 = ysign(i1), ys2 = ysign(i2);
     const bool zo0 = i0 == 4 || i0 == 5, zo1 = i1 == 4 || i1 == 5, zo2 = i2 == 4 || i2 == 5;
-    const unsigned o0 = i0 * qs + kyo, o1 = i1 * qs + kyo, o2 = i2 * qs + kyo;
+    const unsigned o0 = i0 * qs + kyo * KB, o1 = i1 * qs + kyo * KB, o2 = i2 * qs + kyo * KB;
     T nrow[8][3];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int kz = t + q * TPL;
         const bool zneg = kz > MZ / 2;
-        const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy;
+        const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy * KB;
         nrow[q][0] = tplane[o0 + kzo] * ((zneg && zo0) ? -ys0 : ys0);
         nrow[q][1] = tplane[o1 + kzo] * ((zneg && zo1) ? -ys1 : ys1);
         nrow[q][2] = tplane[o2 + kzo] * ((zneg && zo2) ? -ys2 : ys2);
@@ -308,11 +383,20 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
     }
     __syncthreads();
     fft_line<T, MZ, true>(v, L, ip, t, tr, act);
+    if (nt) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int z = t + q * TPL;
-        const bool out = HALF ? q < 4 : z < nz;
-        if (act && out) plane[col + (unsigned)z * my] = v[q];
+        for (int q = 0; q < 8; ++q) {
+            const int z = t + q * TPL;
+            const bool out = HALF ? q < 4 : z < nz;
+            if (act && out) st_nt(&plane[col + (unsigned)z * myb], v[q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int z = t + q * TPL;
+            const bool out = HALF ? q < 4 : z < nz;
+            if (act && out) plane[col + (unsigned)z * myb] = v[q];
+        }
     }
 }
 
@@ -320,8 +404,8 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ>::NTHR))
 // One work-group per kx.  The plane [3][nz][MY] (lines padded one slot per 8)
 // sits in LDS: y transforms of all (c, z) lines, then the z pass with the
 // tensor multiply in chunks of CK ky columns (scratch [3][MZ][CK]), then the
-// inverse y transforms.  S1: [hx][nb][3][nz][ny] in/out (in place); one
-// work-group per (kx, instance).
+// inverse y transforms.  S1 (KB-blocked, read with a stride of KB) in/out,
+// in place; one work-group per (kx, instance).
 template <typename T, int MY, int MZ>
 struct PlaneCfg {
     // FP64 groups use at most 384 threads, leaving 256 VGPRs per wave
@@ -359,7 +443,10 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     if (frozen && frozen[blockIdx.x % nb]) return;
     const IdxPad pad{};
     const int nlines = 3 * nz;
-    cpx<T> *gplane = S1 + (long long)blockIdx.x * nlines * ny;
+    // row (line, y) of this plane in the KB-blocked S1: stride KB
+    const int bi = blockIdx.x - kx * nb;
+    cpx<T> *gplane = S1 + ((long long)(kx >> KBS) * nb * nlines + (long long)bi * nlines) * ny * KB +
+                     (kx & (KB - 1));
 
     // y-pass roles
     const int ly = tid / TPLY, ty = tid - ly * TPLY;
@@ -373,7 +460,7 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     // load the plane (rows y >= ny are zero padding)
     for (int e = tid; e < nlines * MY; e += C::NTHR) {
         const int line = e / MY, y = e - line * MY;
-        pl[line * LINE + pad(y)] = y < ny ? gplane[(long long)line * ny + y] : cpx<T>{T(0), T(0)};
+        pl[line * LINE + pad(y)] = y < ny ? gplane[((long long)line * ny + y) * KB] : cpx<T>{T(0), T(0)};
     }
 
     auto ypass = [&](auto inv_tag) {
@@ -442,7 +529,7 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     __syncthreads();
     for (int e = tid; e < nlines * ny; e += C::NTHR) {
         const int line = e / ny, y = e - line * ny;
-        gplane[e] = pl[line * LINE + pad(y)];
+        gplane[(long long)e * KB] = pl[line * LINE + pad(y)];
     }
 }
 
@@ -463,7 +550,7 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
 template <typename T, int M>
 static hipError_t fx_impl(const void *in, long long nrows, int n_in, long long in_stride,
                           void *out, long long out_kstride, const void *tw, hipStream_t s,
-                          Freeze fz)
+                          Freeze fz, bool blocked)
 {
     constexpr int M2 = M / 2;
     constexpr int TPL = HalfLine<M2>::TPL;
@@ -473,22 +560,28 @@ static hipError_t fx_impl(const void *in, long long nrows, int n_in, long long i
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const size_t shm = ((size_t)lpw * LinePad<M2>::len + (size_t)(M2 + 1) * lpw) *
                        sizeof(cpx<T>);
-    hipLaunchKernelGGL((k_fx<T, M>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
-                       (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_kstride,
-                       (const cpx<T> *)tw, lpw, fz);
+    if (blocked && out_kstride != nrows) return hipErrorInvalidValue;
+    if (blocked)
+        hipLaunchKernelGGL((k_fx<T, M, true>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
+                           (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_kstride,
+                           (const cpx<T> *)tw, lpw, fz);
+    else
+        hipLaunchKernelGGL((k_fx<T, M, false>), dim3((unsigned)blocks), dim3(lpw * TPL), shm, s,
+                           (const T *)in, nrows, n_in, in_stride, (cpx<T> *)out, out_kstride,
+                           (const cpx<T> *)tw, lpw, fz);
     return hipGetLastError();
 }
 
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
                      long long in_stride, void *out, long long out_kstride, const void *tw,
-                     hipStream_t s, Freeze fz)
+                     hipStream_t s, Freeze fz, bool blocked)
 {
     if (prec == PREC_F32) {
         TDGL_LEN_SWITCH(M, return (fx_impl<float, LEN_>(in, nrows, n_in, in_stride, out,
-                                                         out_kstride, tw, s, fz)))
+                                                         out_kstride, tw, s, fz, blocked)))
     } else {
         TDGL_LEN_SWITCH(M, return (fx_impl<double, LEN_>(in, nrows, n_in, in_stride, out,
-                                                          out_kstride, tw, s, fz)))
+                                                          out_kstride, tw, s, fz, blocked)))
     }
 }
 
@@ -533,6 +626,83 @@ hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long
     } else {
         TDGL_LEN_SWITCH(M, return (row_impl<double, LEN_>(inv, in, out, nlines, in_stride,
                                                            out_stride, n_in, n_out, tw, s, fz)))
+    }
+}
+
+template <typename T, int M>
+static hipError_t rowb_prepare()
+{
+    constexpr int TPL = M / 8;
+    constexpr int lpw = TPL >= 128 / KB ? KB : 128 / TPL;
+    constexpr size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
+    if (shm <= 65536) return hipSuccess;
+    const void *f[4] = {(const void *)k_rowb<T, M, false, false>,
+                        (const void *)k_rowb<T, M, false, true>,
+                        (const void *)k_rowb<T, M, true, false>,
+                        (const void *)k_rowb<T, M, true, true>};
+    for (const void *k : f) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int M>
+static hipError_t rowb_impl(bool inv, const void *S1, void *S2, int hx, long long R, int ny,
+                            int my, int n_in, int n_out, const void *tw, hipStream_t s,
+                            Freeze fz, int nt)
+{
+    constexpr int TPL = M / 8;
+    // 128-thread groups as the plain row pass, but at least one block of KB lines
+    // (above 64 KiB of LDS, i.e. 1024-point FP64 lines, rowb_prepare has
+    // raised the kernels' limit)
+    const int lpw = TPL >= 128 / KB ? KB : 128 / TPL;
+    const long long rows = (long long)hx_blocked(hx) / KB * R;      // line blocks
+    const long long blocks = (rows + lpw / KB - 1) / (lpw / KB);
+    if (blocks <= 0) return hipSuccess;
+    if (rows >= (1LL << 32) || blocks > 0x7fffffffLL || lpw * TPL > 1024)
+        return hipErrorInvalidValue;
+    const unsigned mR = div_magic((unsigned)R, (unsigned long long)blocks * (lpw / KB));
+    const size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
+    const dim3 grid((unsigned)blocks), blk(lpw * TPL);
+    const cpx<T> *twm = (const cpx<T> *)tw + M;
+    const bool half = M >= 16 && (inv ? (n_out == M / 2 && n_in == M) : (n_in == M / 2));
+    const unsigned Ru = (unsigned)R;
+    if (inv && half)
+        hipLaunchKernelGGL((k_rowb<T, M, true, true>), grid, blk, shm, s, (const cpx<T> *)S2,
+                           (cpx<T> *)S1, hx, Ru, mR, ny, my, n_in, n_out, twm, lpw, fz, nt);
+    else if (inv)
+        hipLaunchKernelGGL((k_rowb<T, M, true, false>), grid, blk, shm, s, (const cpx<T> *)S2,
+                           (cpx<T> *)S1, hx, Ru, mR, ny, my, n_in, n_out, twm, lpw, fz, nt);
+    else if (half)
+        hipLaunchKernelGGL((k_rowb<T, M, false, true>), grid, blk, shm, s, (const cpx<T> *)S1,
+                           (cpx<T> *)S2, hx, Ru, mR, ny, my, n_in, n_out, twm, lpw, fz, nt);
+    else
+        hipLaunchKernelGGL((k_rowb<T, M, false, false>), grid, blk, shm, s, (const cpx<T> *)S1,
+                           (cpx<T> *)S2, hx, Ru, mR, ny, my, n_in, n_out, twm, lpw, fz, nt);
+    return hipGetLastError();
+}
+
+hipError_t prepare_row_blocked(int prec, int M)
+{
+    if (prec == PREC_F32) {
+        TDGL_LEN_SWITCH(M, return (rowb_prepare<float, LEN_>()))
+    } else {
+        TDGL_LEN_SWITCH(M, return (rowb_prepare<double, LEN_>()))
+    }
+}
+
+hipError_t launch_row_blocked(int prec, int M, bool inv, const void *S1, void *S2, int hx,
+                              long long R, int ny, int my, int n_in, int n_out, const void *tw,
+                              hipStream_t s, Freeze fz, int nt)
+{
+    if (prec == PREC_F32) {
+        TDGL_LEN_SWITCH(M, return (rowb_impl<float, LEN_>(inv, S1, S2, hx, R, ny, my, n_in,
+                                                           n_out, tw, s, fz, nt)))
+    } else {
+        TDGL_LEN_SWITCH(M, return (rowb_impl<double, LEN_>(inv, S1, S2, hx, R, ny, my, n_in,
+                                                            n_out, tw, s, fz, nt)))
     }
 }
 
@@ -587,35 +757,60 @@ hipError_t launch_col(int prec, int M, bool inv, const void *in, void *out, long
     }
 }
 
-template <typename T, int MZ>
-static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *tw,
-                            hipStream_t s)
+template <typename T, int MZ, int RB>
+static hipError_t zmul_tile(const Geom &g, void *S, const void *Nt, const void *tw, hipStream_t s)
 {
-    using C = ZmulCfg<T, MZ>;
-    const int gx = (g.my + C::CT - 1) / C::CT;
-    if ((long long)g.hx * g.nb > 65535) return hipErrorInvalidValue;
+    using C = ZmulCfg<T, MZ, RB>;
+    const int gx = (g.my * KB + C::CT - 1) / C::CT;          // column tiles of a block plane
+    const int nkb = hx_blocked(g.hx) / KB;
+    if ((long long)nkb * g.nb > 65535) return hipErrorInvalidValue;
     const size_t shm = (size_t)3 * C::CT * LinePad<MZ>::len * sizeof(cpx<T>);
-    const unsigned long long ntile = (unsigned long long)gx * g.hx * g.nb;
+    const unsigned long long ntile = (unsigned long long)gx * nkb * g.nb;
     const unsigned mgx = div_magic((unsigned)gx, ntile);
-    const unsigned mnb = div_magic((unsigned)g.nb, (unsigned long long)g.hx * g.nb);
+    const unsigned mnb = div_magic((unsigned)g.nb, (unsigned long long)nkb * g.nb);
     if (2 * g.nz == MZ)
-        hipLaunchKernelGGL((k_zmul<T, MZ, true>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm, s,
-                           (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb,
-                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb);
+        hipLaunchKernelGGL((k_zmul<T, MZ, RB, true>), dim3(gx, nkb * g.nb), dim3(C::NTHR), shm,
+                           s, (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.hx, g.nb,
+                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb, g.nt);
     else
-        hipLaunchKernelGGL((k_zmul<T, MZ, false>), dim3(gx, g.hx * g.nb), dim3(C::NTHR), shm,
-                           s, (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.nb,
-                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb);
+        hipLaunchKernelGGL((k_zmul<T, MZ, RB, false>), dim3(gx, nkb * g.nb), dim3(C::NTHR), shm,
+                           s, (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.hx, g.nb,
+                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb, g.nt);
     return hipGetLastError();
 }
 
-hipError_t launch_zmul(int prec, const Geom &g, void *S, const void *Nt, const void *tw,
-                       hipStream_t s)
+// Column tiles of rb = 64, 128 or 256 bytes per z row; 0 picks 128 bytes, or
+// 64 where 128 would leave fewer than 1024 work-groups (measured on the
+// 128x128x32 film, the 256x256x64 bilayer and the batched boxes;
+// tdgl_autotune tries all three).
+int zmul_auto_tile(int prec, const Geom &g)
 {
+    const int esz = prec == PREC_F32 ? 8 : 16;
+    const int ct = 128 / esz;
+    const long long groups = (long long)((g.my * KB + ct - 1) / ct) * (hx_blocked(g.hx) / KB) * g.nb;
+    return groups < 1024 ? 64 : 128;
+}
+
+template <typename T, int MZ>
+static hipError_t zmul_impl(const Geom &g, void *S, const void *Nt, const void *tw, int rb,
+                            hipStream_t s)
+{
+    switch (rb) {
+    case 64: return zmul_tile<T, MZ, 64>(g, S, Nt, tw, s);
+    case 128: return zmul_tile<T, MZ, 128>(g, S, Nt, tw, s);
+    case 256: return zmul_tile<T, MZ, 256>(g, S, Nt, tw, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zmul(int prec, const Geom &g, void *S, const void *Nt, const void *tw,
+                       int tile_bytes, hipStream_t s)
+{
+    const int rb = tile_bytes == 0 ? zmul_auto_tile(prec, g) : tile_bytes;
     if (prec == PREC_F32) {
-        TDGL_LEN_SWITCH(g.mz, return (zmul_impl<float, LEN_>(g, S, Nt, tw, s)))
+        TDGL_LEN_SWITCH(g.mz, return (zmul_impl<float, LEN_>(g, S, Nt, tw, rb, s)))
     } else {
-        TDGL_LEN_SWITCH(g.mz, return (zmul_impl<double, LEN_>(g, S, Nt, tw, s)))
+        TDGL_LEN_SWITCH(g.mz, return (zmul_impl<double, LEN_>(g, S, Nt, tw, rb, s)))
     }
 }
 

@@ -13,6 +13,18 @@ constexpr int MAXLEN = 1024;   // largest FFT length
 constexpr int GL_MAXN = 24;    // Gauss-Legendre table rows/columns
 
 enum { PREC_F32 = 0, PREC_F64 = 1 };
+
+// The x spectra (S1) and y spectra (S2) of a context are stored in blocks of
+// KB consecutive kx: element (kx, row) at ((kx / KB) * rows + row) * KB +
+// kx % KB, where row = ((b*3 + c)*nz + z)*L + y runs over all rows of all
+// instances (L = ny for S1, my for S2).  A work-group of the update kernel,
+// which reads and writes yt consecutive rows for every kx, then touches
+// whole 128-byte lines (yt * KB * 8 bytes per block), the y passes read and
+// write KB lines side by side, and the z pass reads tiles of (ky, kx)
+// columns.  The buffers hold hx rounded up to a multiple of KB.
+constexpr int KB = 4;
+constexpr int KBS = 2;                  // log2(KB)
+__host__ __device__ constexpr int hx_blocked(int hx) { return (hx + KB - 1) / KB * KB; }
 enum { T_LANDAU = 1, T_GRAD = 2, T_ELEC = 4, T_EXT = 8 };
 
 // Device-resident scalars read by the update kernel (can change between
@@ -38,6 +50,9 @@ struct Geom {
     // advance (relaxed and retired): the FFT passes skip their lines and the
     // update kernel copies their state unchanged; null = none
     const int *frozen = nullptr;
+    // the step kernels' stores of spectra and states are non-temporal (a
+    // per-context choice, see st_nt)
+    int nt = 0;
 };
 
 // Frozen-instance test for kernels that see flat line or row indices:
@@ -63,7 +78,7 @@ struct UpdArgs {
     const void *P_in;      // state the field is evaluated at
     const void *P_old;     // Heun corrector: state at the start of the step
     void *P_out;           // new state (STEP) or field (FIELD)
-    void *S1;              // x spectra, kx-major [hx][3][nz][ny]: field in, new P spectrum out
+    void *S1;              // x spectra in kx blocks of KB (above): field in, new P spectrum out
     const void *coef;      // [nz][NCOEF]
     const void *kp;        // KParams<T>
     double *partials;      // ENERGY: [grid][8]
@@ -88,20 +103,33 @@ struct UpdArgs {
 hipError_t launch_cross(int prec, const Geom &g, const void *P, void *H, const void *coef,
                         const void *kp, hipStream_t s);
 
-// spectra are kx-major: x pass output element k of row r at out[k*out_kstride + r]
+// x pass: output element k of row r at out[k*out_kstride + r] (kx-major), or,
+// with blocked (out_kstride = number of rows), in the KB-blocked layout above
 hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
                      long long in_stride, void *out, long long out_kstride,
-                     const void *tw, hipStream_t s, Freeze fz = {});
+                     const void *tw, hipStream_t s, Freeze fz = {}, bool blocked = false);
 hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long long nlines,
                       long long in_stride, long long out_stride, int n_in, int n_out,
                       const void *tw, hipStream_t s, Freeze fz = {});
+// y pass between the KB-blocked x spectra S1 (lines of ny points, rows per
+// kx: R = nb*3*nz) and the KB-blocked y spectra S2 (lines of my points):
+// forward S1 -> S2, inverse S2 -> S1
+hipError_t launch_row_blocked(int prec, int M, bool inv, const void *S1, void *S2, int hx,
+                              long long R, int ny, int my, int n_in, int n_out, const void *tw,
+                              hipStream_t s, Freeze fz, int nt);
+// once per context, outside graph capture: lets the blocked y passes of
+// length M use more than 64 KiB of LDS where they need it
+hipError_t prepare_row_blocked(int prec, int M);
 hipError_t launch_plane(int prec, const Geom &g, void *S1, const void *Nt, const void *tw,
                         size_t lds_max, hipStream_t s, bool query);
 hipError_t launch_col(int prec, int M, bool inv, const void *in, void *out, long long C,
                       long long nbatch, long long in_bstride, long long out_bstride,
                       long long lstride, int n_in, int n_out, const void *tw, hipStream_t s);
+// z pass with the tensor multiply; tile_bytes: bytes per z row of a column
+// tile (64, 128, 256; 0 = zmul_auto_tile)
 hipError_t launch_zmul(int prec, const Geom &g, void *S, const void *Nt, const void *tw,
-                       hipStream_t s);
+                       int tile_bytes, hipStream_t s);
+int zmul_auto_tile(int prec, const Geom &g);
 hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a,
                          const void *tw, hipStream_t s, int *nblocks_out);
 int update_rows_per_block(int prec, const Geom &g);

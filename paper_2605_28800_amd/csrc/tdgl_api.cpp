@@ -107,6 +107,7 @@ struct tdgl_ctx {
     int hist_pos = 0;             // buffer of the newest entry
     size_t lds_max = 65536;      // dynamic LDS one work-group may use on this device
     int fft_path = 0;            // 0: fused plane pass when it fits, 1: three passes
+    int ztile = 0;               // z-pass column tile, bytes per z row (0: built-in choice)
     bool use_plane = false;
     int nblocks = 1;
     bool P_set = false, tensor_built = false, spec_valid = false, params_dirty = true;
@@ -159,9 +160,9 @@ Layout layout_of(const tdgl_ctx *c, int scheme)
         return o;
     };
     L.P = take(2 * 3 * N * c->esz);
-    L.S1 = take((size_t)3 * g.nb * g.nz * g.ny * g.hx * 2 * c->esz);
-    L.S2 = take((size_t)3 * g.nb * g.nz * g.my * g.hx * 2 * c->esz);
-    L.Nt = take((size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * g.hx * c->esz);
+    L.S1 = take((size_t)3 * g.nb * g.nz * g.ny * hx_blocked(g.hx) * 2 * c->esz);
+    L.S2 = take((size_t)3 * g.nb * g.nz * g.my * hx_blocked(g.hx) * 2 * c->esz);
+    L.Nt = take((size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * hx_blocked(g.hx) * c->esz);
     L.coef = take((size_t)g.nb * g.nz * NCOEF * c->esz);
     L.kp = take(sizeof(KParams<double>));
     L.twf = take((size_t)2 * MAXLEN * 2 * sizeof(float));
@@ -286,6 +287,8 @@ tdgl_status ensure_device(tdgl_ctx *c)
         c->lds_max = (size_t)optin;
     c->dev_init = true;
     choose_path(c);
+    if (prepare_row_blocked(c->prec, c->g.my) != hipSuccess)
+        return fail(c, TDGL_E_HIP, "cannot raise the LDS limit of the y pass");
     return TDGL_OK;
 }
 
@@ -427,24 +430,38 @@ hipError_t enq_fx(tdgl_ctx *c, const void *P, hipStream_t s)
     const Geom &g = c->g;
     const long long rows = 3LL * g.nb * g.nz * g.ny;      // rows of all instances
     const Freeze fz{g.frozen, 3LL * g.nz * g.ny, g.nb};   // rows [nb][3][nz][ny]
-    return launch_fx(c->prec, g.mx, P, rows, g.nx, g.nx, c->S1, rows, tw(c), s, fz);
+    return launch_fx(c->prec, g.mx, P, rows, g.nx, g.nx, c->S1, rows, tw(c), s, fz, true);
 }
 
-// y pass, z pass with the tensor, inverse y pass: S1 (x spectra, kx-major
-// [hx][3][nz][ny]) -> S1 (field rows), fused into one kernel when possible.
+// the y passes between S1 (x spectra) and S2 (y spectra), both in blocks of
+// KB kx; lines (kx, r) with r < nb*3*nz
+hipError_t enq_yfwd(tdgl_ctx *c, hipStream_t s, bool freeze = true)
+{
+    const Geom &g = c->g;
+    const Freeze fz{freeze ? g.frozen : nullptr, 3LL * g.nz, g.nb};   // line kx*R + r
+    return launch_row_blocked(c->prec, g.my, false, c->S1, c->S2, g.hx, 3LL * g.nb * g.nz, g.ny,
+                              g.my, g.ny, g.my, tw(c), s, fz, g.nt);
+}
+
+hipError_t enq_yinv(tdgl_ctx *c, hipStream_t s, bool freeze = true)
+{
+    const Geom &g = c->g;
+    const Freeze fz{freeze ? g.frozen : nullptr, 3LL * g.nz, g.nb};
+    return launch_row_blocked(c->prec, g.my, true, c->S1, c->S2, g.hx, 3LL * g.nb * g.nz, g.ny,
+                              g.my, g.my, g.ny, tw(c), s, fz, g.nt);
+}
+
+// y pass, z pass with the tensor, inverse y pass: S1 (x spectra) -> S1
+// (field rows), fused into one kernel when possible.
 hipError_t enq_yz(tdgl_ctx *c, hipStream_t s)
 {
     const Geom &g = c->g;
     if (c->use_plane) return launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, s, false);
-    const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
-    const Freeze fz{g.frozen, 3LL * g.nz, g.nb};          // lines [hx][nb][3][nz]
-    hipError_t e = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
-                              tw(c), s, fz);
+    hipError_t e = enq_yfwd(c, s);
     if (e != hipSuccess) return e;
-    e = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), s);
+    e = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), c->ztile, s);
     if (e != hipSuccess) return e;
-    return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny, tw(c), s,
-                      fz);
+    return enq_yinv(c, s);
 }
 
 // field of the gradient cross terms at Pin into xbuf, when the model has them
@@ -782,6 +799,7 @@ tdgl_status tdgl_create_batch(const tdgl_grid *grid, int nbatch, int precision, 
     c->esz = precision == TDGL_FP32 ? 4 : 8;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->g.nb = nbatch;
+    c->g.nt = nbatch == 1 ? 1 : 0;       // the built-in store mode (tdgl_set_store_mode)
     c->Tb.assign(nbatch, 300.0);
     c->layer.assign(n[2], 0);
     c->yt = update_rows_per_block(c->prec, c->g);
@@ -955,16 +973,23 @@ tdgl_status tdgl_get_tensor_spectrum(tdgl_ctx *c, double *dst, size_t count)
     if (!c || !dst) return TDGL_E_ARG;
     if (!c->tensor_built) return fail(c, TDGL_E_STATE, "tensor not built");
     const Geom &g = c->g;
-    const size_t n = (size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * g.hx;
+    const size_t qs = (size_t)(g.mz / 2 + 1) * (g.my / 2 + 1);
+    const size_t n = 6 * qs * g.hx;
     if (count < n) return fail(c, TDGL_E_ARG, "need %zu doubles", n);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // the device copy is stored in blocks of KB kx: [hx/KB][6][kz][ky][KB]
+    const size_t nblk = 6 * qs * hx_blocked(g.hx);
+    std::vector<double> tmp(nblk);
     if (c->prec == PREC_F64) {
-        HIP_TRY(c, hipMemcpy(dst, c->Nt, n * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(tmp.data(), c->Nt, nblk * sizeof(double), hipMemcpyDeviceToHost));
     } else {
-        std::vector<float> tmp(n);
-        HIP_TRY(c, hipMemcpy(tmp.data(), c->Nt, n * sizeof(float), hipMemcpyDeviceToHost));
-        for (size_t i = 0; i < n; ++i) dst[i] = tmp[i];
+        std::vector<float> tf(nblk);
+        HIP_TRY(c, hipMemcpy(tf.data(), c->Nt, nblk * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < nblk; ++i) tmp[i] = tf[i];
     }
+    for (size_t kx = 0; kx < (size_t)g.hx; ++kx)
+        for (size_t e = 0; e < 6 * qs; ++e)
+            dst[kx * 6 * qs + e] = tmp[((kx / KB) * 6 * qs + e) * KB + kx % KB];
     return TDGL_OK;
 }
 
@@ -1059,6 +1084,39 @@ tdgl_status tdgl_set_update_rows(tdgl_ctx *c, int rows)
     c->yt = yt;
     if (!c->dev_init) c->nblocks = nb > c->nblocks ? nb : c->nblocks;
     drop_graphs(c);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_store_mode(tdgl_ctx *c, int mode)
+{
+    if (!c) return TDGL_E_ARG;
+    if (mode < 0 || mode > 2) return fail(c, TDGL_E_ARG, "store mode must be 0, 1 or 2");
+    c->g.nt = mode == 0 ? (c->g.nb == 1 ? 1 : 0) : (mode == 1 ? 1 : 0);
+    drop_graphs(c);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_store_mode(const tdgl_ctx *c, int *mode)
+{
+    if (!c || !mode) return TDGL_E_ARG;
+    *mode = c->g.nt ? 1 : 2;
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_set_z_tile(tdgl_ctx *c, int row_bytes)
+{
+    if (!c) return TDGL_E_ARG;
+    if (row_bytes != 0 && row_bytes != 64 && row_bytes != 128 && row_bytes != 256)
+        return fail(c, TDGL_E_ARG, "z tile must be 0, 64, 128 or 256 bytes");
+    c->ztile = row_bytes;
+    drop_graphs(c);
+    return TDGL_OK;
+}
+
+tdgl_status tdgl_get_z_tile(const tdgl_ctx *c, int *row_bytes)
+{
+    if (!c || !row_bytes) return TDGL_E_ARG;
+    *row_bytes = c->ztile == 0 ? zmul_auto_tile(c->prec, c->g) : c->ztile;
     return TDGL_OK;
 }
 
@@ -1693,15 +1751,11 @@ tdgl_status tdgl_profile_step(tdgl_ctx *c, int nsteps, double ms_out[5])
                 (void)hipEventRecord(E[2], c->stream);
                 (void)hipEventRecord(E[3], c->stream);
             } else if (el) {
-                const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
-                le = launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
-                                tw(c), c->stream);
+                le = enq_yfwd(c, c->stream, false);
                 (void)hipEventRecord(E[1], c->stream);
-                if (le == hipSuccess) le = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), c->stream);
+                if (le == hipSuccess) le = launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), c->ztile, c->stream);
                 (void)hipEventRecord(E[2], c->stream);
-                if (le == hipSuccess)
-                    le = launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny,
-                                    tw(c), c->stream);
+                if (le == hipSuccess) le = enq_yinv(c, c->stream, false);
                 (void)hipEventRecord(E[3], c->stream);
             } else {
                 (void)hipEventRecord(E[1], c->stream);
@@ -1765,7 +1819,6 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
     if (he == hipSuccess) he = hipEventCreate(&e1);
     void *A = c->P[c->cur], *B = c->P[1 - c->cur];
     const Geom &g = c->g;
-    const long long nl = (long long)g.hx * g.nb * 3 * g.nz;
     const unsigned t = c->terms;
     // one kernel, nrep times, as one graph; returns ms per launch
     auto time_kernel = [&](int which, double *out) -> hipError_t {
@@ -1774,12 +1827,9 @@ tdgl_status tdgl_profile_kernels(tdgl_ctx *c, int nrep, double ms_out[5])
             case 0:
                 if (c->use_plane)
                     return launch_plane(c->prec, g, c->S1, c->Nt, tw(c), c->lds_max, s, false);
-                return launch_row(c->prec, g.my, false, c->S1, c->S2, nl, g.ny, g.my, g.ny, g.my,
-                                  tw(c), s);
-            case 1: return launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), s);
-            case 2:
-                return launch_row(c->prec, g.my, true, c->S2, c->S1, nl, g.my, g.ny, g.my, g.ny,
-                                  tw(c), s);
+                return enq_yfwd(c, s, false);
+            case 1: return launch_zmul(c->prec, g, c->S2, c->Nt, tw(c), c->ztile, s);
+            case 2: return enq_yinv(c, s, false);
             case 3: return enq_upd(c, UPD_STEP, A, nullptr, B, 0, t, el, el, s);
             default: return enq_upd(c, UPD_STEP, B, A, A, 1, t, el, el, s);
             }
@@ -1875,10 +1925,39 @@ tdgl_status tdgl_autotune(tdgl_ctx *c, int nsteps, int choice[2], double *ms_per
     if (he == hipSuccess) he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     const int nb_groups = c->nblocks;               // partials the workspace holds per instance
+    const int zt0 = c->ztile, nt0 = c->g.nt;
     double best = 1e300;
-    int best_path = path0, best_yt = yt0;
+    int best_path = path0, best_yt = yt0, best_zt = zt0, best_nt = nt0;
     tdgl_status rs = TDGL_OK;
     c->graph_chunk = nsteps;                        // one graph of nsteps steps per candidate
+    // time the current configuration from the saved state; false if the
+    // device rejects it (the candidate is skipped)
+    auto trial = [&](double *ms_step) -> bool {
+        drop_graphs(c);
+        // every candidate starts from the saved state and runs the same steps
+        he = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+        if (he != hipSuccess) return false;
+        c->cur = cur0;
+        c->spec_valid = false;
+        rs = tdgl_step(c, nsteps);                  // warm-up: captures the graph
+        if (rs != TDGL_OK) {                        // a tile the device rejects: skip it
+            rs = TDGL_OK;
+            (void)hipGetLastError();
+            return false;
+        }
+        he = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
+        c->cur = cur0;
+        c->spec_valid = false;
+        if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+        if (he == hipSuccess) rs = tdgl_step(c, nsteps);
+        if (he == hipSuccess && rs == TDGL_OK) he = hipEventRecord(e1, c->stream);
+        if (he == hipSuccess && rs == TDGL_OK) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess && rs == TDGL_OK) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess || rs != TDGL_OK) return false;
+        *ms_step = ms / nsteps;
+        return true;
+    };
     for (int path = 0; path <= 1 && he == hipSuccess && rs == TDGL_OK; ++path) {
         c->fft_path = path;
         choose_path(c);
@@ -1887,37 +1966,48 @@ tdgl_status tdgl_autotune(tdgl_ctx *c, int nsteps, int choice[2], double *ms_per
             if (((c->g.ny + yt - 1) / yt) * c->g.nz > nb_groups) continue;
             if (yt > 2 && yt > c->g.ny + (c->g.ny & 1)) break;
             c->yt = yt;
-            drop_graphs(c);
-            // every candidate starts from the saved state and runs the same steps
-            he = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
-            if (he != hipSuccess) break;
-            c->cur = cur0;
-            c->spec_valid = false;
-            rs = tdgl_step(c, nsteps);              // warm-up: captures the graph
-            if (rs != TDGL_OK) {                    // a tile the device rejects: skip it
-                rs = TDGL_OK;
-                (void)hipGetLastError();
-                continue;
-            }
-            he = hipMemcpyAsync(c->P[cur0], save, pbytes, hipMemcpyDeviceToDevice, c->stream);
-            c->cur = cur0;
-            c->spec_valid = false;
-            if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
-            if (he == hipSuccess) rs = tdgl_step(c, nsteps);
-            if (he == hipSuccess && rs == TDGL_OK) he = hipEventRecord(e1, c->stream);
-            if (he == hipSuccess && rs == TDGL_OK) he = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (he == hipSuccess && rs == TDGL_OK) he = hipEventElapsedTime(&ms, e0, e1);
-            if (he == hipSuccess && rs == TDGL_OK && ms / nsteps < best) {
-                best = ms / nsteps;
+            c->ztile = 0;
+            double ms = 0;
+            if (trial(&ms) && ms < best) {
+                best = ms;
                 best_path = path;
                 best_yt = yt;
+                best_zt = 0;
             }
+        }
+    }
+    // then the z-pass tile of the three-pass path, with the rows found
+    if (best_path == 1 && best < 1e300) {
+        c->fft_path = 1;
+        choose_path(c);
+        c->yt = best_yt;
+        for (int zt = 64; zt <= 256 && he == hipSuccess && rs == TDGL_OK; zt *= 2) {
+            c->ztile = zt;
+            double ms = 0;
+            if (trial(&ms) && ms < best) {
+                best = ms;
+                best_zt = zt;
+            }
+        }
+        c->ztile = best_zt;
+    }
+    // last, the other store mode with everything else found
+    if (best < 1e300 && he == hipSuccess && rs == TDGL_OK) {
+        c->fft_path = best_path;
+        choose_path(c);
+        c->yt = best_yt;
+        c->g.nt = 1 - nt0;
+        double ms = 0;
+        if (trial(&ms) && ms < best) {
+            best = ms;
+            best_nt = c->g.nt;
         }
     }
     // the winner stays set; the state goes back to what it was
     c->fft_path = best_path;
     c->yt = best_yt;
+    c->ztile = best_zt;
+    c->g.nt = best_nt;
     c->graph_chunk = chunk0;
     drop_graphs(c);
     if (c->dev_init) choose_path(c);

@@ -295,9 +295,10 @@ hipError_t launch_tensor_k0(const Geom &g, unsigned pmask, double *R, double *su
     return hipGetLastError();
 }
 
-// Octant of the real spectrum, scaled, kx-major:
-//   Nt[kx][q][kz][ky] = scale * Re C[kx][q][kz][ky],  kz <= mz/2, ky <= my/2,
-// from the full spectrum C[kx][q][mz][my].
+// Octant of the real spectrum, scaled:
+//   Nt(kx, q, kz, ky) = scale * Re C[kx][q][kz][ky],  kz <= mz/2, ky <= my/2,
+// from the full spectrum C[kx][q][mz][my], stored in blocks of KB kx:
+// Nt(kx, q, kz, ky) at (((kx/KB)*6 + q)*(mz/2+1) + kz)*(my/2+1) + ky)*KB + kx%KB.
 template <typename T>
 __global__ void k_tensor_octant(Geom g, const cpx<double> *__restrict__ C, double scale,
                                 T *__restrict__ Nt)
@@ -310,7 +311,10 @@ __global__ void k_tensor_octant(Geom g, const cpx<double> *__restrict__ C, doubl
     const int kz = (int)((idx / hy) % hz);
     const long long kq = idx / ((long long)hy * hz);      // kx*6 + q
     const long long src = (kq * g.mz + kz) * g.my + ky;
-    Nt[idx] = (T)(scale * C[src].x);
+    // stored in blocks of KB kx, as the spectra that it multiplies
+    const long long kx = kq / 6, q = kq - kx * 6;
+    const long long dst = ((((kx >> KBS) * 6 + q) * hz + kz) * hy + ky) * KB + (kx & (KB - 1));
+    Nt[dst] = (T)(scale * C[src].x);
 }
 
 hipError_t launch_tensor_octant(int prec, const Geom &g, const void *C, double scale, void *Nt,

@@ -18,6 +18,8 @@
 //      complex points per row, split into the half spectrum), written over
 //      the spectra rows read in step 1, so the next field evaluation starts
 //      at the y pass.
+// The spectra are stored in blocks of KB consecutive kx (internal.h), so the
+// yt rows of a group read and write yt*KB contiguous values per block.
 #include <mutex>
 
 #include "fft_core.h"
@@ -115,7 +117,9 @@ struct UpdMaxThreads {    // FP64 groups stay at 512 threads (room for 256 VGPRs
     static constexpr int v = sizeof(T) == 8 ? 512 : 1024;
 };
 
-template <typename T, int M, int MODE>
+// NT: the new state and its spectrum go out as non-temporal stores (the
+// context's store mode, instantiated for the stepping mode only)
+template <typename T, int M, int MODE, bool NT>
 __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     k_update(UpdArgs a, Geom g, const cpx<T> *__restrict__ tw)
 {
@@ -186,8 +190,10 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const int partner = (lane - t) + ((TPL - t) & (TPL - 1));
     cpx<T> *L = scr + (lact ? l : 0) * LEN;
     cpx<T> *S1 = reinterpret_cast<cpx<T> *>(a.S1);
-    const long long kst = 3LL * g.nb * nz * ny;   // S1 stride between kx
-    cpx<T> *s1row = S1 + ((long long)(b * 3 + lc) * nz + z) * ny + y0 + (has ? lyy : 0);
+    // S1 in blocks of KB kx: X[k] of this row at s1row[(k / KB) * kst + k % KB]
+    const long long kst = 3LL * g.nb * nz * ny * KB;   // S1 stride between kx blocks
+    cpx<T> *s1row = S1 + (((long long)(b * 3 + lc) * nz + z) * ny + y0 + (has ? lyy : 0)) * KB;
+    auto s1k = [&](int k) -> long long { return (long long)(k >> KBS) * kst + (k & (KB - 1)); };
 
     // ---- prologue: issue the global loads up front, the cells first
     // cells: centre, neighbours (-x +x -y +y -z +z; a missing neighbour is
@@ -246,8 +252,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     if (a.elec_in) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q)
-            xa[q] = has ? s1row[(long long)(t + q * TPL) * kst] : cpx<T>{T(0), T(0)};
-        if (has && t == 0) xn = s1row[(long long)M2 * kst];
+            xa[q] = has ? s1row[s1k(t + q * TPL)] : cpx<T>{T(0), T(0)};
+        if (has && t == 0) xn = s1row[s1k(M2)];
     }
     // z neighbours in vacuum layers are dropped (they read as the centre)
     const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
@@ -464,7 +470,10 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             const bool store = !(MODE == UPD_STEP_RK && a.stage == 7);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if (store) Pout[c * comp + off] = o[c];
+                if (store) {
+                    if constexpr (NT) st_nt(&Pout[c * comp + off], o[c]);
+                    else Pout[c * comp + off] = o[c];
+                }
                 bad = bad || !isfinite(o[c]);
                 if (do_fx) hs[((c << ysh) + yy) * HS + x] = o[c];
             }
@@ -505,8 +514,13 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             cpx<T> xh;
             const cpx<T> xk = real_split(v[q], zm_, wk[q], xh);
             if (has) {
-                s1row[(long long)(t + q * TPL) * kst] = xk;
-                if (t == 0 && q == 0) s1row[(long long)M2 * kst] = xh;
+                if constexpr (NT) {
+                    st_nt(&s1row[s1k(t + q * TPL)], xk);
+                    if (t == 0 && q == 0) st_nt(&s1row[s1k(M2)], xh);
+                } else {
+                    s1row[s1k(t + q * TPL)] = xk;
+                    if (t == 0 && q == 0) s1row[s1k(M2)] = xh;
+                }
             }
         }
     }
@@ -583,9 +597,10 @@ static int rows_for(const Geom &g)
     const int maxthr = UpdMaxThreads<T>::v;
     const int ny_even = g.ny + (g.ny & 1);
     int best = 2;
-    // at most 8 rows for FP32 and 4 for FP64 (measured best on the
-    // 128x128x32 film; tdgl_autotune picks per grid)
-    const int ymax = sizeof(T) == 4 ? 8 : 4;
+    // at most 8 rows for FP32 and 4 for FP64, 2 for rows of 512 points or
+    // more (measured best on the 128x128x32 film and the 256x256x64
+    // bilayer; tdgl_autotune picks per grid)
+    const int ymax = M >= 512 ? 2 : (sizeof(T) == 4 ? 8 : 4);
     for (int yt = 2; yt <= ymax && yt <= (ny_even > 2 ? ny_even : 2); yt *= 2) {
         if (update_threads(g, yt, M >= 16 ? M / 16 : 1) > maxthr) break;
         if (update_lds<T, M>(g, yt) > 65536) break;
@@ -629,8 +644,17 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
     UpdArgs am = a;
     am.mgx = div_magic(grid.x, (unsigned long long)grid.x * grid.y);
     am.mnz = div_magic((unsigned)g.nz, (unsigned long long)g.nz * g.nb);
-    hipLaunchKernelGGL((k_update<T, M, MODE>), grid, dim3(nthr), shm, s, am, g,
-                       (const cpx<T> *)tw);
+    bool launched = false;
+    if constexpr (MODE == UPD_STEP) {
+        if (g.nt) {
+            hipLaunchKernelGGL((k_update<T, M, MODE, true>), grid, dim3(nthr), shm, s, am, g,
+                               (const cpx<T> *)tw);
+            launched = true;
+        }
+    }
+    if (!launched)
+        hipLaunchKernelGGL((k_update<T, M, MODE, false>), grid, dim3(nthr), shm, s, am, g,
+                           (const cpx<T> *)tw);
     return hipGetLastError();
 }
 

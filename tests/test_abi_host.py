@@ -87,6 +87,8 @@ def test_setter_validation_leaves_context_usable():
                      lambda: T.tdgl_set_terms(ctx, 16),
                      lambda: T.tdgl_set_temperature(ctx, -3.0),
                      lambda: T.tdgl_set_layer_materials(ctx, [0] * 7 + [20]),
+                     lambda: T.tdgl_set_z_tile(ctx, 96),
+                     lambda: T.tdgl_set_store_mode(ctx, 3),
                      lambda: T.tdgl_build_tensor(ctx, 65)):
             with pytest.raises(T.TdglError) as e:
                 call()
@@ -95,6 +97,16 @@ def test_setter_validation_leaves_context_usable():
             T.tdgl_set_gradient(ctx, 5.1e-10, float("nan"), 2e-11, 2e-11)
         assert e.value.status == T.TDGL_E_ARG
         T.tdgl_set_gradient(ctx, 5.1e-10, -2e-11, 2e-11, 2e-11)       # full eq 4 accepted
+        # the z-pass tile: a knob, resolved on the host
+        assert T.tdgl_get_z_tile(ctx) in (64, 128)
+        T.tdgl_set_z_tile(ctx, 256)
+        assert T.tdgl_get_z_tile(ctx) == 256
+        T.tdgl_set_z_tile(ctx, 0)
+        assert T.tdgl_get_store_mode(ctx) == 1          # one instance: non-temporal
+        T.tdgl_set_store_mode(ctx, 2)
+        assert T.tdgl_get_store_mode(ctx) == 2
+        T.tdgl_set_store_mode(ctx, 0)
+        assert T.tdgl_get_store_mode(ctx) == 1
         with pytest.raises(T.TdglError) as e:
             T.tdgl_step(ctx, 1)                                        # no P yet
         assert e.value.status == T.TDGL_E_STATE

@@ -297,3 +297,35 @@ def test_integrator_buffers_live_in_the_bound_workspace():
         ctx.close()
     ref = O.run(P0, O.Problem(dict(cfg, scheme="heun")), "heun", cfg["dtau"], 5)
     assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_tuning_knobs_do_not_change_results(prec):
+    """The z-pass tile and the store mode are launch choices only: every
+    combination advances the film (three passes) and a batch of three boxes
+    bit for bit as the built-in choice does."""
+    dt = np.float32 if prec == "f32" else np.float64
+    out = T.TDGL_FP32 if prec == "f32" else T.TDGL_FP64
+    film = I.config("c2_small")
+    box = I.config("c1")
+    box.update(n=(12, 10, 6), layers=[0] * 6, scheme="heun", T=[300.0, 350.0, 420.0])
+    for cfg, nb in ((film, 1), (box, 3)):
+        announce("tuning knobs %s, %d instance(s)" % (prec, nb))
+        P0 = I.initial_P(cfg, 3, dt) if nb == 1 else np.stack(
+            [I.initial_P(cfg, 3 + b, dt) for b in range(nb)])
+        results = {}
+        for zt in (0, 64, 128, 256):
+            for mode in (0, 1, 2):
+                ctx = T.Context(cfg, T.TDGL_FP32 if prec == "f32" else T.TDGL_FP64, batch=nb)
+                try:
+                    T.tdgl_set_fft_path(ctx.ctx, 1)
+                    T.tdgl_set_z_tile(ctx.ctx, zt)
+                    T.tdgl_set_store_mode(ctx.ctx, mode)
+                    ctx.set_P(P0)
+                    ctx.step(40)
+                    results[(zt, mode)] = ctx.get_P(out)
+                finally:
+                    ctx.close()
+        ref = results[(0, 0)]
+        for key, P in results.items():
+            assert np.array_equal(P, ref), key
