@@ -263,7 +263,7 @@ def run_c3(max_steps, check, tune_steps, seq_every):
     nrel = int(sum((r > 0).sum() for r in relaxed))
     return {
         "workload": "64 open BaTiO3 boxes: 24 of 32x32x32, 24 of 64x64x16, 16 of 96x96x8 "
-                    "(padded 64^3 / 128x128x32 / 256x256x16), T ~ U(200, 450) K, "
+                    "(padded 64^3 / 128x128x32 / 192x192x16), T ~ U(200, 450) K, "
                     "P ~ U(-0.1, 0.1), FP32 Heun dtau=1e-3",
         "criterion": "|dF| over %d steps < 1e-6 max(|F|, alpha_ref P0^2 1e-3 V), on the device"
                      % check,

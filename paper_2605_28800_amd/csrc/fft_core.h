@@ -1,17 +1,19 @@
-// Radix-8/4/2 Stockham FFT of one line per group of threads, for gfx950.
+// Mixed-radix Stockham FFT of one line per group of threads, for gfx950.
 //
-// A line of length M (power of two, 8..1024) is owned by M/8 threads.  Thread
-// t of the line holds the eight elements x[t + q*M/8], q = 0..7, in registers
-// on entry and the eight outputs X[t + q*M/8] (natural order) on exit.  Only
-// the exchanges between radix stages go through LDS, so a pass kernel can
-// load its inputs from and store its outputs to global memory directly, with
-// consecutive threads touching consecutive addresses.
+// A line of length M (a power of two, 8..1024, or 3 * 2^a, 12..768) is owned
+// by M/PPT threads of PPT points each (8 for powers of two, 12 otherwise).
+// Thread t of the line holds the elements x[t + q*M/PPT], q < PPT, in
+// registers on entry and the outputs X[t + q*M/PPT] (natural order) on exit.
+// Only the exchanges between radix stages go through LDS, so a pass kernel
+// can load its inputs from and store its outputs to global memory directly,
+// with consecutive threads touching consecutive addresses.
 //
 // Stage with radix R after stages of total length P (Stockham autosort):
 // butterfly i in [0, M/R), k = i mod P, inputs x[i + r M/R] twiddled by
 // W_{PR}^{rk}, R-point DFT, outputs to y[(i-k) R + k + r P].  The first stage
 // (P = 1) needs no twiddles and reads the registers; the last stage
 // (P R = M) writes y[i + r M/R], which is again the register layout.
+// Radices: 8, 4, 2 for powers of two; 4, 2 and a last 3 otherwise.
 //
 // Forward transforms use W = exp(-2 pi i/M); inverse transforms the
 // conjugate, unnormalised.
@@ -115,11 +117,27 @@ __device__ __forceinline__ void dft8(cpx<T> *v)
     }
 }
 
+// 3-point DFT: X0 = a + b + c, X1,2 = a - (b + c)/2 -/+ i (sqrt 3 / 2)(b - c)
+// for the forward transform (signs of the imaginary part swapped for the
+// inverse).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cpx<T> *v)
+{
+    const T h = T(0.86602540378443864676372317075294);     // sqrt(3) / 2
+    const cpx<T> s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const cpx<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    const cpx<T> r = INV ? cpx<T>{-h * d.y, h * d.x} : cpx<T>{h * d.y, -h * d.x};   // -/+ i h d
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftR(cpx<T> *v)
 {
     if constexpr (R == 8) dft8<T, INV>(v);
     else if constexpr (R == 4) dft4<T, INV>(v);
+    else if constexpr (R == 3) dft3<T, INV>(v);
     else dft2<T, INV>(v);
 }
 
@@ -153,25 +171,42 @@ struct LinePad {
     static constexpr int len = M + M / 8;   // LDS elements per line with IdxPad
 };
 
-// Radix schedule: stage 0 has P = 1, R = 8; stage s has P = 8^s and
-// R = min(8, M/P).  Each thread needs NB*(R-1) twiddles per stage s >= 1;
-// they depend only on the thread's position, so a kernel loads them into
-// registers at its start (TwReg), overlapping their latency with the data
-// loads, and the stages read them from registers.
+// Stockham plan of a line of M points.  M = 2^a: eight points per thread,
+// radix 8 while at least 8 points remain, then 4 or 2.  M = 3 * 2^a (a >= 2):
+// twelve points per thread, radix 4 while a multiple of 12 remains, one
+// radix 2 where 6 remain, and a last radix-3 stage, so that every stage
+// before the last has a power-of-two span P.
+template <int M>
+struct Plan {
+    static constexpr bool R3 = M % 3 == 0;
+    static constexpr int PPT = R3 ? 12 : 8;    // points per thread
+    static constexpr int TPL = M / PPT;        // threads per line
+    static constexpr int radix(int P)
+    {
+        return !R3 ? (M / P >= 8 ? 8 : M / P)
+                   : (M / P == 3 ? 3 : (M / P % 12 == 0 ? 4 : 2));
+    }
+};
+
+// Stage s spans P points (the product of the earlier radices) with radix R;
+// each thread does NB = PPT / R butterflies.  Each thread needs NB*(R-1)
+// twiddles per stage s >= 1; they depend only on the thread's position, so
+// a kernel loads them into registers at its start (TwReg), overlapping their
+// latency with the data loads, and the stages read them from registers.
 template <int M, int S>
 struct Stage {
-    static constexpr int P = S == 0 ? 1 : 8 * Stage<M, (S > 0 ? S - 1 : 0)>::P;
-    static constexpr int R = (M / P >= 8) ? 8 : (M / P);
-    static constexpr int NB = 8 / R;
+    using Prev = Stage<M, (S > 0 ? S - 1 : 0)>;
+    static constexpr int P = S == 0 ? 1 : Prev::P * Prev::R;
+    static constexpr int R = Plan<M>::radix(P);
+    static constexpr int NB = Plan<M>::PPT / R;
     static constexpr int NTW = S == 0 ? 0 : NB * (R - 1);
-    static constexpr int OFF = S == 0 ? 0 : Stage<M, (S > 0 ? S - 1 : 0)>::OFF +
-                                               Stage<M, (S > 0 ? S - 1 : 0)>::NTW;
+    static constexpr int OFF = S == 0 ? 0 : Prev::OFF + Prev::NTW;
     static constexpr bool LAST = P * R == M;
 };
 template <int M>
 struct Stage<M, 0> {
-    static constexpr int P = 1, R = 8, NB = 1, NTW = 0, OFF = 0;
-    static constexpr bool LAST = (M <= 8);
+    static constexpr int P = 1, R = Plan<M>::radix(1), NB = Plan<M>::PPT / R, NTW = 0, OFF = 0;
+    static constexpr bool LAST = (R == M);
 };
 
 template <int M, int S = 0>
@@ -191,9 +226,9 @@ template <typename T, int M, int S = 1>
 __device__ __forceinline__ void twiddle_load(TwReg<T, M> &tr, const cpx<T> *__restrict__ tab,
                                              int t)
 {
-    if constexpr (M > 8) {
+    if constexpr (!Stage<M, 0>::LAST) {
         using St = Stage<M, S>;
-        constexpr int TPL = M / 8;
+        constexpr int TPL = Plan<M>::TPL;
 #pragma unroll
         for (int b = 0; b < St::NB; ++b) {
             const int i = t + b * TPL;
@@ -209,13 +244,14 @@ __device__ __forceinline__ void twiddle_load(TwReg<T, M> &tr, const cpx<T> *__re
 // Stages s >= 1.  Every thread of the work-group must reach these barriers;
 // threads with act == false only skip memory traffic.
 template <typename T, int M, int S, bool INV, class Idx>
-__device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds, Idx idx, int t,
                                            const TwReg<T, M> &tr, bool act)
 {
     using St = Stage<M, S>;
     constexpr int R = St::R, NB = St::NB, P = St::P;
-    constexpr int TPL = M / 8;
+    constexpr int PPT = Plan<M>::PPT, TPL = Plan<M>::TPL;
     constexpr int MR = M / R;
+    static_assert((P & (P - 1)) == 0, "the span of a stage is a power of two");
     // element i + d of a read, j + r P of a write: constant offsets from one
     // base index when the displacements are multiples of 8
     constexpr bool FAST_READ = TPL % 8 == 0 && MR % 8 == 0;
@@ -248,9 +284,9 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx,
     }
     if constexpr (St::LAST) {
         if constexpr (NB > 1) {
-            cpx<T> tmp[8];
+            cpx<T> tmp[PPT];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) tmp[q] = v[q];
+            for (int q = 0; q < PPT; ++q) tmp[q] = v[q];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -278,24 +314,47 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[8], cpx<T> *lds, Idx idx,
     }
 }
 
-// Full line transform.  The caller must make sure no thread still reads the
-// line's LDS region from an earlier use (barrier) before calling, and must
-// barrier again before reusing it afterwards.  tr: this thread's twiddles
-// (twiddle_load with the forward table; the inverse conjugates them).
+// Full line transform: thread t holds elements t + q TPL (q < PPT) on entry
+// and the transform at the same positions on exit.  The caller must make
+// sure no thread still reads the line's LDS region from an earlier use
+// (barrier) before calling, and must barrier again before reusing it
+// afterwards.  tr: this thread's twiddles (twiddle_load with the forward
+// table; the inverse conjugates them).
 template <typename T, int M, bool INV, class Idx>
-__device__ __forceinline__ void fft_line(cpx<T> (&v)[8], cpx<T> *lds, Idx idx, int t,
+__device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds, Idx idx, int t,
                                          const TwReg<T, M> &tr, bool act)
 {
-    static_assert(M >= 8 && M <= 1024 && (M & (M - 1)) == 0, "length");
-    if (act) dft8<T, INV>(v);
-    if constexpr (M > 8) {
-        if (act) {
-            const int f8 = idx(8 * t);
+    static_assert(M >= 8 && M <= 1024 &&
+                      ((M & (M - 1)) == 0 || (M % 3 == 0 && M >= 12 && ((M / 3) & (M / 3 - 1)) == 0)),
+                  "length");
+    using S0 = Stage<M, 0>;
+    constexpr int R0 = S0::R, NB0 = S0::NB, TPL = Plan<M>::TPL;
+    if constexpr (NB0 == 1) {
+        // one radix-PPT butterfly over the thread's own elements
+        if (act) dftR<T, R0, INV>(v);
+        if constexpr (!S0::LAST) {
+            if (act) {
+                const int f8 = idx(R0 * t);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) lds[f8 + idx.near(r)] = v[r];
+                for (int r = 0; r < R0; ++r) lds[f8 + idx.near(r)] = v[r];
+            }
         }
-        fft_stages<T, M, 1, INV, Idx>(v, lds, idx, t, tr, act);
+    } else {
+        // butterfly b of the first stage takes the thread's elements b + NB0 r
+        // (points t + (b + NB0 r) TPL, i.e. i + r M/R0 with i = t + b TPL)
+        if (act) {
+#pragma unroll
+            for (int b = 0; b < NB0; ++b) {
+                cpx<T> u[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) u[r] = v[b + NB0 * r];
+                dftR<T, R0, INV>(u);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) lds[idx((t + b * TPL) * R0 + r)] = u[r];
+            }
+        }
     }
+    if constexpr (!S0::LAST) fft_stages<T, M, 1, INV, Idx>(v, lds, idx, t, tr, act);
 }
 
 // Quotient n / d of uniform operands through d's magic number m =
@@ -364,16 +423,16 @@ __device__ __forceinline__ cpx<T> real_merge(cpx<T> a, cpx<T> b, cpx<T> wk)
     return {e.x - d.y, e.y + d.x};
 }
 
-// Complex transform of one line of M2 points: M2/8 threads of eight points
-// each, or, for M2 = 4, one thread's registers.
+// Complex transform of one line of M2 points: the plan's threads of PPT
+// points each, or, for M2 = 4, one thread's registers.
 template <int M2>
 struct HalfLine {
-    static constexpr int PPT = M2 >= 8 ? 8 : M2;   // points per thread
-    static constexpr int TPL = M2 / PPT;           // threads per line
+    static constexpr int PPT = M2 >= 8 ? Plan<M2 >= 8 ? M2 : 8>::PPT : M2;   // points per thread
+    static constexpr int TPL = M2 / PPT;                                   // threads per line
 };
 
 template <typename T, int M2, bool INV>
-__device__ __forceinline__ void half_fft(cpx<T> (&v)[8], cpx<T> *lds, int t,
+__device__ __forceinline__ void half_fft(cpx<T> (&v)[HalfLine<M2>::PPT], cpx<T> *lds, int t,
                                          const TwReg<T, M2> &tr, bool act)
 {
     if constexpr (M2 >= 8) fft_line<T, M2, INV>(v, lds, IdxPad{}, t, tr, act);

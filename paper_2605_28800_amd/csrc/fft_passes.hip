@@ -51,11 +51,11 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     const long long r = r0 + l;
     const bool act = (l < lpw) && (r < nrows) && !fz.skip(r);
     TwReg<T, M2> tr;
-    twiddle_load(tr, tw + M2, t);
-    cpx<T> wk[8];
+    twiddle_load(tr, tw + tw_off(M2), t);
+    cpx<T> wk[PPT];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
-    cpx<T> v[8];
+    for (int q = 0; q < PPT; ++q) wk[q] = tw[tw_off(M) + t + q * TPL];
+    cpx<T> v[PPT];
     const T *row = in + (act ? r : 0) * in_stride;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -78,7 +78,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
         for (int q = 0; q < PPT; ++q) {
             const int k = t + q * TPL;
             cpx<T> xh;
-            stg[k * lpw + l] = real_split(zx[k], zx[(M2 - k) & (M2 - 1)], wk[q], xh);
+            stg[k * lpw + l] = real_split(zx[k], zx[k == 0 ? 0 : M2 - k], wk[q], xh);
             if (k == 0) stg[M2 * lpw + l] = xh;
         }
     }
@@ -112,7 +112,7 @@ __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long
                       long long out_stride, int n_in, int n_out, const cpx<T> *__restrict__ tw,
                       int lpw, Freeze fz)
 {
-    constexpr int TPL = M / 8;
+    constexpr int PPT = Plan<M>::PPT, TPL = Plan<M>::TPL;
     constexpr int LEN = LinePad<M>::len;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
@@ -123,19 +123,19 @@ __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long
     TwReg<T, M> tr;
     twiddle_load(tr, tw, t);
     const cpx<T> *src = in + (act ? line : 0) * in_stride;
-    cpx<T> v[8];
+    cpx<T> v[PPT];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int e = t + q * TPL;
-        const bool in_ok = (HALF && !INV) ? q < 4 : e < n_in;
+        const bool in_ok = (HALF && !INV) ? q < PPT / 2 : e < n_in;
         v[q] = (act && in_ok) ? src[e] : cpx<T>{T(0), T(0)};
     }
     fft_line<T, M, INV>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr, act);
     cpx<T> *dst = out + (act ? line : 0) * out_stride;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int e = t + q * TPL;
-        const bool out_ok = (HALF && INV) ? q < 4 : e < n_out;
+        const bool out_ok = (HALF && INV) ? q < PPT / 2 : e < n_out;
         if (act && out_ok) dst[e] = v[q];
     }
 }
@@ -152,7 +152,7 @@ __global__ void k_rowb(const cpx<T> *in, cpx<T> *out, int hx, unsigned R, unsign
                        int my, int n_in, int n_out, const cpx<T> *__restrict__ tw, int lpw,
                        Freeze fz, int nt)
 {
-    constexpr int TPL = M / 8;
+    constexpr int PPT = Plan<M>::PPT, TPL = Plan<M>::TPL;
     constexpr int LEN = LinePad<M>::len;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
@@ -169,27 +169,27 @@ __global__ void k_rowb(const cpx<T> *in, cpx<T> *out, int hx, unsigned R, unsign
     const long long b1 = (long long)rb * ny * KB + sub;     // S1 line
     const long long b2 = (long long)rb * my * KB + sub;     // S2 line
     const cpx<T> *src = in + (act ? (INV ? b2 : b1) : 0);
-    cpx<T> v[8];
+    cpx<T> v[PPT];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const int e = t + q * TPL;
-        const bool in_ok = (HALF && !INV) ? q < 4 : e < n_in;
+        const bool in_ok = (HALF && !INV) ? q < PPT / 2 : e < n_in;
         v[q] = (act && in_ok) ? src[(long long)e * KB] : cpx<T>{T(0), T(0)};
     }
     fft_line<T, M, INV>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr, act);
     cpx<T> *dst = out + (act ? (INV ? b1 : b2) : 0);
     if (nt) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < PPT; ++q) {
             const int e = t + q * TPL;
-            const bool out_ok = (HALF && INV) ? q < 4 : e < n_out;
+            const bool out_ok = (HALF && INV) ? q < PPT / 2 : e < n_out;
             if (act && out_ok) st_nt(&dst[(long long)e * KB], v[q]);
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < PPT; ++q) {
             const int e = t + q * TPL;
-            const bool out_ok = (HALF && INV) ? q < 4 : e < n_out;
+            const bool out_ok = (HALF && INV) ? q < PPT / 2 : e < n_out;
             if (act && out_ok) dst[(long long)e * KB] = v[q];
         }
     }
@@ -534,6 +534,26 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
 }
 
 // -------------------------------------------------------------- launchers
+// lengths of the x and y transforms: powers of two and 3 * 2^a
+#define TDGL_LEN_SWITCH_XY(M, CALL)                    \
+    switch (M) {                                       \
+    case 8: { constexpr int LEN_ = 8; CALL; }          \
+    case 16: { constexpr int LEN_ = 16; CALL; }        \
+    case 24: { constexpr int LEN_ = 24; CALL; }        \
+    case 32: { constexpr int LEN_ = 32; CALL; }        \
+    case 48: { constexpr int LEN_ = 48; CALL; }        \
+    case 64: { constexpr int LEN_ = 64; CALL; }        \
+    case 96: { constexpr int LEN_ = 96; CALL; }        \
+    case 128: { constexpr int LEN_ = 128; CALL; }      \
+    case 192: { constexpr int LEN_ = 192; CALL; }      \
+    case 256: { constexpr int LEN_ = 256; CALL; }      \
+    case 384: { constexpr int LEN_ = 384; CALL; }      \
+    case 512: { constexpr int LEN_ = 512; CALL; }      \
+    case 768: { constexpr int LEN_ = 768; CALL; }      \
+    case 1024: { constexpr int LEN_ = 1024; CALL; }    \
+    default: return hipErrorInvalidValue;              \
+    }
+
 #define TDGL_LEN_SWITCH(M, CALL)                       \
     switch (M) {                                       \
     case 8: { constexpr int LEN_ = 8; CALL; }          \
@@ -577,10 +597,10 @@ hipError_t launch_fx(int prec, int M, const void *in, long long nrows, int n_in,
                      hipStream_t s, Freeze fz, bool blocked)
 {
     if (prec == PREC_F32) {
-        TDGL_LEN_SWITCH(M, return (fx_impl<float, LEN_>(in, nrows, n_in, in_stride, out,
+        TDGL_LEN_SWITCH_XY(M, return (fx_impl<float, LEN_>(in, nrows, n_in, in_stride, out,
                                                          out_kstride, tw, s, fz, blocked)))
     } else {
-        TDGL_LEN_SWITCH(M, return (fx_impl<double, LEN_>(in, nrows, n_in, in_stride, out,
+        TDGL_LEN_SWITCH_XY(M, return (fx_impl<double, LEN_>(in, nrows, n_in, in_stride, out,
                                                           out_kstride, tw, s, fz, blocked)))
     }
 }
@@ -590,7 +610,7 @@ static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines
                            long long in_stride, long long out_stride, int n_in, int n_out,
                            const void *tw, hipStream_t s, Freeze fz)
 {
-    constexpr int TPL = M / 8;
+    constexpr int TPL = Plan<M>::TPL;
     const int lpw = TPL >= 128 ? 1 : 128 / TPL;     // 128-thread groups (measured best)
     const long long blocks = (nlines + lpw - 1) / lpw;
     if (blocks <= 0) return hipSuccess;
@@ -598,8 +618,8 @@ static hipError_t row_impl(bool inv, const void *in, void *out, long long nlines
     const dim3 grid((unsigned)blocks), blk(lpw * TPL);
     const cpx<T> *ci = (const cpx<T> *)in;
     cpx<T> *co = (cpx<T> *)out;
-    const cpx<T> *twm = (const cpx<T> *)tw + M;
-    // (the HALF forms need M >= 16: 8 points per thread, the upper 4 zero)
+    const cpx<T> *twm = (const cpx<T> *)tw + tw_off(M);
+    // (the HALF forms need at least two threads per line or M >= 16)
     const bool half = M >= 16 && (inv ? (n_out == M / 2 && n_in == M) : (n_in == M / 2));
     if (inv && half)
         hipLaunchKernelGGL((k_row<T, M, true, true>), grid, blk, shm, s, ci, co, nlines,
@@ -621,10 +641,10 @@ hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long
                       const void *tw, hipStream_t s, Freeze fz)
 {
     if (prec == PREC_F32) {
-        TDGL_LEN_SWITCH(M, return (row_impl<float, LEN_>(inv, in, out, nlines, in_stride,
+        TDGL_LEN_SWITCH_XY(M, return (row_impl<float, LEN_>(inv, in, out, nlines, in_stride,
                                                           out_stride, n_in, n_out, tw, s, fz)))
     } else {
-        TDGL_LEN_SWITCH(M, return (row_impl<double, LEN_>(inv, in, out, nlines, in_stride,
+        TDGL_LEN_SWITCH_XY(M, return (row_impl<double, LEN_>(inv, in, out, nlines, in_stride,
                                                            out_stride, n_in, n_out, tw, s, fz)))
     }
 }
@@ -632,7 +652,7 @@ hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long
 template <typename T, int M>
 static hipError_t rowb_prepare()
 {
-    constexpr int TPL = M / 8;
+    constexpr int TPL = Plan<M>::TPL;
     constexpr int lpw = TPL >= 128 / KB ? KB : 128 / TPL;
     constexpr size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
     if (shm <= 65536) return hipSuccess;
@@ -653,7 +673,7 @@ static hipError_t rowb_impl(bool inv, const void *S1, void *S2, int hx, long lon
                             int my, int n_in, int n_out, const void *tw, hipStream_t s,
                             Freeze fz, int nt)
 {
-    constexpr int TPL = M / 8;
+    constexpr int TPL = Plan<M>::TPL;
     // 128-thread groups as the plain row pass, but at least one block of KB lines
     // (above 64 KiB of LDS, i.e. 1024-point FP64 lines, rowb_prepare has
     // raised the kernels' limit)
@@ -666,7 +686,7 @@ static hipError_t rowb_impl(bool inv, const void *S1, void *S2, int hx, long lon
     const unsigned mR = div_magic((unsigned)R, (unsigned long long)blocks * (lpw / KB));
     const size_t shm = (size_t)lpw * LinePad<M>::len * sizeof(cpx<T>);
     const dim3 grid((unsigned)blocks), blk(lpw * TPL);
-    const cpx<T> *twm = (const cpx<T> *)tw + M;
+    const cpx<T> *twm = (const cpx<T> *)tw + tw_off(M);
     const bool half = M >= 16 && (inv ? (n_out == M / 2 && n_in == M) : (n_in == M / 2));
     const unsigned Ru = (unsigned)R;
     if (inv && half)
@@ -687,9 +707,9 @@ static hipError_t rowb_impl(bool inv, const void *S1, void *S2, int hx, long lon
 hipError_t prepare_row_blocked(int prec, int M)
 {
     if (prec == PREC_F32) {
-        TDGL_LEN_SWITCH(M, return (rowb_prepare<float, LEN_>()))
+        TDGL_LEN_SWITCH_XY(M, return (rowb_prepare<float, LEN_>()))
     } else {
-        TDGL_LEN_SWITCH(M, return (rowb_prepare<double, LEN_>()))
+        TDGL_LEN_SWITCH_XY(M, return (rowb_prepare<double, LEN_>()))
     }
 }
 
@@ -698,10 +718,10 @@ hipError_t launch_row_blocked(int prec, int M, bool inv, const void *S1, void *S
                               hipStream_t s, Freeze fz, int nt)
 {
     if (prec == PREC_F32) {
-        TDGL_LEN_SWITCH(M, return (rowb_impl<float, LEN_>(inv, S1, S2, hx, R, ny, my, n_in,
+        TDGL_LEN_SWITCH_XY(M, return (rowb_impl<float, LEN_>(inv, S1, S2, hx, R, ny, my, n_in,
                                                            n_out, tw, s, fz, nt)))
     } else {
-        TDGL_LEN_SWITCH(M, return (rowb_impl<double, LEN_>(inv, S1, S2, hx, R, ny, my, n_in,
+        TDGL_LEN_SWITCH_XY(M, return (rowb_impl<double, LEN_>(inv, S1, S2, hx, R, ny, my, n_in,
                                                             n_out, tw, s, fz, nt)))
     }
 }
@@ -734,11 +754,11 @@ static hipError_t col_impl(bool inv, const void *in, void *out, long long C, lon
     if (inv)
         hipLaunchKernelGGL((k_col<T, M, true>), grid, dim3(ct * TPL), shm, s,
                            (const cpx<T> *)in, (cpx<T> *)out, C, ncols, ct, in_bstride,
-                           out_bstride, lstride, n_in, n_out, (const cpx<T> *)tw + M);
+                           out_bstride, lstride, n_in, n_out, (const cpx<T> *)tw + tw_off(M));
     else
         hipLaunchKernelGGL((k_col<T, M, false>), grid, dim3(ct * TPL), shm, s,
                            (const cpx<T> *)in, (cpx<T> *)out, C, ncols, ct, in_bstride,
-                           out_bstride, lstride, n_in, n_out, (const cpx<T> *)tw + M);
+                           out_bstride, lstride, n_in, n_out, (const cpx<T> *)tw + tw_off(M));
     return hipGetLastError();
 }
 
@@ -771,11 +791,11 @@ static hipError_t zmul_tile(const Geom &g, void *S, const void *Nt, const void *
     if (2 * g.nz == MZ)
         hipLaunchKernelGGL((k_zmul<T, MZ, RB, true>), dim3(gx, nkb * g.nb), dim3(C::NTHR), shm,
                            s, (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.hx, g.nb,
-                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb, g.nt);
+                           (const cpx<T> *)tw + tw_off(MZ), g.frozen, mgx, mnb, g.nt);
     else
         hipLaunchKernelGGL((k_zmul<T, MZ, RB, false>), dim3(gx, nkb * g.nb), dim3(C::NTHR), shm,
                            s, (cpx<T> *)S, (const T *)Nt, g.nz, g.my, g.hx, g.nb,
-                           (const cpx<T> *)tw + MZ, g.frozen, mgx, mnb, g.nt);
+                           (const cpx<T> *)tw + tw_off(MZ), g.frozen, mgx, mnb, g.nt);
     return hipGetLastError();
 }
 
@@ -829,8 +849,8 @@ static hipError_t plane_impl(const Geom &g, void *S1, const void *Nt, const void
         return hipSuccess;
     }
     hipLaunchKernelGGL((k_plane<T, MY, MZ>), dim3(g.hx * g.nb), dim3(C::NTHR), shm, s,
-                       (cpx<T> *)S1, (const T *)Nt, g.ny, g.nz, g.nb, (const cpx<T> *)tw + MY,
-                       (const cpx<T> *)tw + MZ, g.frozen);
+                       (cpx<T> *)S1, (const T *)Nt, g.ny, g.nz, g.nb,
+                       (const cpx<T> *)tw + tw_off(MY), (const cpx<T> *)tw + tw_off(MZ), g.frozen);
     return hipGetLastError();
 }
 

@@ -10,6 +10,13 @@ namespace tdgl {
 
 constexpr int NCOEF = 12;      // per z layer: a1x a1y a1z a11 a12 a111 a112 a123, material, pad
 constexpr int MAXLEN = 1024;   // largest FFT length
+// twiddle tables of every length L (W_L^k, k < L): powers of two at offset L,
+// lengths 3 * 2^a at 2 MAXLEN + L (tw_off in fft_core.h)
+constexpr int TW_ENTRIES = 4 * MAXLEN;
+__host__ __device__ constexpr int tw_off(int L)
+{
+    return (L & (L - 1)) == 0 ? L : 2 * MAXLEN + L;
+}
 constexpr int GL_MAXN = 24;    // Gauss-Legendre table rows/columns
 
 enum { PREC_F32 = 0, PREC_F64 = 1 };

@@ -57,6 +57,17 @@ int next_pow2(int v)
     return p;
 }
 
+// FFT length for an open x or y dimension of n cells: the smallest power of
+// two or 3 * 2^a (at least 24) that holds the 2n - 1 offsets, at least 8
+int fft_len_xy(int n)
+{
+    const int p = next_pow2(2 * n - 1);
+    int t = 24;
+    while (t < 2 * n - 1) t <<= 1;
+    const int m = t < p ? t : p;
+    return m < 8 ? 8 : m;
+}
+
 }  // namespace
 
 struct tdgl_ctx {
@@ -165,8 +176,8 @@ Layout layout_of(const tdgl_ctx *c, int scheme)
     L.Nt = take((size_t)6 * (g.mz / 2 + 1) * (g.my / 2 + 1) * hx_blocked(g.hx) * c->esz);
     L.coef = take((size_t)g.nb * g.nz * NCOEF * c->esz);
     L.kp = take(sizeof(KParams<double>));
-    L.twf = take((size_t)2 * MAXLEN * 2 * sizeof(float));
-    L.twd = take((size_t)2 * MAXLEN * 2 * sizeof(double));
+    L.twf = take((size_t)TW_ENTRIES * 2 * sizeof(float));
+    L.twd = take((size_t)TW_ENTRIES * 2 * sizeof(double));
     L.gl = take((size_t)2 * GL_MAXN * GL_MAXN * sizeof(double));
     L.partials = take((size_t)c->nblocks * g.nb * 8 * sizeof(double));
     L.flag = take(sizeof(int));
@@ -225,13 +236,17 @@ void gauss_legendre_tables(double *t, double *w)
 template <typename T>
 std::vector<T> twiddle_table()
 {
-    std::vector<T> tw(2 * 2 * MAXLEN, T(0));
-    for (int M = 1; M <= MAXLEN; M <<= 1)
+    std::vector<T> tw(2 * TW_ENTRIES, T(0));
+    auto fill = [&](int M) {
+        const int o = tw_off(M);
         for (int k = 0; k < M; ++k) {
             const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / M;
-            tw[2 * (M + k)] = (T)cosl(a);
-            tw[2 * (M + k) + 1] = (T)sinl(a);
+            tw[2 * (o + k)] = (T)cosl(a);
+            tw[2 * (o + k) + 1] = (T)sinl(a);
         }
+    };
+    for (int M = 1; M <= MAXLEN; M <<= 1) fill(M);           // powers of two
+    for (int M = 12; M <= MAXLEN; M <<= 1) fill(M);          // 3 * 2^a
     return tw;
 }
 
@@ -783,8 +798,10 @@ tdgl_status tdgl_create_batch(const tdgl_grid *grid, int nbatch, int precision, 
         if (pm >> k & 1u) {
             if (n[k] < 8 || (n[k] & (n[k] - 1)) != 0) return TDGL_E_UNSUPPORTED;
             m[k] = n[k];
+        } else if (k < 2) {
+            m[k] = fft_len_xy(n[k]);
         } else {
-            m[k] = next_pow2(2 * n[k] - 1);
+            m[k] = next_pow2(2 * n[k] - 1);     // the z pass takes powers of two
             if (m[k] < 8) m[k] = 8;
         }
         if (m[k] > MAXLEN) return TDGL_E_UNSUPPORTED;

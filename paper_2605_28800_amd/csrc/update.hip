@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     // the spectrum X[k], k = t + q*TPL, of this thread's row (lane t = 0 also
     // reads X[M/2]), issued behind the cell loads: the local terms below wait
     // for the cells only, the transform for these
-    cpx<T> xa[8], xn = {T(0), T(0)};
+    cpx<T> xa[PPT], xn = {T(0), T(0)};
     if (a.elec_in) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q)
@@ -339,16 +339,16 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     // twiddles of the transforms (a small table, cached): loaded here, not in
     // the prologue, so that they do not occupy registers during the local terms
     TwReg<T, M2> tr;
-    cpx<T> wk[8];                              // W_M^k, k = t + q*TPL
+    cpx<T> wk[PPT];                            // W_M^k, k = t + q*TPL
     if (a.elec_in || do_fx) {
-        twiddle_load(tr, tw + M2, t);
+        twiddle_load(tr, tw + tw_off(M2), t);
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) wk[q] = tw[M + t + q * TPL];
+        for (int q = 0; q < PPT; ++q) wk[q] = tw[tw_off(M) + t + q * TPL];
     }
 
     // ---- 1. electrostatic field rows (inverse x transform, half length)
     if (a.elec_in) {
-        cpx<T> v[8];
+        cpx<T> v[PPT];
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             // X[M2 - k]: lane TPL - t, point PPT-1-q; for t = 0 it is this
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     // ---- 3. x spectrum of the new rows (half length), written back kx-major
     if (do_fx) {
         __syncthreads();
-        cpx<T> v[8];
+        cpx<T> v[PPT];
         const T *ha = hs + (lact ? l : 0) * HS;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
@@ -602,7 +602,7 @@ static int rows_for(const Geom &g)
     // bilayer; tdgl_autotune picks per grid)
     const int ymax = M >= 512 ? 2 : (sizeof(T) == 4 ? 8 : 4);
     for (int yt = 2; yt <= ymax && yt <= (ny_even > 2 ? ny_even : 2); yt *= 2) {
-        if (update_threads(g, yt, M >= 16 ? M / 16 : 1) > maxthr) break;
+        if (update_threads(g, yt, HalfLine<M / 2>::TPL) > maxthr) break;
         if (update_lds<T, M>(g, yt) > 65536) break;
         best = yt;
     }
@@ -613,11 +613,17 @@ static int rows_for(const Geom &g)
     switch (g.mx) {                                        \
     case 8: return rows_for<T, 8>(g);                      \
     case 16: return rows_for<T, 16>(g);                    \
+    case 24: return rows_for<T, 24>(g);                    \
     case 32: return rows_for<T, 32>(g);                    \
+    case 48: return rows_for<T, 48>(g);                    \
     case 64: return rows_for<T, 64>(g);                    \
+    case 96: return rows_for<T, 96>(g);                    \
     case 128: return rows_for<T, 128>(g);                  \
+    case 192: return rows_for<T, 192>(g);                  \
     case 256: return rows_for<T, 256>(g);                  \
+    case 384: return rows_for<T, 384>(g);                  \
     case 512: return rows_for<T, 512>(g);                  \
+    case 768: return rows_for<T, 768>(g);                  \
     case 1024: return rows_for<T, 1024>(g);                \
     default: return 2;                                     \
     }
@@ -635,7 +641,7 @@ template <typename T, int M, int MODE>
 static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, hipStream_t s,
                               int *nblocks_out)
 {
-    const int nthr = update_threads(g, a.yt, M >= 16 ? M / 16 : 1);
+    const int nthr = update_threads(g, a.yt, HalfLine<M / 2>::TPL);
     const size_t shm = update_lds<T, M>(g, a.yt);
     if (shm > 65536 || nthr > UpdMaxThreads<T>::v) return hipErrorInvalidConfiguration;
     if ((long long)g.nz * g.nb > 65535) return hipErrorInvalidValue;
@@ -671,11 +677,17 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
     switch (g.mx) {                                            \
     case 8: TDGL_MODE_SWITCH(T, 8)                             \
     case 16: TDGL_MODE_SWITCH(T, 16)                           \
+    case 24: TDGL_MODE_SWITCH(T, 24)                           \
     case 32: TDGL_MODE_SWITCH(T, 32)                           \
+    case 48: TDGL_MODE_SWITCH(T, 48)                           \
     case 64: TDGL_MODE_SWITCH(T, 64)                           \
+    case 96: TDGL_MODE_SWITCH(T, 96)                           \
     case 128: TDGL_MODE_SWITCH(T, 128)                         \
+    case 192: TDGL_MODE_SWITCH(T, 192)                         \
     case 256: TDGL_MODE_SWITCH(T, 256)                         \
+    case 384: TDGL_MODE_SWITCH(T, 384)                         \
     case 512: TDGL_MODE_SWITCH(T, 512)                         \
+    case 768: TDGL_MODE_SWITCH(T, 768)                         \
     case 1024: TDGL_MODE_SWITCH(T, 1024)                       \
     default: return hipErrorInvalidValue;                      \
     }

@@ -62,7 +62,9 @@ def test_create_rejects(n, d, pm, status):
 
 @pytest.mark.parametrize("n,pm,dims", [
     ((16, 16, 8), 0, (32, 32, 16)),
-    ((12, 10, 5), 0, (32, 32, 16)),
+    ((12, 10, 5), 0, (24, 24, 16)),          # x, y: 3 * 2^a lengths; z: powers of two
+    ((96, 96, 8), 0, (192, 192, 16)),
+    ((16, 12, 12), 0, (32, 24, 32)),
     ((1, 1, 1), 0, (8, 8, 8)),
     ((128, 128, 32), 3, (128, 128, 64)),
     ((256, 256, 64), 0, (512, 512, 128)),

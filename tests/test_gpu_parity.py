@@ -38,6 +38,10 @@ CASES = {
                                    layers=[0, 0, 0, 1, 1, -1], two_materials=True),
     # 512-point x transforms: the update tile needs more than 64 KiB of LDS
     "open_long_rows_256x8x4": dict(n=(256, 8, 4), periodic=(0, 0, 0)),
+    # transform lengths 3 * 2^a (radix-3 last stage): 192 in x and y (the
+    # batched workload's 96x96x8 boxes), 96 and 48 in x and y
+    "open_96x96x8": dict(n=(96, 96, 8), periodic=(0, 0, 0)),
+    "open_48x24x4": dict(n=(48, 24, 4), periodic=(0, 0, 0)),
 }
 
 
