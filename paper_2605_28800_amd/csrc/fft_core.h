@@ -241,9 +241,24 @@ __device__ __forceinline__ void twiddle_load(TwReg<T, M> &tr, const cpx<T> *__re
     }
 }
 
-// Stages s >= 1.  Every thread of the work-group must reach these barriers;
-// threads with act == false only skip memory traffic.
-template <typename T, int M, int S, bool INV, class Idx>
+// Barrier between the stages of a line: the whole work-group, or (WAVE)
+// only the wave, when every line of the caller lies within one wave (then
+// the other waves of the group need not take part).
+template <bool WAVE>
+__device__ __forceinline__ void line_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Stages s >= 1.  Every thread of the work-group (WAVE: of the wave) must
+// reach these barriers; threads with act == false only skip memory traffic.
+template <typename T, int M, int S, bool INV, class Idx, bool WAVE = false>
 __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds, Idx idx, int t,
                                            const TwReg<T, M> &tr, bool act)
 {
@@ -256,7 +271,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
     // base index when the displacements are multiples of 8
     constexpr bool FAST_READ = TPL % 8 == 0 && MR % 8 == 0;
     constexpr bool FAST_WRITE = P % 8 == 0;
-    __syncthreads();
+    line_sync<WAVE>();
     if (act) {
         if constexpr (FAST_READ) {
             const int f0 = idx(t);
@@ -293,7 +308,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
                 for (int r = 0; r < R; ++r) v[b + r * NB] = tmp[b * R + r];
         }
     } else {
-        __syncthreads();
+        line_sync<WAVE>();
         if (act) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -310,7 +325,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
                 }
             }
         }
-        fft_stages<T, M, S + 1, INV, Idx>(v, lds, idx, t, tr, act);
+        fft_stages<T, M, S + 1, INV, Idx, WAVE>(v, lds, idx, t, tr, act);
     }
 }
 
@@ -320,7 +335,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
 // (barrier) before calling, and must barrier again before reusing it
 // afterwards.  tr: this thread's twiddles (twiddle_load with the forward
 // table; the inverse conjugates them).
-template <typename T, int M, bool INV, class Idx>
+template <typename T, int M, bool INV, class Idx, bool WAVE = false>
 __device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds, Idx idx, int t,
                                          const TwReg<T, M> &tr, bool act)
 {
@@ -354,7 +369,7 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds,
             }
         }
     }
-    if constexpr (!S0::LAST) fft_stages<T, M, 1, INV, Idx>(v, lds, idx, t, tr, act);
+    if constexpr (!S0::LAST) fft_stages<T, M, 1, INV, Idx, WAVE>(v, lds, idx, t, tr, act);
 }
 
 // Quotient n / d of uniform operands through d's magic number m =
@@ -431,11 +446,11 @@ struct HalfLine {
     static constexpr int TPL = M2 / PPT;                                   // threads per line
 };
 
-template <typename T, int M2, bool INV>
+template <typename T, int M2, bool INV, bool WAVE = false>
 __device__ __forceinline__ void half_fft(cpx<T> (&v)[HalfLine<M2>::PPT], cpx<T> *lds, int t,
                                          const TwReg<T, M2> &tr, bool act)
 {
-    if constexpr (M2 >= 8) fft_line<T, M2, INV>(v, lds, IdxPad{}, t, tr, act);
+    if constexpr (M2 >= 8) fft_line<T, M2, INV, IdxPad, WAVE>(v, lds, IdxPad{}, t, tr, act);
     else if (act) dft4<T, INV>(v);
 }
 

@@ -176,7 +176,10 @@ __global__ void k_rowb(const cpx<T> *in, cpx<T> *out, int hx, unsigned R, unsign
         const bool in_ok = (HALF && !INV) ? q < PPT / 2 : e < n_in;
         v[q] = (act && in_ok) ? src[(long long)e * KB] : cpx<T>{T(0), T(0)};
     }
-    fft_line<T, M, INV>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr, act);
+    // a line's lanes (KB * TPL of them) lie within one wave where 4 TPL <= 64:
+    // its stages then need wave-level barriers only
+    fft_line<T, M, INV, IdxPad, KB * TPL <= 64>(v, lds + (l < lpw ? l : 0) * LEN, IdxPad{}, t, tr,
+                                                act);
     cpx<T> *dst = out + (act ? (INV ? b1 : b2) : 0);
     if (nt) {
 #pragma unroll
@@ -357,7 +360,9 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
     twiddle_load(tr, tw, t);
     const IdxStridePad ip{CT};
     cpx<T> *L = lds + c * LZ * CT + cc;
-    fft_line<T, MZ, false>(v, L, ip, t, tr, act);
+    // a column's lanes lie within one wave where CT TPL <= 64
+    constexpr bool WAVE = CT * TPL <= 64;
+    fft_line<T, MZ, false, IdxStridePad, WAVE>(v, L, ip, t, tr, act);
     // element kz = t + q*TPL of a line sits at ip(t) + ip.shift(q*TPL) when
     // TPL is a multiple of 8 (a constant offset per q)
     auto ipq = [&](int q) {
@@ -382,7 +387,7 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
         }
     }
     __syncthreads();
-    fft_line<T, MZ, true>(v, L, ip, t, tr, act);
+    fft_line<T, MZ, true, IdxStridePad, WAVE>(v, L, ip, t, tr, act);
     if (nt) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {

@@ -1,14 +1,17 @@
 // Fused local-field and time-integration kernel.
 //
 // One work-group owns yt consecutive rows (all x) of one z layer, for all
-// three components.  In order:
-//   1. inverse x transform of the electrostatic field rows: each real row of
-//      padded length M is one complex line of M/2 points (even samples real,
-//      odd samples imaginary), built from the half spectrum on the fly;
-//   2. per cell: Landau field (minus the P-derivative of eq 3), gradient
-//      field (eq 4, diagonal part, 7-point stencil; neighbours across an open
-//      surface or in vacuum are dropped, periodic dimensions wrap), applied
-//      field (eq 7) and the electrostatic field (eqs 5-6), then
+// three components:
+//   0. per cell (all waves): Landau field (minus the P-derivative of eq 3),
+//      gradient field (eq 4, diagonal part, 7-point stencil; neighbours
+//      across an open surface or in vacuum are dropped, periodic dimensions
+//      wrap) and the cross terms' field;
+//   1. (the waves that hold the x lines, beside step 0) inverse x transform
+//      of the electrostatic field rows: each real row of padded length M is
+//      one complex line of M/2 points (even samples real, odd samples
+//      imaginary), built from the half spectrum on the fly;
+//   2. after one barrier, per cell: the electrostatic field (eqs 5-6) and
+//      the applied field (eq 7) are added, then
 //        STEP  : an explicit stage of eq 1 (L = 1, reduced time):
 //                stage 0  P_out = P_in + dtau E          (Euler / Heun predictor)
 //                stage 1  P_out = (P_old + P_in)/2 + dtau/2 E   (Heun corrector)
@@ -194,6 +197,75 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const long long kst = 3LL * g.nb * nz * ny * KB;   // S1 stride between kx blocks
     cpx<T> *s1row = S1 + (((long long)(b * 3 + lc) * nz + z) * ny + y0 + (has ? lyy : 0)) * KB;
     auto s1k = [&](int k) -> long long { return (long long)(k >> KBS) * kst + (k & (KB - 1)); };
+    // the waves that hold the x lines (every line lies within one wave, so
+    // their transforms need wave-level barriers only, and the waves without
+    // lines never wait for them before the field rows are complete)
+    const int fft_waves = (nrows * TPL + 63) >> 6;
+    const bool lwave = (tid >> 6) < fft_waves;          // uniform per wave
+    const bool fftw = a.elec_in && lwave;
+
+    // twiddles of the transforms (a small table, cached)
+    TwReg<T, M2> tr;
+    cpx<T> wk[PPT];                            // W_M^k, k = t + q*TPL
+    auto load_twiddles = [&]() {
+        twiddle_load(tr, tw + tw_off(M2), t);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) wk[q] = tw[tw_off(M) + t + q * TPL];
+    };
+
+    // ---- 1. (line waves) electrostatic field rows: the spectrum X[k],
+    // k = t + q*TPL, of this thread's row (lane t = 0 also reads X[M/2]),
+    // inverse x transform of half length, rows into LDS.  For rows of up to
+    // 128 points (early: the line waves are few among the cell waves) the
+    // line waves do this before loading their cells, while the other waves
+    // work on their local terms; for longer rows, where most waves hold
+    // lines, after the local terms (measured on the 128x128x32 film and the
+    // 256x256x64 bilayer).
+    constexpr bool early = M <= 128;
+    cpx<T> xa[PPT], xn = {T(0), T(0)};
+    auto load_spectra = [&]() {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            xa[q] = has ? s1row[s1k(t + q * TPL)] : cpx<T>{T(0), T(0)};
+        if (has && t == 0) xn = s1row[s1k(M2)];
+    };
+    auto field_rows = [&]() {
+        load_twiddles();
+        cpx<T> v[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            // X[M2 - k]: lane TPL - t, point PPT-1-q; for t = 0 it is this
+            // lane's point PPT - q (or X[M2] at q = 0)
+            const int qs = PPT - 1 - q;
+            cpx<T> b = {__shfl(xa[qs].x, partner, 64), __shfl(xa[qs].y, partner, 64)};
+            if (t == 0) b = q == 0 ? xn : xa[(PPT - q) % PPT];
+            cpx<T> A = xa[q];
+            if (t == 0 && q == 0) {                    // X[0], X[M/2] are real
+                A.y = T(0);
+                b.y = T(0);
+            }
+            v[q] = real_merge(A, b, wk[q]);
+        }
+        half_fft<T, M2, true, true>(v, L, t, tr, lact);
+        if (lact) {
+            T *ha = hs + l * HS;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const int n = t + q * TPL;
+                if (2 * n + 1 < nx) {
+                    *reinterpret_cast<cpx<T> *>(ha + 2 * n) = v[q];
+                } else if (2 * n < nx) {
+                    ha[2 * n] = v[q].x;
+                }
+            }
+        }
+    };
+    if constexpr (early) {
+        if (fftw) {
+            load_spectra();
+            field_rows();
+        }
+    }
 
     // ---- prologue: issue the global loads up front, the cells first
     // cells: centre, neighbours (-x +x -y +y -z +z; a missing neighbour is
@@ -245,15 +317,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     }
 
 
-    // the spectrum X[k], k = t + q*TPL, of this thread's row (lane t = 0 also
-    // reads X[M/2]), issued behind the cell loads: the local terms below wait
-    // for the cells only, the transform for these
-    cpx<T> xa[PPT], xn = {T(0), T(0)};
-    if (a.elec_in) {
-#pragma unroll
-        for (int q = 0; q < PPT; ++q)
-            xa[q] = has ? s1row[s1k(t + q * TPL)] : cpx<T>{T(0), T(0)};
-        if (has && t == 0) xn = s1row[s1k(M2)];
+    if constexpr (!early) {
+        if (fftw) load_spectra();                   // behind the cell loads
     }
     // z neighbours in vacuum layers are dropped (they read as the centre)
     const bool hzm = zm >= 0 && coef0[(long long)zm * NCOEF + 8] != T(0);
@@ -267,8 +332,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                 if (!hzp) cn[i][5][c] = cp[i][c];
             }
     }
-    // ---- 0. local terms of every cell (Landau, gradient, cross terms) while
-    // the spectra are still arriving; the neighbours are dead afterwards
+    // ---- 0. local terms of every cell (Landau, gradient, cross terms); the
+    // neighbours are dead afterwards
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     T Eloc[CPT][3];
 #pragma unroll
@@ -336,48 +401,11 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         (void)fg;
     }
 
-    // twiddles of the transforms (a small table, cached): loaded here, not in
-    // the prologue, so that they do not occupy registers during the local terms
-    TwReg<T, M2> tr;
-    cpx<T> wk[PPT];                            // W_M^k, k = t + q*TPL
-    if (a.elec_in || do_fx) {
-        twiddle_load(tr, tw + tw_off(M2), t);
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) wk[q] = tw[tw_off(M) + t + q * TPL];
+    if constexpr (!early) {
+        if (fftw) field_rows();
     }
-
-    // ---- 1. electrostatic field rows (inverse x transform, half length)
-    if (a.elec_in) {
-        cpx<T> v[PPT];
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            // X[M2 - k]: lane TPL - t, point PPT-1-q; for t = 0 it is this
-            // lane's point PPT - q (or X[M2] at q = 0)
-            const int qs = PPT - 1 - q;
-            cpx<T> b = {__shfl(xa[qs].x, partner, 64), __shfl(xa[qs].y, partner, 64)};
-            if (t == 0) b = q == 0 ? xn : xa[(PPT - q) % PPT];
-            cpx<T> A = xa[q];
-            if (t == 0 && q == 0) {                    // X[0], X[M/2] are real
-                A.y = T(0);
-                b.y = T(0);
-            }
-            v[q] = real_merge(A, b, wk[q]);
-        }
-        half_fft<T, M2, true>(v, L, t, tr, lact);
-        if (lact) {
-            T *ha = hs + l * HS;
-#pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                const int n = t + q * TPL;
-                if (2 * n + 1 < nx) {
-                    *reinterpret_cast<cpx<T> *>(ha + 2 * n) = v[q];
-                } else if (2 * n < nx) {
-                    ha[2 * n] = v[q].x;
-                }
-            }
-        }
-        __syncthreads();
-    }
+    if (do_fx && lwave && !fftw) load_twiddles();
+    if (a.elec_in) __syncthreads();                // the field rows are in LDS
 
     // ---- 2. the electrostatic and applied fields, and the update
     const T dtau = kp->dtau;
@@ -490,8 +518,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     }
 
     // ---- 3. x spectrum of the new rows (half length), written back kx-major
-    if (do_fx) {
-        __syncthreads();
+    if (do_fx) __syncthreads();                    // the new rows are in LDS
+    if (do_fx && lwave) {
         cpx<T> v[PPT];
         const T *ha = hs + (lact ? l : 0) * HS;
 #pragma unroll
@@ -503,7 +531,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                 v[q] = {(has && 2 * n < nx) ? ha[2 * n] : T(0), T(0)};
             }
         }
-        half_fft<T, M2, false>(v, L, t, tr, lact);
+        half_fft<T, M2, false, true>(v, L, t, tr, lact);
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             // Z[M2 - k]: as for the inverse; for t = 0 this lane's point
