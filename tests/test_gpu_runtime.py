@@ -309,7 +309,11 @@ def test_tuning_knobs_do_not_change_results(prec):
     film = I.config("c2_small")
     box = I.config("c1")
     box.update(n=(12, 10, 6), layers=[0] * 6, scheme="heun", T=[300.0, 350.0, 420.0])
-    for cfg, nb in ((film, 1), (box, 3)):
+    # a tall box: 64-point z transforms, where the tile widths change how
+    # many lines a wave holds
+    tall = I.config("c1")
+    tall.update(n=(8, 8, 32), layers=[0] * 32, scheme="heun", T=300.0)
+    for cfg, nb in ((film, 1), (box, 3), (tall, 1)):
         announce("tuning knobs %s, %d instance(s)" % (prec, nb))
         P0 = I.initial_P(cfg, 3, dt) if nb == 1 else np.stack(
             [I.initial_P(cfg, 3 + b, dt) for b in range(nb)])
