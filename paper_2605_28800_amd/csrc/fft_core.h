@@ -45,6 +45,21 @@ __device__ __forceinline__ void st_nt(cpx<T> *p, cpx<T> v)
 template <typename T>
 __device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
 
+// A value at a uniform base plus a 32-bit byte offset.  Written this way
+// (the offset zero-extended next to the access) the load takes the
+// scalar-base form, one 32-bit offset register per access, instead of a
+// 64-bit address per lane: callers keep the offsets below 2^32 bytes.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *base, unsigned boff)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ T *at(T *base, unsigned boff)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff);
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>

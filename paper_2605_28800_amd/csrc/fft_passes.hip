@@ -323,8 +323,11 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
     cpx<T> *plane = S + (long long)kbb * 3 * nz * myb;
     const int hy = my / 2 + 1, hz = MZ / 2 + 1;
     const unsigned qs = (unsigned)hz * hy * KB;      // one tensor component of a block
-    const T *tplane = Nt + (long long)kblk * 6 * qs + (kxc & (KB - 1));
+    // uniform base of the block's octant; byte offsets within it (an octant
+    // block holds 6 KB (MZ/2+1)(my/2+1) values, far below 2^32 bytes)
+    const T *tplane = Nt + (long long)kblk * 6 * qs;
     const unsigned col = (unsigned)(c * nz) * myb + (act ? j : 0);
+    constexpr unsigned CSZ = sizeof(cpx<T>);         // byte offsets: 3 nz myb CSZ < 2^32
     // data first: the forward transform waits for these loads only, the
     // tensor loads behind them complete during the transform
     cpx<T> v[8];
@@ -332,7 +335,7 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
     for (int q = 0; q < 8; ++q) {
         const int z = t + q * TPL;
         const bool in = HALF ? q < 4 : z < nz;
-        v[q] = (act && in) ? plane[col + (unsigned)z * myb] : cpx<T>{T(0), T(0)};
+        v[q] = (act && in) ? ld_at(plane, (col + (unsigned)z * myb) * CSZ) : cpx<T>{T(0), T(0)};
     }
     // row c of the tensor: components (c,x) (c,y) (c,z) of the octant store
     // Nt(kx, comp, kz', ky') (comp: xx yy zz xy xz yz), KB-blocked in kx; xy
@@ -345,16 +348,19 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
     auto ysign = [&](int i) { return (yneg && (i == 3 || i == 5)) ? T(-1) : T(1); };
     const T ys0 = ysign(i0), ys1 = ysign(i1), ys2 = ysign(i2);
     const bool zo0 = i0 == 4 || i0 == 5, zo1 = i1 == 4 || i1 == 5, zo2 = i2 == 4 || i2 == 5;
-    const unsigned o0 = i0 * qs + kyo * KB, o1 = i1 * qs + kyo * KB, o2 = i2 * qs + kyo * KB;
+    constexpr unsigned SZ = sizeof(T);
+    const unsigned kxs = (unsigned)(kxc & (KB - 1));
+    const unsigned o0 = (i0 * qs + kyo * KB + kxs) * SZ, o1 = (i1 * qs + kyo * KB + kxs) * SZ,
+                   o2 = (i2 * qs + kyo * KB + kxs) * SZ;
     T nrow[8][3];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int kz = t + q * TPL;
         const bool zneg = kz > MZ / 2;
-        const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy * KB;
-        nrow[q][0] = tplane[o0 + kzo] * ((zneg && zo0) ? -ys0 : ys0);
-        nrow[q][1] = tplane[o1 + kzo] * ((zneg && zo1) ? -ys1 : ys1);
-        nrow[q][2] = tplane[o2 + kzo] * ((zneg && zo2) ? -ys2 : ys2);
+        const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy * (KB * SZ);
+        nrow[q][0] = ld_at(tplane, o0 + kzo) * ((zneg && zo0) ? -ys0 : ys0);
+        nrow[q][1] = ld_at(tplane, o1 + kzo) * ((zneg && zo1) ? -ys1 : ys1);
+        nrow[q][2] = ld_at(tplane, o2 + kzo) * ((zneg && zo2) ? -ys2 : ys2);
     }
     TwReg<T, MZ> tr;
     twiddle_load(tr, tw, t);
@@ -393,14 +399,14 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
         for (int q = 0; q < 8; ++q) {
             const int z = t + q * TPL;
             const bool out = HALF ? q < 4 : z < nz;
-            if (act && out) st_nt(&plane[col + (unsigned)z * myb], v[q]);
+            if (act && out) st_nt(at(plane, (col + (unsigned)z * myb) * CSZ), v[q]);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int z = t + q * TPL;
             const bool out = HALF ? q < 4 : z < nz;
-            if (act && out) plane[col + (unsigned)z * myb] = v[q];
+            if (act && out) *at(plane, (col + (unsigned)z * myb) * CSZ) = v[q];
         }
     }
 }

@@ -279,11 +279,24 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     const bool need_old = (MODE == UPD_STEP && a.stage == 1) || (MODE == UPD_STEP_MS && a.stage == 3);
     const T *Pin0 = reinterpret_cast<const T *>(a.P_in) + 3 * b * comp;
     const T *Pold0 = a.P_old ? reinterpret_cast<const T *>(a.P_old) + 3 * b * comp : nullptr;
-    const T *Pc[3] = {Pin0, Pin0 + comp, Pin0 + 2 * comp};
+    // uniform bases of the components in this layer and in the neighbour
+    // layers (a missing neighbour layer: this one); a cell is its byte
+    // offset within the layer (a layer holds at most 1024 x 1024 cells)
+    const int zoff = z * plane;
+    const int zmoff = zm >= 0 ? zm * plane : zoff;
+    const int zpoff = zp >= 0 ? zp * plane : zoff;
+    const T *Pz[3], *Pzm[3], *Pzp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Pz[c] = Pin0 + c * comp + zoff;
+        Pzm[c] = Pin0 + c * comp + zmoff;
+        Pzp[c] = Pin0 + c * comp + zpoff;
+    }
+    constexpr unsigned SZ = sizeof(T);
     const unsigned nx_div = 0xffffffffu / (unsigned)nx + 1u;   // e / nx for e < 2^16
     T cp[CPT][3], cn[CPT][6][3], co[CPT][3];
     bool cok[CPT];
-    int cyy[CPT], cx[CPT], coff[CPT];
+    int cyy[CPT], cx[CPT], cip[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
         const unsigned e = tid + i * nthr;
@@ -293,26 +306,31 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         const int yc = cok[i] ? y : y0, xc = cok[i] ? x : 0;   // a valid cell for the tail
         cyy[i] = yy;
         cx[i] = x;
-        const int off = z * plane + yc * nx + xc;
-        coff[i] = off;
+        const int ip = yc * nx + xc;                             // within the layer
+        cip[i] = ip;
+        const unsigned cb = (unsigned)ip * SZ;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) cp[i][c] = Pc[c][off];
+        for (int c = 0; c < 3; ++c) cp[i][c] = ld_at(Pz[c], cb);
         if (need_nb) {
-            const int xm = xc > 0 ? off - 1 : (g.px ? off + nx - 1 : off);
-            const int xp = xc < nx - 1 ? off + 1 : (g.px ? off - nx + 1 : off);
-            const int ym = yc > 0 ? off - nx : (g.py ? off + plane - nx : off);
-            const int yp = yc < ny - 1 ? off + nx : (g.py ? off - plane + nx : off);
-            const int zmo = zm >= 0 ? off + (zm - z) * plane : off;
-            const int zpo = zp >= 0 ? off + (zp - z) * plane : off;
-            const int nb[6] = {xm, xp, ym, yp, zmo, zpo};
+            const int xm = xc > 0 ? ip - 1 : (g.px ? ip + nx - 1 : ip);
+            const int xp = xc < nx - 1 ? ip + 1 : (g.px ? ip - nx + 1 : ip);
+            const int ym = yc > 0 ? ip - nx : (g.py ? ip + plane - nx : ip);
+            const int yp = yc < ny - 1 ? ip + nx : (g.py ? ip - plane + nx : ip);
+            const unsigned nb[4] = {(unsigned)xm * SZ, (unsigned)xp * SZ, (unsigned)ym * SZ,
+                                    (unsigned)yp * SZ};
 #pragma unroll
-            for (int d = 0; d < 6; ++d)
+            for (int d = 0; d < 4; ++d)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) cn[i][d][c] = Pc[c][nb[d]];
+                for (int c = 0; c < 3; ++c) cn[i][d][c] = ld_at(Pz[c], nb[d]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cn[i][4][c] = ld_at(Pzm[c], cb);
+                cn[i][5][c] = ld_at(Pzp[c], cb);
+            }
         }
         if (need_old) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) co[i][c] = Pold0[c * comp + off];
+            for (int c = 0; c < 3; ++c) co[i][c] = ld_at(Pold0 + c * comp + zoff, cb);
         }
     }
 
@@ -341,7 +359,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         T *E = Eloc[i];
         E[0] = E[1] = E[2] = T(0);
         if (!cok[i]) continue;
-        const int off = coff[i];
+        const unsigned cb = (unsigned)cip[i] * SZ;
         const T *p = cp[i];
         T sq[3];
 #pragma unroll
@@ -380,9 +398,9 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
                           kp->gm * (D[0][1] * D[1][0] + D[1][2] * D[2][1] + D[2][0] * D[0][2]);
                 }
                 if (a.cross) {                               // their field, from k_cross
-                    const T *hx = reinterpret_cast<const T *>(a.cross) + 3LL * b * comp + off;
+                    const T *hx = reinterpret_cast<const T *>(a.cross) + 3LL * b * comp + zoff;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) E[c] += hx[c * comp];
+                    for (int c = 0; c < 3; ++c) E[c] += ld_at(hx + c * comp, cb);
                 }
             }
         }
@@ -414,8 +432,10 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     for (int i = 0; i < CPT; ++i) {
         if (!cok[i]) continue;
         const int yy = cyy[i], x = cx[i];
-        const int off = coff[i];
+        const int off = zoff + cip[i];           // the multistep and RK buffers
+        const unsigned cb = (unsigned)cip[i] * SZ;
         const T *p = cp[i];
+        (void)off;
         T *E = Eloc[i];
         T hel[3] = {T(0), T(0), T(0)};
         if (a.elec_in) {
@@ -499,8 +519,8 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (store) {
-                    if constexpr (NT) st_nt(&Pout[c * comp + off], o[c]);
-                    else Pout[c * comp + off] = o[c];
+                    if constexpr (NT) st_nt(at(Pout + c * comp + zoff, cb), o[c]);
+                    else *at(Pout + c * comp + zoff, cb) = o[c];
                 }
                 bad = bad || !isfinite(o[c]);
                 if (do_fx) hs[((c << ysh) + yy) * HS + x] = o[c];
@@ -509,7 +529,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
         } else if constexpr (MODE == UPD_FIELD) {
             const T sc = kp->out_scale;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Pout[c * comp + off] = material ? sc * E[c] : T(0);
+            for (int c = 0; c < 3; ++c) *at(Pout + c * comp + zoff, cb) = material ? sc * E[c] : T(0);
         } else {
             if (material && a.elec_in)
                 acc[2] += -0.5 * ((double)p[0] * hel[0] + (double)p[1] * hel[1] +
