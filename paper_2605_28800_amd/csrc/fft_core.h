@@ -23,10 +23,35 @@
 
 namespace tdgl {
 
+// Aligned to its own size, so that a complex value moves as one 8-byte
+// (FP32) or 16-byte (FP64) access; in LDS those take 16-bit byte offsets
+// where pairs of separate accesses take 8-bit element offsets, which the
+// strides of the transforms overflow.
 template <typename T>
-struct cpx {
+struct alignas(2 * sizeof(T)) cpx {
     T x, y;
 };
+
+// A complex value in LDS at the alignment of one component: it moves as two
+// separate accesses.  The transforms take either element type for their
+// LDS lines (measured per kernel: the long z transforms keep lower register
+// counts with this one).
+template <typename T>
+struct cpx1 {
+    T x, y;
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> lds_get(const cpx<T> *p) { return *p; }
+template <typename T>
+__device__ __forceinline__ cpx<T> lds_get(const cpx1<T> *p) { return {p->x, p->y}; }
+template <typename T>
+__device__ __forceinline__ void lds_put(cpx<T> *p, cpx<T> v) { *p = v; }
+template <typename T>
+__device__ __forceinline__ void lds_put(cpx1<T> *p, cpx<T> v)
+{
+    p->x = v.x;
+    p->y = v.y;
+}
 
 // Non-temporal stores, for the spectra and states that a step kernel writes
 // for the next kernel when the context asks for them (Geom::nt, uniform; the
@@ -273,8 +298,8 @@ __device__ __forceinline__ void line_sync()
 
 // Stages s >= 1.  Every thread of the work-group (WAVE: of the wave) must
 // reach these barriers; threads with act == false only skip memory traffic.
-template <typename T, int M, int S, bool INV, class Idx, bool WAVE = false>
-__device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds, Idx idx, int t,
+template <typename T, int M, int S, bool INV, class Idx, bool WAVE = false, class LT>
+__device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], LT *lds, Idx idx, int t,
                                            const TwReg<T, M> &tr, bool act)
 {
     using St = Stage<M, S>;
@@ -293,13 +318,14 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b * R + r] = lds[f0 + idx.shift(b * TPL + r * MR)];
+                for (int r = 0; r < R; ++r)
+                    v[b * R + r] = lds_get(&lds[f0 + idx.shift(b * TPL + r * MR)]);
         } else {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int i = t + b * TPL;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b * R + r] = lds[idx(i + r * MR)];
+                for (int r = 0; r < R; ++r) v[b * R + r] = lds_get(&lds[idx(i + r * MR)]);
             }
         }
 #pragma unroll
@@ -333,10 +359,10 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
                 if constexpr (FAST_WRITE) {
                     const int fj = idx(j);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) lds[fj + idx.shift(r * P)] = v[b * R + r];
+                    for (int r = 0; r < R; ++r) lds_put(&lds[fj + idx.shift(r * P)], v[b * R + r]);
                 } else {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) lds[idx(j + r * P)] = v[b * R + r];
+                    for (int r = 0; r < R; ++r) lds_put(&lds[idx(j + r * P)], v[b * R + r]);
                 }
             }
         }
@@ -350,8 +376,8 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *ld
 // (barrier) before calling, and must barrier again before reusing it
 // afterwards.  tr: this thread's twiddles (twiddle_load with the forward
 // table; the inverse conjugates them).
-template <typename T, int M, bool INV, class Idx, bool WAVE = false>
-__device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds, Idx idx, int t,
+template <typename T, int M, bool INV, class Idx, bool WAVE = false, class LT>
+__device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], LT *lds, Idx idx, int t,
                                          const TwReg<T, M> &tr, bool act)
 {
     static_assert(M >= 8 && M <= 1024 &&
@@ -366,7 +392,7 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds,
             if (act) {
                 const int f8 = idx(R0 * t);
 #pragma unroll
-                for (int r = 0; r < R0; ++r) lds[f8 + idx.near(r)] = v[r];
+                for (int r = 0; r < R0; ++r) lds_put(&lds[f8 + idx.near(r)], v[r]);
             }
         }
     } else {
@@ -380,7 +406,7 @@ __device__ __forceinline__ void fft_line(cpx<T> (&v)[Plan<M>::PPT], cpx<T> *lds,
                 for (int r = 0; r < R0; ++r) u[r] = v[b + NB0 * r];
                 dftR<T, R0, INV>(u);
 #pragma unroll
-                for (int r = 0; r < R0; ++r) lds[idx((t + b * TPL) * R0 + r)] = u[r];
+                for (int r = 0; r < R0; ++r) lds_put(&lds[idx((t + b * TPL) * R0 + r)], u[r]);
             }
         }
     }

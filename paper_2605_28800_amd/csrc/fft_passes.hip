@@ -42,7 +42,7 @@ __global__ void k_fx(const T *__restrict__ in, long long nrows, int n_in, long l
     constexpr int M2 = M / 2;
     constexpr int PPT = HalfLine<M2>::PPT, TPL = HalfLine<M2>::TPL;
     constexpr int LEN = LinePad<M2>::len;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *stg = lds + lpw * LEN;                  // [M2 + 1][lpw] output staging
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -114,7 +114,7 @@ __global__ void k_row(const cpx<T> *in, cpx<T> *out, long long nlines, long long
 {
     constexpr int PPT = Plan<M>::PPT, TPL = Plan<M>::TPL;
     constexpr int LEN = LinePad<M>::len;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
@@ -154,7 +154,7 @@ __global__ void k_rowb(const cpx<T> *in, cpx<T> *out, int hx, unsigned R, unsign
 {
     constexpr int PPT = Plan<M>::PPT, TPL = Plan<M>::TPL;
     constexpr int LEN = LinePad<M>::len;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     const int tid = threadIdx.x;
     const int sub = tid & (KB - 1), tq = tid >> KBS;
@@ -208,7 +208,7 @@ __global__ void k_col(const cpx<T> *in, cpx<T> *out, long long C, long long ncol
                       int n_out, const cpx<T> *__restrict__ tw)
 {
     constexpr int TPL = M / 8;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
     const int tid = threadIdx.x;
     const int cc = tid % CT, t = tid / CT;
@@ -289,6 +289,18 @@ struct ZmulCfg {
     }
     static constexpr int CT = fit(RB / (int)sizeof(cpx<T>));    // rows of RB bytes
     static constexpr int NTHR = 3 * CT * TPL;
+    // Register allocation, measured on the 128x128x32 film (64-point z
+    // transforms), its FP64 version, the 256x256x64 bilayer (128 points) and
+    // the batched boxes.  Up to 64 points: the tensor row is loaded after the
+    // forward transform and FP32 groups leave room for 6 waves per SIMD
+    // (<= 80 VGPRs); from 128 points on, the tensor loads overlap the
+    // forward transform and the LDS lines take component-aligned values
+    // (paired 4-byte accesses), which keeps the 768-thread groups at two per
+    // CU (with 8-byte accesses the allocation grows past 80 VGPRs and the
+    // bilayer's z pass slows from 172 to 250 us).
+    static constexpr bool LATE = MZ <= 64;
+    static constexpr int WEU = (sizeof(T) == 4 && MZ <= 64) ? 6 : 1;
+    using LT = typename std::conditional<(MZ >= 128), cpx1<T>, cpx<T>>::type;
 };
 
 // HALF: nz == MZ/2 (an open dimension padded to twice its length): the upper
@@ -297,15 +309,21 @@ struct ZmulCfg {
 // their arithmetic drops out.
 template <typename T, int MZ, int RB, bool HALF>
 __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
+    __attribute__((amdgpu_waves_per_eu(ZmulCfg<T, MZ, RB>::WEU)))
     k_zmul(cpx<T> *S, const T *__restrict__ Nt, int nz, int my, int hx, int nb,
            const cpx<T> *__restrict__ tw, const int *__restrict__ frozen, unsigned mgx,
            unsigned mnb, int nt)
 {
     using C = ZmulCfg<T, MZ, RB>;
+    using LT = typename C::LT;
     constexpr int TPL = C::TPL, CT = C::CT;
     constexpr int LZ = LinePad<MZ>::len;
+    // From 128 points on the base is offset by a value the compiler cannot
+    // prove zero (it is: grids hold fewer than 2^31 groups), so that it keeps
+    // the element type's 4-byte alignment instead of merging the pairs into
+    // 8-byte accesses (whose schedule needs 90 registers here).
     extern __shared__ unsigned char smem_raw[];
-    cpx<T> *lds = reinterpret_cast<cpx<T> *>(smem_raw);
+    LT *lds = reinterpret_cast<LT *>(smem_raw + (MZ >= 128 ? (blockIdx.x >> 31) * 4u : 0u));
     const int tid = threadIdx.x;
     const int cc = tid % CT;
     const int t = (tid / CT) % TPL;
@@ -353,22 +371,26 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
     const unsigned o0 = (i0 * qs + kyo * KB + kxs) * SZ, o1 = (i1 * qs + kyo * KB + kxs) * SZ,
                    o2 = (i2 * qs + kyo * KB + kxs) * SZ;
     T nrow[8][3];
+    auto load_tensor = [&]() {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int kz = t + q * TPL;
-        const bool zneg = kz > MZ / 2;
-        const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy * (KB * SZ);
-        nrow[q][0] = ld_at(tplane, o0 + kzo) * ((zneg && zo0) ? -ys0 : ys0);
-        nrow[q][1] = ld_at(tplane, o1 + kzo) * ((zneg && zo1) ? -ys1 : ys1);
-        nrow[q][2] = ld_at(tplane, o2 + kzo) * ((zneg && zo2) ? -ys2 : ys2);
-    }
+        for (int q = 0; q < 8; ++q) {
+            const int kz = t + q * TPL;
+            const bool zneg = kz > MZ / 2;
+            const unsigned kzo = (unsigned)(zneg ? MZ - kz : kz) * hy * (KB * SZ);
+            nrow[q][0] = ld_at(tplane, o0 + kzo) * ((zneg && zo0) ? -ys0 : ys0);
+            nrow[q][1] = ld_at(tplane, o1 + kzo) * ((zneg && zo1) ? -ys1 : ys1);
+            nrow[q][2] = ld_at(tplane, o2 + kzo) * ((zneg && zo2) ? -ys2 : ys2);
+        }
+    };
+    if constexpr (!C::LATE) load_tensor();
     TwReg<T, MZ> tr;
     twiddle_load(tr, tw, t);
     const IdxStridePad ip{CT};
-    cpx<T> *L = lds + c * LZ * CT + cc;
+    LT *L = lds + c * LZ * CT + cc;
     // a column's lanes lie within one wave where CT TPL <= 64
     constexpr bool WAVE = CT * TPL <= 64;
     fft_line<T, MZ, false, IdxStridePad, WAVE>(v, L, ip, t, tr, act);
+    if constexpr (C::LATE) load_tensor();
     // element kz = t + q*TPL of a line sits at ip(t) + ip.shift(q*TPL) when
     // TPL is a multiple of 8 (a constant offset per q)
     auto ipq = [&](int q) {
@@ -378,16 +400,16 @@ __global__ void __launch_bounds__((ZmulCfg<T, MZ, RB>::NTHR))
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) L[ipq(q)] = v[q];
+        for (int q = 0; q < 8; ++q) lds_put(&L[ipq(q)], v[q]);
     }
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int o = ipq(q) + cc;
-            const cpx<T> p0 = lds[0 * LZ * CT + o];
-            const cpx<T> p1 = lds[1 * LZ * CT + o];
-            const cpx<T> p2 = lds[2 * LZ * CT + o];
+            const cpx<T> p0 = lds_get(&lds[0 * LZ * CT + o]);
+            const cpx<T> p1 = lds_get(&lds[1 * LZ * CT + o]);
+            const cpx<T> p2 = lds_get(&lds[2 * LZ * CT + o]);
             const T n0 = nrow[q][0], n1 = nrow[q][1], n2 = nrow[q][2];
             v[q] = {n0 * p0.x + n1 * p1.x + n2 * p2.x, n0 * p0.y + n1 * p1.y + n2 * p2.y};
         }
@@ -444,7 +466,7 @@ __global__ void __launch_bounds__((PlaneCfg<T, MY, MZ>::NTHR))
     using C = PlaneCfg<T, MY, MZ>;
     constexpr int TPLY = C::TPLY, TPLZ = C::TPLZ, CK = C::CK, LINE = C::LINE;
     static_assert(C::YROUND >= 1 && C::NTHR <= 1024, "plane configuration");
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T> *pl = reinterpret_cast<cpx<T> *>(smem_raw);        // [3*nz][LINE]
     cpx<T> *zs = pl + 3 * nz * LINE;                            // [3][MZ + MZ/8][CK]
     constexpr int LZ = LinePad<MZ>::len;

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
     constexpr int LEN = LinePad<M2>::len;
     constexpr int CPT = 2;                     // cells per thread, at most
     static_assert(64 % TPL == 0, "a line must not straddle waves");
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int yt = a.yt;                       // a power of two
     const int ysh = __ffs(yt) - 1;
     const int nrows = 3 * yt;
