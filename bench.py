@@ -136,6 +136,30 @@ def copy_calibration(mib=256, reps=3):
     return {"copy_bytes": n * 4, "launches": reps}
 
 
+def stream_copy(mib=1024, reps=20):
+    """Achievable HBM bandwidth of the device: a device-to-device copy of
+    mib MiB (torch's copy kernel, far more than the caches hold), its read
+    plus written bytes over the mean of reps back-to-back copies timed with
+    HIP events on torch's stream."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return {"GBps": round(2 * n * 4 / sec / 1e9, 1), "bytes_per_copy": 2 * n * 4,
+            "copies": reps, "kind": "device-to-device copy (torch), read + written bytes"}
+
+
 KERNEL_KEYS = {        # rocprofv3 kernel-name fragments of the step kernels
     "y_forward": "k_rowb<float, 128, false,",
     "z_tensor": "k_zmul<float, 64,",
@@ -672,6 +696,8 @@ def main():
                for k in names}
     step_bytes = model_bytes_per_cell_step(r32["dims"], 4)
     log("kernels:", json.dumps(kernels))
+    copy_bw = stream_copy()
+    log("stream copy: %.1f GB/s" % copy_bw["GBps"])
 
     fp64 = None
     if args.fp64_steps > 0:
@@ -721,7 +747,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": dom,
-                     "alg_bytes_per_launch": dom_bytes, "mean_launch_ms": dom_ms},
+                     "alg_bytes_per_launch": dom_bytes, "mean_launch_ms": dom_ms,
+                     "frac_of_stream_copy": round(achieved / copy_bw["GBps"], 4)},
         "cpu_baseline": cpu,
         "fp64": fp64,
         "c4_large_grid": c4,
@@ -731,7 +758,10 @@ def main():
         "kernels": kernels,
         "step_roofline": {"bytes_per_cell_step": round(step_bytes, 1),
                           "frac": round(value * step_bytes / (HBM_PEAK_GBS * 1e9), 4),
+                          "frac_of_stream_copy": round(value * step_bytes
+                                                       / (copy_bw["GBps"] * 1e9), 4),
                           "note": "whole step vs an HBM model of a 5-pass design"},
+        "stream_copy": copy_bw,
         "energies_J": list(r32["F"]),
         "windows_ms": [round(w, 4) for w in r32["window_ms"]],
     }
