@@ -138,9 +138,10 @@ def copy_calibration(mib=256, reps=3):
 
 def stream_copy(mib=1024, reps=20):
     """Achievable HBM bandwidth of the device: a device-to-device copy of
-    mib MiB (torch's copy kernel, far more than the caches hold), its read
-    plus written bytes over the mean of reps back-to-back copies timed with
-    HIP events on torch's stream."""
+    mib MiB (far more than the caches hold; torch's copy_ of contiguous
+    tensors is hipMemcpyAsync, the runtime's copy kernel), its read plus
+    written bytes over the mean of reps back-to-back copies timed with HIP
+    events on torch's stream."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.rand(n, device="cuda")
@@ -157,7 +158,7 @@ def stream_copy(mib=1024, reps=20):
     sec = e0.elapsed_time(e1) * 1e-3 / reps
     del src, dst
     return {"GBps": round(2 * n * 4 / sec / 1e9, 1), "bytes_per_copy": 2 * n * 4,
-            "copies": reps, "kind": "device-to-device copy (torch), read + written bytes"}
+            "copies": reps, "kind": "device-to-device hipMemcpyAsync, read + written bytes"}
 
 
 KERNEL_KEYS = {        # rocprofv3 kernel-name fragments of the step kernels
