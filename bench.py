@@ -122,7 +122,8 @@ def run_gpu(cfg, precision, steps, warmup, profile_steps, fft_path=0, rows=0, ch
 
 
 def copy_calibration(mib=256, reps=3):
-    """A plain device copy of known size (torch's copy kernel), for scaling
+    """A plain device copy of known size (hipMemcpyAsync through torch's
+    copy_, the runtime's copy kernel), for scaling
     the FETCH_SIZE / WRITE_SIZE counters: each launch reads and writes
     mib MiB, far more than the L2 holds."""
     import torch
