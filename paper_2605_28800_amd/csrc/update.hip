@@ -166,9 +166,10 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
             return;
         }
     }
-    // LDS: rows hs[(c*yt + yy)*HS + x] (HS = nx + 2, even, so that (even,
-    // odd) sample pairs are 8-byte aligned), then the FFT scratch per line.
-    const int HS = nx + 2;
+    // LDS: rows hs[(c*yt + yy)*HS + x] (HS = nx + 2 rounded down to even, so
+    // that (even, odd) sample pairs are aligned as one complex value), then
+    // the FFT scratch per line.
+    const int HS = (nx + 2) & ~1;
     const size_t hbytes = ((size_t)nrows * HS * sizeof(T) + 15) / 16 * 16;
     T *hs = reinterpret_cast<T *>(smem_raw);
     cpx<T> *scr = reinterpret_cast<cpx<T> *>(smem_raw + hbytes);
@@ -617,11 +618,12 @@ __global__ void __launch_bounds__(UpdMaxThreads<T>::v)
 }
 
 // LDS bytes of the update kernel for rows-per-group yt: the rows
-// [3 yt][nx + 2] and the half-length FFT scratch [3 yt][M/2 + M/16].
+// [3 yt][HS] (HS = nx + 2 rounded down to even) and the half-length FFT
+// scratch [3 yt][M/2 + M/16].
 template <typename T, int M>
 static size_t update_lds(const Geom &g, int yt)
 {
-    const size_t a = ((size_t)3 * yt * (g.nx + 2) * sizeof(T) + 15) / 16 * 16;
+    const size_t a = ((size_t)3 * yt * ((g.nx + 2) & ~1) * sizeof(T) + 15) / 16 * 16;
     const size_t b = (size_t)3 * yt * LinePad<M / 2>::len * sizeof(cpx<T>);
     size_t tot = a + b;
     if (tot < 16 * 8 * sizeof(double)) tot = 16 * 8 * sizeof(double);
