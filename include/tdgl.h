@@ -63,8 +63,10 @@ enum { TDGL_LANDAU = 1, TDGL_GRAD = 2, TDGL_ELEC = 4, TDGL_EXT = 8, TDGL_ALL = 1
  * (fully periodic).  Open dimensions are zero-padded to the smallest power
  * of two >= max(8, 2n-1), or in x and y to 3 * 2^a (>= 24) where that is
  * smaller (96 cells: 192); a periodic dimension needs n a power of two in
- * [8, 1024].  Padded lengths must not exceed 1024.  tdgl_get_dims reports
- * the padded lengths. */
+ * [8, 1024].  Padded lengths must not exceed 1024, and an FP64 context
+ * takes rows of at most 512 cells (nx <= 512; the time-step kernel's
+ * smallest tile must fit 512 threads); tdgl_create returns
+ * TDGL_E_UNSUPPORTED otherwise.  tdgl_get_dims reports the padded lengths. */
 typedef struct {
     int nx, ny, nz;
     double dx, dy, dz;            /* cell edge lengths, m                      */

@@ -682,6 +682,35 @@ hipError_t launch_row(int prec, int M, bool inv, const void *in, void *out, long
     }
 }
 
+// The x pass's LDS (fx_impl's shm) exceeds 64 KiB for FP64 lines of 1024
+// points: raise the limit of both forms.
+template <typename T, int M>
+static hipError_t fx_prepare()
+{
+    constexpr int M2 = M / 2;
+    constexpr int TPL = HalfLine<M2>::TPL;
+    constexpr int lpw = TPL >= 256 ? 1 : 256 / TPL;
+    constexpr size_t shm = ((size_t)lpw * LinePad<M2>::len + (size_t)(M2 + 1) * lpw) *
+                           sizeof(cpx<T>);
+    if (shm <= 65536) return hipSuccess;
+    const void *f[2] = {(const void *)k_fx<T, M, false>, (const void *)k_fx<T, M, true>};
+    for (const void *k : f) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t prepare_fx(int prec, int M)
+{
+    if (prec == PREC_F32) {
+        TDGL_LEN_SWITCH_XY(M, return (fx_prepare<float, LEN_>()))
+    } else {
+        TDGL_LEN_SWITCH_XY(M, return (fx_prepare<double, LEN_>()))
+    }
+}
+
 template <typename T, int M>
 static hipError_t rowb_prepare()
 {

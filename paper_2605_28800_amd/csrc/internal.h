@@ -140,6 +140,10 @@ int zmul_auto_tile(int prec, const Geom &g);
 hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a,
                          const void *tw, hipStream_t s, int *nblocks_out);
 int update_rows_per_block(int prec, const Geom &g);
+// Raise the LDS limits of the update kernels and of the x pass above 64 KiB
+// where their smallest tiles need it (FP64 at 1024 points); once per device
+hipError_t prepare_update(int prec, const Geom &g);
+hipError_t prepare_fx(int prec, int M);
 hipError_t launch_reduce_partials(const double *partials, int n, int nb, double *out,
                                   hipStream_t s);
 // final energies [nb][8] (J and C/m^2, as tdgl_energies_batch) from the partials

@@ -304,6 +304,11 @@ tdgl_status ensure_device(tdgl_ctx *c)
     choose_path(c);
     if (prepare_row_blocked(c->prec, c->g.my) != hipSuccess)
         return fail(c, TDGL_E_HIP, "cannot raise the LDS limit of the y pass");
+    // the x pass in the context's precision and in FP64 (the tensor build)
+    if (prepare_fx(c->prec, c->g.mx) != hipSuccess || prepare_fx(PREC_F64, c->g.mx) != hipSuccess)
+        return fail(c, TDGL_E_HIP, "cannot raise the LDS limit of the x pass");
+    if (prepare_update(c->prec, c->g) != hipSuccess)
+        return fail(c, TDGL_E_HIP, "cannot raise the LDS limit of the update kernel");
     return TDGL_OK;
 }
 
@@ -787,6 +792,9 @@ tdgl_status tdgl_create_batch(const tdgl_grid *grid, int nbatch, int precision, 
         if (n[k] < 1 || n[k] > 4096) return TDGL_E_ARG;
     }
     if ((long long)n[0] * n[1] * n[2] >= (1LL << 31)) return TDGL_E_UNSUPPORTED;
+    // the update kernel's smallest tile (two rows, two cells per thread) fits
+    // the 512 threads of an FP64 group for rows of at most 512 cells
+    if (precision == TDGL_FP64 && n[0] > 512) return TDGL_E_UNSUPPORTED;
     if ((long long)n[2] * nbatch > 65535) return TDGL_E_UNSUPPORTED;     // launch grid rows
     for (int k = 0; k < 3; ++k) {
         if (!(d[k] > 0.0) || !std::isfinite(d[k])) return TDGL_E_ARG;

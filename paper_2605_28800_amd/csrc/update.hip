@@ -630,6 +630,18 @@ static size_t update_lds(const Geom &g, int yt)
     return tot;
 }
 
+// LDS one work-group may use on gfx950 (160 KiB per CU).  Tiles are kept at
+// 64 KiB or less where the smallest (two rows) allows; FP64 rows of 512
+// cells padded to 1024 points need 80 KiB, and update_prepare raises the
+// kernels' limit for them.
+constexpr size_t UPD_LDS_MAX = 160 * 1024;
+
+template <typename T, int M>
+static size_t update_lds_cap(const Geom &g)
+{
+    return update_lds<T, M>(g, 2) > 65536 ? UPD_LDS_MAX : 65536;
+}
+
 // tpl: threads per line of the half-length transform
 static int update_threads(const Geom &g, int yt, int tpl)
 {
@@ -653,7 +665,7 @@ static int rows_for(const Geom &g)
     const int ymax = M >= 512 ? 2 : (sizeof(T) == 4 ? 8 : 4);
     for (int yt = 2; yt <= ymax && yt <= (ny_even > 2 ? ny_even : 2); yt *= 2) {
         if (update_threads(g, yt, HalfLine<M / 2>::TPL) > maxthr) break;
-        if (update_lds<T, M>(g, yt) > 65536) break;
+        if (yt > 2 && update_lds<T, M>(g, yt) > 65536) break;
         best = yt;
     }
     return best;
@@ -693,7 +705,8 @@ static hipError_t update_impl(const Geom &g, const UpdArgs &a, const void *tw, h
 {
     const int nthr = update_threads(g, a.yt, HalfLine<M / 2>::TPL);
     const size_t shm = update_lds<T, M>(g, a.yt);
-    if (shm > 65536 || nthr > UpdMaxThreads<T>::v) return hipErrorInvalidConfiguration;
+    if (shm > update_lds_cap<T, M>(g) || nthr > UpdMaxThreads<T>::v)
+        return hipErrorInvalidConfiguration;
     if ((long long)g.nz * g.nb > 65535) return hipErrorInvalidValue;
     dim3 grid((g.ny + a.yt - 1) / a.yt, g.nz * g.nb);
     if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
@@ -749,6 +762,43 @@ hipError_t launch_update(int prec, int mode, const Geom &g, const UpdArgs &a, co
         TDGL_UPD_LEN(float)
     } else {
         TDGL_UPD_LEN(double)
+    }
+}
+
+// Raise the LDS limit of every update kernel of row length M above 64 KiB
+// when even the two-row tile needs more (update_lds_cap).
+template <typename T, int M>
+static hipError_t update_prepare(const Geom &g)
+{
+    if (update_lds<T, M>(g, 2) <= 65536) return hipSuccess;
+    const void *f[6] = {(const void *)k_update<T, M, UPD_STEP, true>,
+                        (const void *)k_update<T, M, UPD_STEP, false>,
+                        (const void *)k_update<T, M, UPD_FIELD, false>,
+                        (const void *)k_update<T, M, UPD_ENERGY, false>,
+                        (const void *)k_update<T, M, UPD_STEP_MS, false>,
+                        (const void *)k_update<T, M, UPD_STEP_RK, false>};
+    for (const void *k : f) {
+        const hipError_t e =
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)UPD_LDS_MAX);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+#define TDGL_PREP_LEN(T)                                   \
+    switch (g.mx) {                                        \
+    case 512: return update_prepare<T, 512>(g);            \
+    case 768: return update_prepare<T, 768>(g);            \
+    case 1024: return update_prepare<T, 1024>(g);          \
+    default: return hipSuccess;                            \
+    }
+
+hipError_t prepare_update(int prec, const Geom &g)
+{
+    if (prec == PREC_F32) {
+        TDGL_PREP_LEN(float)
+    } else {
+        TDGL_PREP_LEN(double)
     }
 }
 

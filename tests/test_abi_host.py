@@ -60,6 +60,21 @@ def test_create_rejects(n, d, pm, status):
     assert e.value.status == status
 
 
+def test_fp64_rows_of_at_most_512_cells():
+    # FP64: the time-step kernel's two-row tile of 1024-cell rows needs more
+    # than its 512 threads; FP32 takes them, and FP64 takes 512-cell rows
+    # (padded to 1024 points)
+    with pytest.raises(T.TdglError) as e:
+        T.tdgl_create(_grid((1024, 8, 8), pm=3), T.TDGL_FP64)
+    assert e.value.status == T.TDGL_E_UNSUPPORTED
+    for n, pm, prec in (((1024, 8, 8), 3, T.TDGL_FP32), ((512, 4, 2), 0, T.TDGL_FP64)):
+        ctx = T.tdgl_create(_grid(n, pm=pm), prec)
+        try:
+            assert T.tdgl_get_dims(ctx)[3] == 1024
+        finally:
+            T.tdgl_destroy(ctx)
+
+
 @pytest.mark.parametrize("n,pm,dims", [
     ((16, 16, 8), 0, (32, 32, 16)),
     ((12, 10, 5), 0, (24, 24, 16)),          # x, y: 3 * 2^a lengths; z: powers of two

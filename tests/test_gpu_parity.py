@@ -42,6 +42,11 @@ CASES = {
     # batched workload's 96x96x8 boxes), 96 and 48 in x and y
     "open_96x96x8": dict(n=(96, 96, 8), periodic=(0, 0, 0)),
     "open_48x24x4": dict(n=(48, 24, 4), periodic=(0, 0, 0)),
+    # the largest transforms, 1024 points, in x (FP64: the x pass and the
+    # two-row update tile need more than 64 KiB of LDS), in y and in z
+    "open_max_x_512x4x2": dict(n=(512, 4, 2), periodic=(0, 0, 0)),
+    "open_max_y_4x512x2": dict(n=(4, 512, 2), periodic=(0, 0, 0)),
+    "open_max_z_4x4x512": dict(n=(4, 4, 512), periodic=(0, 0, 0)),
 }
 
 
@@ -65,6 +70,47 @@ def test_field_parity(case, prec, path):
             assert err <= tol, (case, prec, mask, err)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_field_parity_periodic_rows_of_1024_cells_fp32(path):
+    """Periodic rows of 1024 cells (FP32 only: an FP64 context takes rows of
+    at most 512 cells, which the host tests check)."""
+    cfg = _cfg(n=(1024, 8, 2), periodic=(1, 1, 0))
+    announce("field parity film 1024x8x2 f32 path %d" % path)
+    P = I.initial_P(cfg, 3, np.float32)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f32", path=path)
+    try:
+        ctx.set_P(P)
+        for mask in MASKS:
+            got = ctx.eval_field(mask).cpu().numpy()
+            ref = oracle_field(P.astype(np.float64), prob, mask)
+            err = rel_inf(got, ref)
+            assert err <= 2e-6, (mask, err)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("case", ["open_max_x_512x4x2", "open_max_z_4x4x512"])
+def test_heun_trajectory_at_1024_point_transforms_fp64(case):
+    """Heun steps at the largest transforms, FP64 (the update kernel's
+    stepping forms with the raised LDS limit in x): 20 steps against the
+    oracle's own, all terms."""
+    cfg = _cfg(**CASES[case])
+    cfg["scheme"] = "heun"
+    announce("heun trajectory fp64 %s" % case)
+    P0 = I.initial_P(cfg, 5)
+    prob = O.Problem(cfg)
+    ctx = gpu_context(cfg, "f64", path=1)
+    try:
+        ctx.set_P(P0)
+        ctx.step(20)
+        got = ctx.get_P()
+    finally:
+        ctx.close()
+    ref = O.run(P0, prob, "heun", cfg["dtau"], 20)
+    assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-12
 
 
 @pytest.mark.parametrize("case", ["open_16x16x8", "open_ragged_12x10x5", "film_16x16x4",
