@@ -60,6 +60,17 @@ def test_create_rejects(n, d, pm, status):
     assert e.value.status == status
 
 
+def test_sweep_without_field_values_is_refused():
+    # an empty sweep is an argument error, found before any device work
+    ctx = T.tdgl_create(_grid(), T.TDGL_FP32)
+    try:
+        with pytest.raises(T.TdglError) as e:
+            T.tdgl_sweep_eext(ctx, np.zeros((0, 3)), 10)
+        assert e.value.status == T.TDGL_E_ARG
+    finally:
+        T.tdgl_destroy(ctx)
+
+
 def test_fp64_rows_of_at_most_512_cells():
     # FP64: the time-step kernel's two-row tile of 1024-cell rows needs more
     # than its 512 threads; FP32 takes them, and FP64 takes 512-cell rows

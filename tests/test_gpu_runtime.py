@@ -299,6 +299,29 @@ def test_integrator_buffers_live_in_the_bound_workspace():
     assert np.abs(got - ref).max() / ps_of(cfg) <= 1e-12
 
 
+def test_zero_steps_leave_the_state_unchanged():
+    """Empty work: step(0) right after set_P and after a run, and a sweep whose
+    field values are held for 0 steps, leave P bit for bit as it was; the
+    sweep's two records of the same state agree exactly."""
+    cfg = I.config("c2_small")
+    announce("zero steps c2_small")
+    P0 = I.initial_P(cfg, 1, np.float32)
+    ctx = gpu_context(cfg, "f32")
+    try:
+        ctx.set_P(P0)
+        ctx.step(0)
+        assert np.array_equal(ctx.get_P(T.TDGL_FP32), P0)
+        ctx.step(7)
+        P7 = ctx.get_P(T.TDGL_FP32)
+        ctx.step(0)
+        m, F = T.tdgl_sweep_eext(ctx.ctx, np.zeros((2, 3)), 0)
+        assert np.array_equal(ctx.get_P(T.TDGL_FP32), P7)
+        assert np.array_equal(m[0], m[1]) and np.array_equal(F[0], F[1])
+        assert np.isfinite(F).all() and np.abs(m).max() > 0
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_tuning_knobs_do_not_change_results(prec):
     """The z-pass tile and the store mode are launch choices only: every
