@@ -3,7 +3,8 @@
 * eq 10 (section 4.1): the relaxed 1-D 180-degree wall of the 2-4 model with
   the paper's parameters converges to the tanh profile at second order in h.
 * the sixth-order BaTiO3 wall (closed form derived from the first integral
-  G P'^2/2 = f(P) - f(Ps)) converges the same way.
+  G P'^2/2 = f(P) - f(Ps) of the 1-D stationary equation) converges the
+  same way.
 * an exact discrete eigenmode of the linear problem decays by exactly the
   Euler / Heun amplification factor (pins the Laplacian with periodic and
   open boundaries, and both integrators).
