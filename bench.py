@@ -713,6 +713,9 @@ def main():
         log("fp64: %.4f ms/step, %.3e cell-steps/s" % (fp64["ms_per_step"], v64))
 
     c4 = run_c4(args) if args.c4_steps > 0 else None
+    if c4 is not None and c4.get("roofline_frac_step") is not None:
+        c4["roofline_frac_step_of_stream_copy"] = round(
+            c4["roofline_frac_step"] * HBM_PEAK_GBS / copy_bw["GBps"], 4)
 
     loop = run_c4_loop(args) if args.c4_loop_values > 0 else None
 
